@@ -1,0 +1,154 @@
+/*
+ * lumiq.h -- C ABI of the MI355X luminaire emission-query library.
+ *
+ * The library answers the render-time query of a learned radiance-field
+ * luminaire (Condor & Jarabo, "A Learned Radiance-Field Representation for
+ * Complex Luminaires", EGSR 2022): for rays leaving a shading point toward
+ * the luminaire's proxy box it returns the emitted radiance L_e (Sec. 4.1,
+ * Eq. 3) and the opacity alpha (Sec. 4.1, Eq. 5) by marching the distilled
+ * plenoctree (Sec. 5).  It also trains and runs a small Fourier-feature MLP
+ * that stands in for the octree march, with the octree as its fallback.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: every call returns lq_status; on failure lq_last_error()
+ *    returns a message for the calling thread (valid until its next call).
+ *    Argument errors are reported synchronously, before any launch.
+ *  - Device pointers: ray and output arrays are *device* pointers on the
+ *    handle's device, owned by the caller, contiguous, 4-byte aligned, and
+ *    must not alias.  Host pointers are rejected with LQ_ERR_INVALID_ARG.
+ *  - Streams: hip_stream is a hipStream_t (NULL = the default stream).  Calls
+ *    are stream-ordered and asynchronous; device faults surface as LQ_ERR_HIP
+ *    on a later call.
+ *  - Rays: origins[n][3] and dirs[n][3] are float32.  dirs points from the
+ *    shading point INTO the luminaire; it need not be unit length.  The
+ *    paper's ray is x - omega t (Sec. 4.1, Eq. 3), so the emission direction
+ *    at which the SH are evaluated is omega = -dirs/|dirs|.
+ *  - Per-ray outcomes that are not errors: n = 0 is a no-op; a ray with a
+ *    non-finite component or a zero direction, or that meets the proxy box
+ *    [-1,1]^3 in no positive length, returns RGB 0 and alpha 0; an origin
+ *    inside the box marches from t = 0.
+ *  - Handles are immutable after creation and safe for concurrent queries
+ *    on different streams.
+ */
+#ifndef LUMIQ_H
+#define LUMIQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LQ_OK = 0,
+    LQ_ERR_INVALID_ARG = -1,  /* bad pointer, size, enum or flag           */
+    LQ_ERR_FORMAT = -2,       /* malformed tree file or descriptor         */
+    LQ_ERR_OOM = -3,          /* device or host allocation failed          */
+    LQ_ERR_HIP = -4,          /* HIP runtime error (incl. no device)       */
+    LQ_ERR_UNSUPPORTED = -5,  /* valid but unsupported combination         */
+    LQ_ERR_STATE = -6,        /* call not valid in the handle's state      */
+    LQ_ERR_IO = -7            /* file could not be read or written         */
+} lq_status;
+
+/* storage precision of density and SH coefficients on the device */
+enum { LQ_F32 = 0, LQ_F16 = 1, LQ_BF16 = 2 };
+/* transmittance model: linear T = max(0, 1 - int sigma) (Sec. 4.1, Eq. 4),
+ * or exponential T = exp(-int sigma) (the model compared in Sec. 6.2, Table 4) */
+enum { LQ_LINEAR = 0, LQ_EXP = 1 };
+/* query flags */
+enum {
+    LQ_NO_EARLY_TERM = 1,   /* march to the far proxy hit (no alpha_max stop)    */
+    LQ_FP64_ACCUM = 2,      /* validation: accumulate T, weights and L in FP64   */
+    LQ_NO_SIGMA_SKIP = 4    /* composite every data leaf (no sigma_min skip)     */
+};
+
+typedef struct lq_octree lq_octree;   /* opaque, library-owned */
+typedef struct lq_mlp lq_mlp;         /* opaque, library-owned */
+
+/*
+ * Plenoctree descriptor (host memory, read during the call only).
+ *   child[n_nodes][8]: > 0 index of an internal node, < 0 -(leaf + 1), 0 empty.
+ *     Node 0 is the root cube [-1,1]^3; octant index = bx | by<<1 | bz<<2 where
+ *     b_a is 1 for the upper half along axis a.  Data leaves sit at max_depth
+ *     (cells of edge 2^(1-max_depth)); the table must be a tree (every node
+ *     reached once, leaves only below nodes of depth max_depth-1).
+ *   sigma[n_leaves], sh[n_leaves][3][(sh_degree+1)^2] float32: density and
+ *     real SH coefficients (orthonormal basis without the Condon-Shortley
+ *     phase, index k = l^2 + l + m) per colour channel; emission is
+ *     Phi_c = l_max * sigmoid(sum_k sh[c][k] Y_k(omega)) (Sec. 4.2, Eq. 6).
+ *   sigma_min, alpha_max: render heuristics (Sec. 6.2: 0.1 and 0.9).
+ */
+typedef struct {
+    int32_t max_depth;        /* 1..10 */
+    int32_t sh_degree;        /* 0..4  */
+    int32_t n_nodes, n_leaves;
+    float l_max, sigma_min, alpha_max;
+    const int32_t *child;
+    const float *sigma;
+    const float *sh;
+} lq_octree_desc;
+
+/*
+ * Create a device octree from a descriptor (or from a file in the format
+ * written by the inputs package: magic "LQOT", version 1, header then child,
+ * sigma and sh arrays, little-endian).  storage selects the device precision
+ * of sigma and SH (FP32 values are rounded to nearest-even).  The tree is
+ * uploaded to `device`, which becomes current for the calling thread.
+ * Errors: LQ_ERR_INVALID_ARG, LQ_ERR_FORMAT (structure check failed),
+ * LQ_ERR_IO, LQ_ERR_OOM, LQ_ERR_HIP.  *out is NULL on failure.
+ */
+lq_status lq_load_octree_desc(const lq_octree_desc *desc, int storage, int device,
+                              lq_octree **out);
+lq_status lq_load_octree(const char *path, int storage, int device, lq_octree **out);
+void lq_free_octree(lq_octree *tree);
+
+/* Device bytes held by the tree's tables, and its shape. */
+lq_status lq_octree_info(const lq_octree *tree, int64_t *device_bytes, int32_t *n_nodes,
+                         int32_t *n_leaves, int32_t *max_depth, int32_t *sh_degree,
+                         int32_t *storage);
+
+/*
+ * The emission query (Sec. 4.1, Eqs. 3-5; Sec. 5; Sec. 6.2 heuristics).
+ * For each ray i: clip to the proxy box, visit in order of t the octree
+ * leaves whose half-open cell the ray crosses in positive length, and for
+ * each data leaf with stored sigma >= sigma_min composite
+ *     w = T_in - T_out  (T by `model`),   L += w * Phi(omega),
+ * stopping after the first composited leaf at which 1 - T >= alpha_max.
+ * Outputs: rgb[n][3] (L_e) and, if alpha != NULL, alpha[n] = 1 - T.
+ * Leaf-segment lengths and every ordering decision of the traversal are
+ * exact (robust predicates on the float32 inputs); compositing is float32
+ * (FP64 with LQ_FP64_ACCUM).
+ */
+lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const float *dirs,
+                            int64_t n, float *rgb, float *alpha, int model, uint32_t flags,
+                            void *hip_stream);
+
+/*
+ * Validation variant of lq_query_radiance: same traversal and compositing,
+ * plus per-ray records of the visited data leaves.  For each ray:
+ *   count[i]     data leaves visited, up to and including the stop leaf;
+ *   hash[i]      FNV-1a style hash: h = 14695981039346656037;
+ *                h = (h ^ id) * 1099511628211 (mod 2^64) for each leaf id in order,
+ *                where id is the Morton code of the leaf cell (x bit b -> bit 3b,
+ *                y -> 3b+1, z -> 3b+2);
+ *   term_idx[i]  index (in that sequence) of the leaf at which alpha_max
+ *                stopped the march, or -1;
+ *   n_comp[i]    leaves composited;
+ *   leaf_ids     optional [n][max_ids]: the first max_ids leaf ids.
+ * rgb/alpha may be NULL.  All arrays are device pointers.
+ */
+lq_status lq_query_trace(const lq_octree *tree, const float *origins, const float *dirs,
+                         int64_t n, float *rgb, float *alpha, int model, uint32_t flags,
+                         uint32_t *count, uint64_t *hash, int32_t *term_idx, uint32_t *n_comp,
+                         uint32_t *leaf_ids, int32_t max_ids, void *hip_stream);
+
+/* Text of the last error on this thread ("" if none). */
+const char *lq_last_error(void);
+/* Library version string. */
+const char *lq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LUMIQ_H */

@@ -25,7 +25,7 @@ from fractions import Fraction as Fr
 
 import numpy as np
 
-FNV_OFFSET = 1469598103934665603
+FNV_OFFSET = 14695981039346656037
 FNV_PRIME = 1099511628211
 MASK64 = (1 << 64) - 1
 

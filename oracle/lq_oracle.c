@@ -173,7 +173,7 @@ static void march(const orc_tree *T, const float *of, const float *df, int model
     memset(res, 0, sizeof(*res));
     res->term_idx = -1;
     res->first_amb_test = -1;
-    res->hash = 1469598103934665603ull;
+    res->hash = 14695981039346656037ull;
     ray_t r;
     r.flags = &res->flags;
     r.D = T->depth;

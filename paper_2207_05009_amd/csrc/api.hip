@@ -1,0 +1,399 @@
+// api.hip -- host side of the C ABI declared in include/lumiq.h: argument
+// checks, plenoctree validation and upload, SH constants, error reporting.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lq_internal.h"
+
+struct lq_octree {
+    int device;
+    lq::DevTree t;
+    int32_t *d_child;
+    void *d_rows;
+    int64_t bytes;
+};
+
+namespace lq {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+static lq_status fail(lq_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+static lq_status hip_fail(hipError_t e, const char *what) {
+    return fail(LQ_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------ conversions
+uint16_t f32_to_f16_rne(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    uint32_t sign = (u >> 16) & 0x8000u;
+    uint32_t ex = (u >> 23) & 0xFFu;
+    uint32_t man = u & 0x7FFFFFu;
+    if (ex == 0xFFu) return (uint16_t)(sign | 0x7C00u | (man ? 0x200u : 0u));
+    int e = (int)ex - 127 + 15;
+    if (e >= 31) return (uint16_t)(sign | 0x7C00u);          // overflow -> inf
+    if (e <= 0) {                                             // subnormal or zero
+        if (e < -10) return (uint16_t)sign;
+        man |= 0x800000u;
+        int shift = 14 - e;                                   // 1 - e + 13
+        uint32_t half = man >> shift;
+        uint32_t rem = man & ((1u << shift) - 1u);
+        uint32_t mid = 1u << (shift - 1);
+        if (rem > mid || (rem == mid && (half & 1u))) ++half;
+        return (uint16_t)(sign | half);
+    }
+    uint32_t half = ((uint32_t)e << 10) | (man >> 13);
+    uint32_t rem = man & 0x1FFFu;
+    if (rem > 0x1000u || (rem == 0x1000u && (half & 1u))) ++half;   // may carry into inf
+    return (uint16_t)(sign | half);
+}
+
+uint16_t f32_to_bf16_rne(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+int row_bytes(int storage, int K);   // octree_query.hip
+
+// ------------------------------------------------------------ SH constants
+// Real SH without the Condon-Shortley phase:
+//   Y_lm = s_m K_l^|m| P_l^|m|(cos theta) trig(m phi),  s_0 = 1, s_m = sqrt(2),
+//   K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+// P_l^|m|(cos theta) sin^|m| ... trig folds into a polynomial in (x, y, z);
+// a_lm is the rational factor between the two, so c_lm = s_m K_l^|m| a_lm
+// multiplies the polynomial evaluated in the kernel (same k = l^2 + l + m order).
+static void sh_constants(float *c) {
+    static const double a[25] = {
+        1.0,                                      // l = 0
+        1.0, 1.0, 1.0,                            // l = 1: y, z, x
+        6.0, 3.0, 0.5, 3.0, 3.0,                  // l = 2: xy, yz, 3z^2-1, xz, x^2-y^2
+        15.0, 30.0, 1.5, 0.5, 1.5, 15.0, 15.0,    // l = 3
+        420.0, 105.0, 15.0, 2.5, 0.125, 2.5, 7.5, 105.0, 105.0,   // l = 4
+    };
+    for (int l = 0; l <= 4; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double f = 1.0;
+            for (int i = l - am + 1; i <= l + am; ++i) f *= (double)i;   // (l+m)!/(l-m)!
+            double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) / f);
+            double s = am == 0 ? 1.0 : sqrt(2.0);
+            c[l * l + l + m] = (float)(s * K * a[l * l + l + m]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ validation
+static lq_status validate_desc(const lq_octree_desc *d) {
+    if (!d) return fail(LQ_ERR_INVALID_ARG, "descriptor is NULL");
+    if (d->max_depth < 1 || d->max_depth > 10) return fail(LQ_ERR_FORMAT, "max_depth must be in [1, 10]");
+    if (d->sh_degree < 0 || d->sh_degree > 4) return fail(LQ_ERR_FORMAT, "sh_degree must be in [0, 4]");
+    if (d->n_nodes < 1) return fail(LQ_ERR_FORMAT, "n_nodes must be >= 1 (the root)");
+    if (d->n_leaves < 0) return fail(LQ_ERR_FORMAT, "n_leaves must be >= 0");
+    if (!d->child) return fail(LQ_ERR_INVALID_ARG, "child table is NULL");
+    if (d->n_leaves > 0 && (!d->sigma || !d->sh)) return fail(LQ_ERR_INVALID_ARG, "sigma/sh is NULL");
+    if (!(d->l_max > 0.0f) || !isfinite(d->l_max)) return fail(LQ_ERR_FORMAT, "l_max must be finite and > 0");
+    if (!isfinite(d->sigma_min) || !(d->alpha_max > 0.0f) || !(d->alpha_max <= 1.0f))
+        return fail(LQ_ERR_FORMAT, "sigma_min must be finite and alpha_max in (0, 1]");
+    // the child table must be a tree with leaves exactly one level above max depth
+    const int D = d->max_depth;
+    std::vector<uint8_t> seen_node(d->n_nodes, 0);
+    std::vector<uint8_t> seen_leaf(d->n_leaves, 0);
+    std::vector<int32_t> cur{0}, nxt;
+    seen_node[0] = 1;
+    int64_t nodes_reached = 1;
+    for (int level = 0; level < D && !cur.empty(); ++level) {
+        nxt.clear();
+        for (int32_t node : cur) {
+            for (int oct = 0; oct < 8; ++oct) {
+                int32_t c = d->child[(size_t)node * 8 + oct];
+                if (c == 0) continue;
+                if (c > 0) {
+                    if (level + 1 >= D) return fail(LQ_ERR_FORMAT, "internal node below max_depth - 1");
+                    if (c >= d->n_nodes || seen_node[c]) return fail(LQ_ERR_FORMAT, "bad or repeated node index");
+                    seen_node[c] = 1;
+                    ++nodes_reached;
+                    nxt.push_back(c);
+                } else {
+                    int64_t leaf = -(int64_t)c - 1;
+                    if (level + 1 != D) return fail(LQ_ERR_FORMAT, "data leaf above max_depth");
+                    if (leaf >= d->n_leaves || seen_leaf[leaf]) return fail(LQ_ERR_FORMAT, "bad or repeated leaf index");
+                    seen_leaf[leaf] = 1;
+                }
+            }
+        }
+        cur.swap(nxt);
+    }
+    if (nodes_reached != d->n_nodes) return fail(LQ_ERR_FORMAT, "unreachable nodes in the child table");
+    return LQ_OK;
+}
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" {
+
+const char *lq_last_error(void) { return g_err.c_str(); }
+const char *lq_version(void) { return "lumiq 0.1 (gfx950)"; }
+
+lq_status lq_load_octree_desc(const lq_octree_desc *desc, int storage, int device, lq_octree **out) {
+    if (!out) return fail(LQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (storage != LQ_F32 && storage != LQ_F16 && storage != LQ_BF16)
+        return fail(LQ_ERR_INVALID_ARG, "storage must be LQ_F32, LQ_F16 or LQ_BF16");
+    lq_status st = validate_desc(desc);
+    if (st != LQ_OK) return st;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(LQ_ERR_HIP, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev) return fail(LQ_ERR_INVALID_ARG, "device index out of range");
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+    const int K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
+    const int esz = storage == LQ_F32 ? 4 : 2;
+    const int rb = row_bytes(storage, K);
+    const int64_t nl = desc->n_leaves;
+    std::vector<uint8_t> rows((size_t)nl * rb, 0);
+    for (int64_t i = 0; i < nl; ++i) {
+        uint8_t *row = rows.data() + (size_t)i * rb;
+        for (int j = 0; j < 1 + 3 * K; ++j) {
+            float v = j == 0 ? desc->sigma[i] : desc->sh[(size_t)i * 3 * K + (j - 1)];
+            if (storage == LQ_F32) {
+                memcpy(row + 4 * j, &v, 4);
+            } else {
+                uint16_t b = storage == LQ_F16 ? f32_to_f16_rne(v) : f32_to_bf16_rne(v);
+                memcpy(row + esz * j, &b, 2);
+            }
+        }
+    }
+    lq_octree *t = new (std::nothrow) lq_octree();
+    if (!t) return fail(LQ_ERR_OOM, "host allocation failed");
+    t->device = device;
+    const size_t child_bytes = (size_t)desc->n_nodes * 32;
+    const size_t row_total = rows.size() ? rows.size() : 64;
+    if ((e = hipMalloc((void **)&t->d_child, child_bytes)) != hipSuccess) {
+        delete t;
+        (void)hipGetLastError();
+        return fail(LQ_ERR_OOM, "device allocation of the node table failed");
+    }
+    if ((e = hipMalloc(&t->d_rows, row_total)) != hipSuccess) {
+        (void)hipFree(t->d_child);
+        delete t;
+        (void)hipGetLastError();
+        return fail(LQ_ERR_OOM, "device allocation of the leaf table failed");
+    }
+    e = hipMemcpy(t->d_child, desc->child, child_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && rows.size()) e = hipMemcpy(t->d_rows, rows.data(), rows.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(t->d_child);
+        (void)hipFree(t->d_rows);
+        delete t;
+        return hip_fail(e, "uploading the tree");
+    }
+    t->bytes = (int64_t)(child_bytes + row_total);
+    DevTree &dt = t->t;
+    dt.child = t->d_child;
+    dt.rows = t->d_rows;
+    dt.depth = desc->max_depth;
+    dt.sh_degree = desc->sh_degree;
+    dt.K = K;
+    dt.storage = storage;
+    dt.n_nodes = desc->n_nodes;
+    dt.n_leaves = desc->n_leaves;
+    dt.row_elems = rb / esz;
+    dt.l_max = desc->l_max;
+    dt.sigma_min = desc->sigma_min;
+    dt.alpha_max = desc->alpha_max;
+    sh_constants(dt.ycoef);
+    *out = t;
+    return LQ_OK;
+}
+
+lq_status lq_load_octree(const char *path, int storage, int device, lq_octree **out) {
+    if (!out) return fail(LQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(LQ_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(LQ_ERR_IO, std::string("cannot open ") + path);
+    struct {
+        char magic[4];
+        uint32_t version;
+        int32_t depth, deg, n_nodes, n_leaves;
+        float l_max, sigma_min, alpha_max;
+        uint32_t reserved;
+    } hdr;
+    static_assert(sizeof(hdr) == 40, "header layout");
+    lq_status st = LQ_OK;
+    std::vector<int32_t> child;
+    std::vector<float> sigma, sh;
+    if (fread(&hdr, sizeof(hdr), 1, f) != 1 || memcmp(hdr.magic, "LQOT", 4) != 0 || hdr.version != 1) {
+        st = fail(LQ_ERR_FORMAT, "not a version-1 LQOT plenoctree file");
+    } else if (hdr.depth < 1 || hdr.depth > 10 || hdr.deg < 0 || hdr.deg > 4 || hdr.n_nodes < 1 ||
+               hdr.n_leaves < 0 || hdr.n_nodes > (1 << 30) || hdr.n_leaves > (1 << 30)) {
+        st = fail(LQ_ERR_FORMAT, "header out of range");
+    } else {
+        const size_t K = (size_t)(hdr.deg + 1) * (hdr.deg + 1);
+        child.resize((size_t)hdr.n_nodes * 8);
+        sigma.resize((size_t)hdr.n_leaves);
+        sh.resize((size_t)hdr.n_leaves * 3 * K);
+        if (fread(child.data(), 4, child.size(), f) != child.size() ||
+            fread(sigma.data(), 4, sigma.size(), f) != sigma.size() ||
+            fread(sh.data(), 4, sh.size(), f) != sh.size())
+            st = fail(LQ_ERR_FORMAT, "truncated plenoctree file");
+    }
+    fclose(f);
+    if (st != LQ_OK) return st;
+    lq_octree_desc d;
+    d.max_depth = hdr.depth;
+    d.sh_degree = hdr.deg;
+    d.n_nodes = hdr.n_nodes;
+    d.n_leaves = hdr.n_leaves;
+    d.l_max = hdr.l_max;
+    d.sigma_min = hdr.sigma_min;
+    d.alpha_max = hdr.alpha_max;
+    d.child = child.data();
+    d.sigma = sigma.data();
+    d.sh = sh.data();
+    return lq_load_octree_desc(&d, storage, device, out);
+}
+
+void lq_free_octree(lq_octree *t) {
+    if (!t) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(t->device);
+    (void)hipFree(t->d_child);
+    (void)hipFree(t->d_rows);
+    (void)hipSetDevice(cur);
+    delete t;
+}
+
+lq_status lq_octree_info(const lq_octree *t, int64_t *device_bytes, int32_t *n_nodes, int32_t *n_leaves,
+                         int32_t *max_depth, int32_t *sh_degree, int32_t *storage) {
+    if (!t) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");
+    if (device_bytes) *device_bytes = t->bytes;
+    if (n_nodes) *n_nodes = t->t.n_nodes;
+    if (n_leaves) *n_leaves = t->t.n_leaves;
+    if (max_depth) *max_depth = t->t.depth;
+    if (sh_degree) *sh_degree = t->t.sh_degree;
+    if (storage) *storage = t->t.storage;
+    return LQ_OK;
+}
+
+}  // extern "C"
+
+namespace lq {
+
+// A device pointer on `device` whose allocation holds `bytes` from ptr on.
+static lq_status check_dev(const void *ptr, size_t bytes, int device, const char *name) {
+    if (!ptr) return fail(LQ_ERR_INVALID_ARG, std::string(name) + " is NULL");
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LQ_ERR_INVALID_ARG, std::string(name) + " is not a device pointer");
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return fail(LQ_ERR_INVALID_ARG, std::string(name) + " is not a device pointer");
+    if (at.device != device) return fail(LQ_ERR_INVALID_ARG, std::string(name) + " is on another device");
+    if ((uintptr_t)ptr % 4 != 0) return fail(LQ_ERR_INVALID_ARG, std::string(name) + " is not 4-byte aligned");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LQ_ERR_INVALID_ARG, std::string(name) + ": allocation range unknown");
+    }
+    if ((const char *)ptr + bytes > (const char *)base + size)
+        return fail(LQ_ERR_INVALID_ARG, std::string(name) + " is smaller than the batch needs");
+    return LQ_OK;
+}
+
+static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace, void *stream) {
+    if (!t) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");
+    if (a.n < 0) return fail(LQ_ERR_INVALID_ARG, "n must be >= 0");
+    if (a.model != LQ_LINEAR && a.model != LQ_EXP) return fail(LQ_ERR_INVALID_ARG, "model must be LQ_LINEAR or LQ_EXP");
+    if (a.flags & ~(uint32_t)(LQ_NO_EARLY_TERM | LQ_FP64_ACCUM | LQ_NO_SIGMA_SKIP))
+        return fail(LQ_ERR_INVALID_ARG, "unknown flag bits");
+    if (a.n > ((int64_t)1 << 40)) return fail(LQ_ERR_INVALID_ARG, "n too large");
+    if (a.n == 0) return LQ_OK;
+    hipError_t e = hipSetDevice(t->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t n = (size_t)a.n;
+    lq_status st;
+    if ((st = check_dev(a.o, n * 12, t->device, "origins")) != LQ_OK) return st;
+    if ((st = check_dev(a.d, n * 12, t->device, "dirs")) != LQ_OK) return st;
+    if (!trace && !a.rgb) return fail(LQ_ERR_INVALID_ARG, "rgb is NULL");
+    if (a.rgb && (st = check_dev(a.rgb, n * 12, t->device, "rgb")) != LQ_OK) return st;
+    if (a.alpha && (st = check_dev(a.alpha, n * 4, t->device, "alpha")) != LQ_OK) return st;
+    if (trace) {
+        if ((st = check_dev(a.count, n * 4, t->device, "count")) != LQ_OK) return st;
+        if ((st = check_dev(a.hash, n * 8, t->device, "hash")) != LQ_OK) return st;
+        if ((uintptr_t)a.hash % 8) return fail(LQ_ERR_INVALID_ARG, "hash is not 8-byte aligned");
+        if ((st = check_dev(a.term_idx, n * 4, t->device, "term_idx")) != LQ_OK) return st;
+        if ((st = check_dev(a.n_comp, n * 4, t->device, "n_comp")) != LQ_OK) return st;
+        if (a.max_ids < 0) return fail(LQ_ERR_INVALID_ARG, "max_ids must be >= 0");
+        if (a.max_ids > 0 && (st = check_dev(a.leaf_ids, n * (size_t)a.max_ids * 4, t->device, "leaf_ids")) != LQ_OK)
+            return st;
+    }
+    e = launch_query(t->t, a, trace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the emission query");
+    return LQ_OK;
+}
+
+}  // namespace lq
+
+extern "C" {
+
+lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const float *dirs, int64_t n,
+                            float *rgb, float *alpha, int model, uint32_t flags, void *hip_stream) {
+    QueryArgs a{};
+    a.o = origins;
+    a.d = dirs;
+    a.n = n;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.model = model;
+    a.flags = flags;
+    return query_common(tree, a, false, hip_stream);
+}
+
+lq_status lq_query_trace(const lq_octree *tree, const float *origins, const float *dirs, int64_t n,
+                         float *rgb, float *alpha, int model, uint32_t flags, uint32_t *count,
+                         uint64_t *hash, int32_t *term_idx, uint32_t *n_comp, uint32_t *leaf_ids,
+                         int32_t max_ids, void *hip_stream) {
+    QueryArgs a{};
+    a.o = origins;
+    a.d = dirs;
+    a.n = n;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.model = model;
+    a.flags = flags;
+    a.count = count;
+    a.hash = hash;
+    a.term_idx = term_idx;
+    a.n_comp = n_comp;
+    a.leaf_ids = leaf_ids;
+    a.max_ids = max_ids;
+    return query_common(tree, a, true, hip_stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal declarations shared by the library's HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lumiq.h"
+
+namespace lq {
+
+// Device image of a plenoctree.
+//  child: [n_nodes][8] int32 (the descriptor's table, unchanged).
+//  rows:  [n_leaves][row_elems] in the storage type: sigma, then the SH
+//         coefficients of R, G, B (K each), zero padded so that a row is a
+//         power-of-two number of bytes >= 64 (one row never straddles a
+//         128-byte line when it is <= 128 bytes).
+struct DevTree {
+    const int32_t *child;
+    const void *rows;
+    int32_t depth, sh_degree, K, storage;
+    int32_t n_nodes, n_leaves, row_elems, pad;
+    float l_max, sigma_min, alpha_max, pad2;
+    float ycoef[25];   // SH normalisation constants, c_lm of Y_lm = c_lm * poly_lm(x,y,z)
+};
+
+struct QueryArgs {
+    const float *o, *d;
+    int64_t n;
+    float *rgb, *alpha;
+    int model;
+    uint32_t flags;
+    // trace outputs (nullptr when not tracing)
+    uint32_t *count;
+    uint64_t *hash;
+    int32_t *term_idx;
+    uint32_t *n_comp;
+    uint32_t *leaf_ids;
+    int32_t max_ids;
+};
+
+// launch the emission query; returns hipSuccess or the launch error
+hipError_t launch_query(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s);
+
+// FP32 -> storage conversions used by the loader (round to nearest even)
+uint16_t f32_to_f16_rne(float x);
+uint16_t f32_to_bf16_rne(float x);
+
+void set_error(const std::string &msg);
+
+}  // namespace lq

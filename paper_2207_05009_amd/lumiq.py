@@ -1,0 +1,168 @@
+"""ctypes binding of liblumiq.so (include/lumiq.h).
+
+Argument marshalling only: torch tensors supply device memory and streams,
+every step of the query runs in the library's HIP kernels.  The binding fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblumiq.so")
+
+LQ_OK = 0
+LQ_F32, LQ_F16, LQ_BF16 = 0, 1, 2
+LQ_LINEAR, LQ_EXP = 0, 1
+LQ_NO_EARLY_TERM, LQ_FP64_ACCUM, LQ_NO_SIGMA_SKIP = 1, 2, 4
+
+STORAGE = {"f32": LQ_F32, "f16": LQ_F16, "bf16": LQ_BF16}
+MODEL = {"linear": LQ_LINEAR, "exp": LQ_EXP}
+STATUS = {0: "LQ_OK", -1: "LQ_ERR_INVALID_ARG", -2: "LQ_ERR_FORMAT", -3: "LQ_ERR_OOM",
+          -4: "LQ_ERR_HIP", -5: "LQ_ERR_UNSUPPORTED", -6: "LQ_ERR_STATE", -7: "LQ_ERR_IO"}
+
+
+class LumiqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class OctreeDesc(C.Structure):
+    _fields_ = [("max_depth", C.c_int32), ("sh_degree", C.c_int32), ("n_nodes", C.c_int32),
+                ("n_leaves", C.c_int32), ("l_max", C.c_float), ("sigma_min", C.c_float),
+                ("alpha_max", C.c_float), ("child", C.c_void_p), ("sigma", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load liblumiq.so (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            L = C.CDLL(LIB_PATH)
+            vp, i64, i32, u32 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32
+            L.lq_last_error.restype = C.c_char_p
+            L.lq_version.restype = C.c_char_p
+            L.lq_load_octree_desc.argtypes = [C.POINTER(OctreeDesc), C.c_int, C.c_int, C.POINTER(vp)]
+            L.lq_load_octree.argtypes = [C.c_char_p, C.c_int, C.c_int, C.POINTER(vp)]
+            L.lq_free_octree.argtypes = [vp]
+            L.lq_free_octree.restype = None
+            L.lq_octree_info.argtypes = [vp] + [C.c_void_p] * 6
+            L.lq_query_radiance.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32, vp]
+            L.lq_query_trace.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32,
+                                         vp, vp, vp, vp, vp, i32, vp]
+            for name in ("lq_load_octree_desc", "lq_load_octree", "lq_octree_info",
+                         "lq_query_radiance", "lq_query_trace"):
+                getattr(L, name).restype = C.c_int
+            _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != LQ_OK:
+        raise LumiqError(status, lib().lq_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Octree:
+    """A plenoctree resident on one GPU.
+
+    tree: an object with depth, sh_degree, l_max, sigma_min, alpha_max,
+    child [n_nodes, 8] int32, sigma [n_leaves] float32, sh [n_leaves, 3, K]
+    float32 (e.g. inputs.Tree), or a path to an LQOT file.
+    """
+
+    def __init__(self, tree, storage: str = "f32", device: int = 0):
+        self.handle = C.c_void_p()
+        self.device = device
+        self.storage = storage
+        st = STORAGE[storage]
+        if isinstance(tree, (str, os.PathLike)):
+            check(lib().lq_load_octree(os.fsencode(tree), st, device, C.byref(self.handle)))
+        else:
+            child = np.ascontiguousarray(tree.child, dtype=np.int32)
+            sigma = np.ascontiguousarray(tree.sigma, dtype=np.float32)
+            sh = np.ascontiguousarray(tree.sh, dtype=np.float32)
+            desc = OctreeDesc(int(tree.depth), int(tree.sh_degree), child.shape[0], sigma.shape[0],
+                              float(tree.l_max), float(tree.sigma_min), float(tree.alpha_max),
+                              child.ctypes.data, sigma.ctypes.data if sigma.size else None,
+                              sh.ctypes.data if sh.size else None)
+            check(lib().lq_load_octree_desc(C.byref(desc), st, device, C.byref(self.handle)))
+
+    def info(self) -> dict:
+        v = [C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()]
+        check(lib().lq_octree_info(self.handle, *[C.byref(x) for x in v]))
+        keys = ("device_bytes", "n_nodes", "n_leaves", "max_depth", "sh_degree", "storage")
+        return {k: x.value for k, x in zip(keys, v)}
+
+    def free(self) -> None:
+        if self.handle:
+            lib().lq_free_octree(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def query(self, origins, dirs, model: str = "linear", flags: int = 0, rgb=None,
+              alpha=None, want_alpha: bool = True, stream=None):
+        """Emission query.  origins/dirs: float32 [n, 3] CUDA tensors.
+        Returns (rgb [n, 3], alpha [n] or None)."""
+        import torch
+        n = origins.shape[0]
+        if rgb is None:
+            rgb = torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+        if alpha is None and want_alpha:
+            alpha = torch.empty((n,), dtype=torch.float32, device=origins.device)
+        check(lib().lq_query_radiance(self.handle, _ptr(origins), _ptr(dirs), n, _ptr(rgb),
+                                      _ptr(alpha), MODEL[model], flags, _stream(stream)))
+        return rgb, alpha
+
+    def trace(self, origins, dirs, model: str = "linear", flags: int = 0, max_ids: int = 0,
+              stream=None) -> dict:
+        """Validation query: radiance plus per-ray leaf records."""
+        import torch
+        n = origins.shape[0]
+        dev = origins.device
+        out = {
+            "rgb": torch.empty((n, 3), dtype=torch.float32, device=dev),
+            "alpha": torch.empty((n,), dtype=torch.float32, device=dev),
+            "count": torch.empty((n,), dtype=torch.int32, device=dev),
+            "hash": torch.empty((n,), dtype=torch.int64, device=dev),
+            "term_idx": torch.empty((n,), dtype=torch.int32, device=dev),
+            "n_comp": torch.empty((n,), dtype=torch.int32, device=dev),
+        }
+        ids = torch.zeros((n, max_ids), dtype=torch.int32, device=dev) if max_ids > 0 else None
+        check(lib().lq_query_trace(self.handle, _ptr(origins), _ptr(dirs), n, _ptr(out["rgb"]),
+                                   _ptr(out["alpha"]), MODEL[model], flags, _ptr(out["count"]),
+                                   _ptr(out["hash"]), _ptr(out["term_idx"]), _ptr(out["n_comp"]),
+                                   _ptr(ids), max_ids, _stream(stream)))
+        if ids is not None:
+            out["leaf_ids"] = ids
+        return out
+
+
+def version() -> str:
+    return lib().lq_version().decode()

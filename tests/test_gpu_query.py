@@ -1,0 +1,216 @@
+"""GPU parity of the emission query (through the C ABI) against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import core
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import torch
+    import paper_2207_05009_amd as lq
+    assert torch.cuda.is_available()
+    lq.lib()
+    return lq
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run_trace(oct_, o, d, model, flags=0, max_ids=0):
+    import torch
+    out = oct_.trace(_dev(o), _dev(d), model=model, flags=flags, max_ids=max_ids)
+    torch.cuda.synchronize()
+    return parity.to_numpy(out)
+
+
+@pytest.mark.parametrize("model", ["linear", "exp"])
+def test_small_config_full_parity(lq, c0_tree, model):
+    o, d = inputs.rays.sphere_to_cube(65536, 1)
+    _say(f"small config, 65536 rays, depth 6, model={model}")
+    oct_ = lq.Octree(c0_tree, "f32")
+    m = 0 if model == "linear" else 1
+    orc = core.query(c0_tree, o, d, model=m, max_ids=160)
+    assert orc["count"].max() <= 160
+    g = _run_trace(oct_, o, d, model, max_ids=160)
+    rep = parity.compare(g, orc, c0_tree.l_max)
+    _say(f"report {rep}")
+    assert rep["ok"], rep
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 5])
+def test_adversarial_rays_small_trees(lq, depth):
+    tree = inputs.random_tree(depth, 0.4, seed=50 + depth)
+    o1, d1 = inputs.rays.adversarial(depth, seed=60 + depth, n=400)
+    rng = np.random.default_rng(depth)
+    o2 = (rng.normal(size=(400, 3)) * 2.5).astype(np.float32)
+    d2 = (rng.uniform(-1.1, 1.1, size=(400, 3)) - o2).astype(np.float32)
+    o, d = np.concatenate([o1, o2]), np.concatenate([d1, d2])
+    _say(f"adversarial rays, depth {depth}, n={len(o)}")
+    oct_ = lq.Octree(tree, "f32")
+    mx = 3 * (1 << depth) + 4
+    for model, m in (("linear", 0), ("exp", 1)):
+        for flags in (0, lq.LQ_NO_EARLY_TERM):
+            orc = parity.oracle_for(tree, o, d, m, flags, max_ids=mx)
+            g = _run_trace(oct_, o, d, model, flags, max_ids=mx)
+            rep = parity.compare(g, orc, tree.l_max)
+            assert rep["ok"], (model, flags, rep)
+
+
+def test_flags_and_fp64_accumulation(lq, c0_tree):
+    o, d = inputs.rays.sphere_to_cube(8192, 2)
+    oct_ = lq.Octree(c0_tree, "f32")
+    for flags in (lq.LQ_NO_EARLY_TERM, lq.LQ_NO_SIGMA_SKIP, lq.LQ_NO_EARLY_TERM | lq.LQ_NO_SIGMA_SKIP,
+                  lq.LQ_FP64_ACCUM, lq.LQ_FP64_ACCUM | lq.LQ_NO_EARLY_TERM):
+        for model, m in (("linear", 0), ("exp", 1)):
+            _say(f"flags={flags} model={model}")
+            orc = parity.oracle_for(c0_tree, o, d, m, flags, max_ids=160)
+            g = _run_trace(oct_, o, d, model, flags, max_ids=160)
+            rep = parity.compare(g, orc, c0_tree.l_max)
+            assert rep["ok"], (flags, model, rep)
+            if flags & lq.LQ_FP64_ACCUM:
+                # FP64 accumulation leaves only the float32 leaf inputs' error
+                assert rep["max_rel"] < 2e-5, rep
+
+
+def test_radiance_kernel_matches_trace_kernel(lq, c0_tree):
+    import torch
+    o, d = inputs.rays.sphere_to_cube(65536, 3)
+    oct_ = lq.Octree(c0_tree, "f32")
+    _say("query vs trace outputs")
+    rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")
+    t = oct_.trace(_dev(o), _dev(d), model="linear")
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, t["rgb"]) and torch.equal(alpha, t["alpha"])
+
+
+def test_empty_tree_and_misses(lq):
+    import torch
+    tree = inputs.empty_tree(4)
+    oct_ = lq.Octree(tree, "f32")
+    o, d = inputs.rays.sphere_to_cube(4096, 4)
+    _say("empty tree")
+    rgb, alpha = oct_.query(_dev(o), _dev(d))
+    torch.cuda.synchronize()
+    assert float(rgb.abs().max()) == 0.0 and float(alpha.abs().max()) == 0.0
+    # rays that miss, non-finite rays, zero directions
+    full = inputs.uniform_tree(2, 3.0, np.zeros((3, 9)))
+    oct2 = lq.Octree(full, "f32")
+    o = np.array([[3, 3, 3], [0, 0, 5], [np.nan, 0, 0], [0, 0, 0], [-3, 0.5, 0.5]], np.float32)
+    d = np.array([[1, 0, 0], [0, 0, 1], [1, 0, 0], [0, 0, 0], [1, 0, np.inf]], np.float32)
+    rgb, alpha = oct2.query(_dev(o), _dev(d))
+    torch.cuda.synchronize()
+    assert float(rgb.abs().max()) == 0.0 and float(alpha.abs().max()) == 0.0
+
+
+def test_uniform_cube_closed_form(lq):
+    import math
+    import torch
+    sig = 0.75
+    tree = inputs.uniform_tree(3, sig, np.array([[-2.0]] * 3))
+    oct_ = lq.Octree(tree, "f32")
+    rng = np.random.default_rng(9)
+    o = rng.normal(size=(2048, 3))
+    o = (3 * o / np.linalg.norm(o, axis=1, keepdims=True)).astype(np.float32)
+    tgt = rng.uniform(-0.9, 0.9, size=(2048, 3))
+    d = (tgt - o).astype(np.float32)
+    _say("uniform cube closed form")
+    rgb, alpha = oct_.query(_dev(o), _dev(d), model="exp", flags=lq.LQ_NO_EARLY_TERM)
+    torch.cuda.synchronize()
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    with np.errstate(divide="ignore"):
+        t0 = (-1 - od) / dd
+        t1 = (1 - od) / dd
+    tin = np.minimum(t0, t1).max(1)
+    tout = np.maximum(t0, t1).min(1)
+    chord = (tout - tin) * np.linalg.norm(dd, axis=1)
+    phi = tree.l_max / (1 + math.exp(2.0 * 0.5 / math.sqrt(math.pi)))
+    ref = phi * (1 - np.exp(-sig * chord))
+    err = np.abs(rgb.cpu().numpy()[:, 0] - ref) / ref
+    assert err.max() < 1e-4, err.max()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_reduced_precision_storage(lq, c0_tree, storage):
+    o, d = inputs.rays.sphere_to_cube(16384, 5)
+    oct_ = lq.Octree(c0_tree, storage)
+    _say(f"storage {storage}")
+    orc_q = core.query(c0_tree, o, d, model=0, storage=storage, max_ids=160)
+    g = _run_trace(oct_, o, d, "linear", max_ids=160)
+    rep = parity.compare(g, orc_q, c0_tree.l_max)
+    assert rep["ok"], rep
+    # stated (not bounded) error against the float32 tree
+    orc32 = core.query(c0_tree, o, d, model=0)
+    err = parity.rel_err(g["rgb"].astype(np.float64), orc32["L"], c0_tree.l_max)
+    _say(f"{storage} vs fp32 tree: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
+
+
+def test_direction_scaling_bit_identical(lq, c0_tree):
+    o, d = inputs.rays.sphere_to_cube(16384, 6)
+    oct_ = lq.Octree(c0_tree, "f32")
+    _say("power-of-two scaling")
+    ref = _run_trace(oct_, o, d, "linear", max_ids=160)
+    for k in (-30, -2, 5, 40):
+        g = _run_trace(oct_, o, (d * np.float32(2.0 ** k)).astype(np.float32), "linear", max_ids=160)
+        for key in ("rgb", "alpha", "count", "hash", "term_idx", "leaf_ids"):
+            assert np.array_equal(g[key], ref[key]), (k, key)
+
+
+def test_full_size_camera_sampled_parity(lq, c1_tree):
+    """The depth-9 tree and the 2048x2048 camera batch in one launch, as the
+    benchmark times it; a seeded sample of rays is checked one by one."""
+    import torch
+    o, d = inputs.rays.pinhole(2048, 2048)
+    _say(f"full-size camera batch: {len(o)} rays, {c1_tree.n_leaves} leaves")
+    oct_ = lq.Octree(c1_tree, "f32")
+    out = parity.to_numpy(oct_.trace(_dev(o), _dev(d), model="linear"))
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(7).choice(len(o), 20000, replace=False))
+    orc = core.query(c1_tree, o[idx], d[idx], model=0)
+    g = {k: v[idx] for k, v in out.items()}
+    rep = parity.compare(g, orc, c1_tree.l_max, ids=False)
+    _say(f"report {rep}")
+    assert rep["ok"], rep
+    # properties on every ray
+    assert np.all(np.isfinite(out["rgb"])) and np.all(out["rgb"] >= 0)
+    assert np.all((out["alpha"] >= 0) & (out["alpha"] <= 1))
+    assert np.all(out["rgb"] <= c1_tree.l_max * out["alpha"][:, None] * (1 + 1e-5) + 1e-6)
+
+
+def test_abi_rejects_bad_pointers(lq, c0_tree):
+    import ctypes as C
+    import torch
+    oct_ = lq.Octree(c0_tree, "f32")
+    o = torch.zeros((16, 3), device="cuda")
+    d = torch.ones((16, 3), device="cuda")
+    rgb = torch.zeros((16, 3), device="cuda")
+    L = lq.lib()
+    host = np.zeros((16, 3), np.float32)
+    _say("ABI pointer checks")
+    st = L.lq_query_radiance(oct_.handle, C.c_void_p(host.ctypes.data), C.c_void_p(d.data_ptr()), 16,
+                             C.c_void_p(rgb.data_ptr()), None, 0, 0, None)
+    assert st == -1 and b"device pointer" in L.lq_last_error()
+    small = torch.zeros((4, 3), device="cuda")
+    st = L.lq_query_radiance(oct_.handle, C.c_void_p(o.data_ptr()), C.c_void_p(d.data_ptr()), 1 << 22,
+                             C.c_void_p(small.data_ptr()), None, 0, 0, None)
+    assert st == -1
+    st = L.lq_query_radiance(oct_.handle, C.c_void_p(o.data_ptr()), C.c_void_p(d.data_ptr()), 16,
+                             C.c_void_p(rgb.data_ptr()), None, 7, 0, None)
+    assert st == -1
+    st = L.lq_query_radiance(oct_.handle, C.c_void_p(o.data_ptr()), C.c_void_p(d.data_ptr()), 16,
+                             C.c_void_p(rgb.data_ptr()), None, 0, 1 << 9, None)
+    assert st == -1
+    assert L.lq_query_radiance(oct_.handle, None, None, 0, None, None, 0, 0, None) == 0
