@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the luminaire emission query on one MI355X.
+
+Workload (one step = one launch of the whole query over the batch, inputs
+resident in HBM): the depth-9 synthetic luminaire plenoctree (512^3 cells,
+~6.2M data leaves, SH degree 2, float32 storage, 16 density blobs + 4 thin
+shells) and the 4,194,304 rays of a 2048x2048 pinhole camera at distance 3
+with a 40 degree field of view; linear transmittance, sigma_min = 0.1,
+alpha_max = 0.9.
+
+Prints one JSON line (rays/s) with the dominant kernel's roofline fraction
+(algorithmic bytes per launch / measured launch time vs 8 TB/s) and the
+CPU oracle's throughput on a bounded sample of the same rays.  Extra
+variants (float16/bfloat16 storage, exponential transmittance, incoherent
+room queries) are reported under "variants".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s: octree radiance query FP32 vs FP16 vs MLP surrogate at ≤1% rel err"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_05009_amd", "csrc", "octree_query.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def src_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def time_launches(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall
+
+
+def alg_bytes(trace, K, elem_bytes):
+    """Bytes the method must move per launch: rays in (24 B), RGB + alpha out
+    (16 B), a density per data leaf visited, 3K SH coefficients per leaf
+    composited, one 4-byte child slot per octree node visited."""
+    n = trace["count"].numel()
+    occ = int(trace["count"].sum())
+    comp = int(trace["n_comp"].sum())
+    steps = int(trace["n_steps"].sum())
+    return 40 * n + occ * elem_bytes + comp * 3 * K * elem_bytes + steps * 4, {
+        "rays": n, "mean_leaves": occ / n, "mean_composited": comp / n, "mean_nodes": steps / n}
+
+
+def traffic_from_profiles(kernel_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    p = os.path.join(PROFILE_DIR, f"traffic_{kernel_tag}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            t = json.load(f)
+        if t.get("kernel_src_sha1") != src_hash(KERNEL_SRC):
+            return None
+        return float(t["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(tree, o, d, budget_s):
+    """The FP64 oracle on the host cores, on a seeded sample of the rays,
+    chunk by chunk until the time budget is spent."""
+    import numpy as np
+    from oracle import core
+    threads = max(1, min(16, os.cpu_count() or 1))
+    P = core.PreparedTree(tree, "f32")
+    rng = np.random.default_rng(123)
+    order = rng.permutation(len(o))
+    done, t_total = 0, 0.0
+    chunk = 131072
+    while done < len(o) and t_total < budget_s:
+        idx = np.sort(order[done: done + chunk])
+        t0 = time.perf_counter()
+        core.query(tree, o[idx], d[idx], model=core.LINEAR, prepared=P, n_threads=threads)
+        t_total += time.perf_counter() - t0
+        done += len(idx)
+    return {"value": done / t_total, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of the {len(o)} camera rays (seeded random subset), FP64 oracle "
+                      f"with its OpenMP loop over rays, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the query shards by rays with no exchange, and this "
+              "build runs on a single MI355X (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2207_05009_amd import lumiq
+
+    if not os.path.exists(lumiq.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    log("generating the depth-9 tree")
+    tree = inputs.cached_tree(inputs.C1_TREE)
+    o_np, d_np = inputs.rays.pinhole(2048, 2048)
+    n = len(o_np)
+    o = torch.from_numpy(o_np).cuda()
+    d = torch.from_numpy(d_np).cuda()
+    rgb = torch.empty((n, 3), device="cuda")
+    alpha = torch.empty((n,), device="cuda")
+
+    oct32 = lumiq.Octree(tree, "f32")
+    log(f"tree uploaded: {oct32.info()}")
+
+    def step():
+        oct32.query(o, d, model="linear", rgb=rgb, alpha=alpha)
+
+    ms, wall = time_launches(step, args.steps, args.warmup)
+    value = n / (ms * 1e-3)
+    log(f"f32 linear: {ms:.3f} ms/step, {value / 1e6:.1f} Mrays/s (wall {wall:.3f} s)")
+
+    tr = oct32.trace(o, d, model="linear")
+    torch.cuda.synchronize()
+    nbytes, counts = alg_bytes(tr, tree.K, 4)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles("query_f32_camera")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": nbytes, "per_ray": counts,
+                "kernel": "k_query<F32, SH deg 2, FP32 accumulation>"}
+
+    variants = {}
+    if not args.no_variants:
+        for storage in ("f16", "bf16"):
+            oc = lumiq.Octree(tree, storage)
+            vms, _ = time_launches(lambda: oc.query(o, d, model="linear", rgb=rgb, alpha=alpha),
+                                   max(5, args.steps // 2), 2)
+            variants[f"camera_{storage}_linear"] = {"rays_per_s": n / (vms * 1e-3), "ms_per_step": vms}
+            log(f"{storage}: {vms:.3f} ms/step")
+            oc.free()
+        vms, _ = time_launches(lambda: oct32.query(o, d, model="exp", rgb=rgb, alpha=alpha),
+                               max(5, args.steps // 2), 2)
+        variants["camera_f32_exp"] = {"rays_per_s": n / (vms * 1e-3), "ms_per_step": vms}
+        # incoherent shading queries from a room around the luminaire
+        ro, rd = inputs.rays.room_to_proxy(1 << 24, 20)
+        ro_t, rd_t = torch.from_numpy(ro).cuda(), torch.from_numpy(rd).cuda()
+        rrgb = torch.empty((1 << 24, 3), device="cuda")
+        ralpha = torch.empty((1 << 24,), device="cuda")
+        for storage in ("f32", "f16", "bf16"):
+            oc = oct32 if storage == "f32" else lumiq.Octree(tree, storage)
+            vms, _ = time_launches(lambda: oc.query(ro_t, rd_t, model="linear", rgb=rrgb, alpha=ralpha),
+                                   max(3, args.steps // 4), 1)
+            variants[f"room16M_{storage}_linear"] = {"rays_per_s": (1 << 24) / (vms * 1e-3),
+                                                     "ms_per_step": vms}
+            log(f"room {storage}: {vms:.3f} ms/step")
+            if storage != "f32":
+                oc.free()
+        del ro_t, rd_t, rrgb, ralpha
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(tree, o_np, d_np, args.cpu_budget)
+        log(f"cpu oracle: {cpu['value']:.0f} rays/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "depth-9 synthetic luminaire plenoctree (512^3, SH degree 2, "
+                               "float32) x 2048x2048 pinhole camera rays, linear transmittance",
+                   "rays": n, "n_leaves": tree.n_leaves, "n_nodes": tree.n_nodes,
+                   "sh_degree": tree.sh_degree, "storage": "f32", "transmittance": "linear",
+                   "sigma_min": 0.1, "alpha_max": 0.9},
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

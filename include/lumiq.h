@@ -135,13 +135,16 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
  *   term_idx[i]  index (in that sequence) of the leaf at which alpha_max
  *                stopped the march, or -1;
  *   n_comp[i]    leaves composited;
+ *   n_steps[i]   optional: octree nodes visited (data leaves and empty
+ *                nodes, each reached by one descent), up to the stop;
  *   leaf_ids     optional [n][max_ids]: the first max_ids leaf ids.
  * rgb/alpha may be NULL.  All arrays are device pointers.
  */
 lq_status lq_query_trace(const lq_octree *tree, const float *origins, const float *dirs,
                          int64_t n, float *rgb, float *alpha, int model, uint32_t flags,
                          uint32_t *count, uint64_t *hash, int32_t *term_idx, uint32_t *n_comp,
-                         uint32_t *leaf_ids, int32_t max_ids, void *hip_stream);
+                         uint32_t *n_steps, uint32_t *leaf_ids, int32_t max_ids,
+                         void *hip_stream);
 
 /* Text of the last error on this thread ("" if none). */
 const char *lq_last_error(void);

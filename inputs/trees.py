@@ -383,3 +383,31 @@ def random_tree(depth: int, p_occ: float, seed: int, sh_degree: int = 2,
 C0_TREE = TreeSpec(depth=6, n_blobs=8, n_shells=0, sh_degree=2, seed=0, occupancy=0.30)
 # about 6M occupied leaves at 512^3 (4.5% of the cells, shells included)
 C1_TREE = TreeSpec(depth=9, n_blobs=16, n_shells=4, sh_degree=2, seed=10, occupancy=0.040)
+
+
+def cached_tree(spec: TreeSpec, cache_dir: str | None = None) -> Tree:
+    """make_tree(spec), memoised as an .npz file (default: $LUMIQ_CACHE or
+    <tmp>/lumiq_inputs) so that several processes on one machine generate a
+    large tree once."""
+    import hashlib
+    import os
+    import tempfile
+    cache_dir = cache_dir or os.environ.get("LUMIQ_CACHE") or os.path.join(
+        tempfile.gettempdir(), "lumiq_inputs")
+    key = hashlib.sha1(repr(spec).encode()).hexdigest()[:16]
+    path = os.path.join(cache_dir, f"tree_{key}.npz")
+    if os.path.exists(path):
+        try:
+            z = np.load(path, allow_pickle=False)
+            return Tree(depth=int(z["depth"]), sh_degree=int(z["sh_degree"]),
+                        l_max=float(z["l_max"]), child=z["child"], sigma=z["sigma"], sh=z["sh"],
+                        leaf_cells=z["leaf_cells"], meta={"cached": path})
+        except Exception:
+            pass
+    t = make_tree(spec)
+    os.makedirs(cache_dir, exist_ok=True)
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, depth=t.depth, sh_degree=t.sh_degree, l_max=t.l_max, child=t.child,
+             sigma=t.sigma, sh=t.sh, leaf_cells=t.leaf_cells)
+    os.replace(tmp, path)
+    return t

@@ -124,7 +124,7 @@ class PreparedTree:
 
 def query(tree, o, d, model: int = LINEAR, opts: int = 0, storage: str = "f32",
           max_ids: int = 0, n_threads: int = 0, exact_fallback: bool = True,
-          prepared: PreparedTree | None = None) -> dict:
+          prepared: PreparedTree | None = None, force_exact: bool = False) -> dict:
     """Run the oracle over a batch of rays.  Returns a dict of numpy arrays:
     L [n,3], alpha, count, hash, term_idx, n_comp, n_nodes, flags, the
     alternative candidate for threshold-ambiguous rays (alt_*), optional
@@ -152,6 +152,8 @@ def query(tree, o, d, model: int = LINEAR, opts: int = 0, storage: str = "f32",
     if ids is not None:
         out["leaf_ids"] = ids
     flagged = np.nonzero(out["flags"] & NEED_EXACT)[0]
+    if force_exact:       # test hook: re-run every ray in exact arithmetic
+        flagged = np.arange(n)
     out["n_exact"] = int(flagged.size)
     if exact_fallback:
         for i in flagged.tolist():
@@ -161,7 +163,7 @@ def query(tree, o, d, model: int = LINEAR, opts: int = 0, storage: str = "f32",
 
 def _exact_ray(P, o, d, model, opts, out, i, ids, max_ids):
     tree = P.tree
-    segs, visited = exact.march_octree(tree, o, d)
+    segs, visited, ordinals = exact.march_octree(tree, o, d, with_ordinals=True)
     flags = int(out["flags"][i]) & ~(NEED_EXACT | AMBIGUOUS | MISS)
     if not segs and not _hits(tree, o, d):
         flags |= MISS
@@ -176,7 +178,8 @@ def _exact_ray(P, o, d, model, opts, out, i, ids, max_ids):
     out["hash"][i] = r["hash"]
     out["term_idx"][i] = r["term_idx"]
     out["n_comp"][i] = r["n_comp"]
-    out["n_nodes"][i] = visited
+    # nodes visited up to the stop leaf (or to the far box hit)
+    out["n_nodes"][i] = ordinals[r["term_idx"]] if r["term_idx"] >= 0 else visited
     out["alt_valid"][i] = 0
     if r["first_amb_test"] >= 0:
         flags |= AMBIGUOUS

@@ -83,16 +83,18 @@ class _Ray:
         return t_start, t_out
 
 
-def march_octree(tree, o, d):
-    """Octree march in exact arithmetic.  Returns (segments, n_nodes_visited)."""
+def march_octree(tree, o, d, with_ordinals=False):
+    """Octree march in exact arithmetic.  Returns (segments, n_nodes_visited)
+    and, with with_ordinals, the 1-based node ordinal of every segment."""
     r = _Ray(o, d, tree.depth)
     span = r.clip()
     if span is None:
-        return [], 0
+        return ([], 0, []) if with_ordinals else ([], 0)
     t, t_out = span
     N = r.N
     child = tree.child
     segs = []
+    ordinals = []
     visited = 0
     while t < t_out:
         node, level = 0, 0
@@ -130,8 +132,9 @@ def march_octree(tree, o, d):
         assert t_next > t
         if c < 0:
             segs.append((-c - 1, _morton(*lo), t, t_next))
+            ordinals.append(visited)
         t = t_next
-    return segs, visited
+    return (segs, visited, ordinals) if with_ordinals else (segs, visited)
 
 
 def brute_force(tree, o, d, leaf_cells):

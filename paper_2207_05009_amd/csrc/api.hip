@@ -349,6 +349,7 @@ static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace
         if ((uintptr_t)a.hash % 8) return fail(LQ_ERR_INVALID_ARG, "hash is not 8-byte aligned");
         if ((st = check_dev(a.term_idx, n * 4, t->device, "term_idx")) != LQ_OK) return st;
         if ((st = check_dev(a.n_comp, n * 4, t->device, "n_comp")) != LQ_OK) return st;
+        if (a.n_steps && (st = check_dev(a.n_steps, n * 4, t->device, "n_steps")) != LQ_OK) return st;
         if (a.max_ids < 0) return fail(LQ_ERR_INVALID_ARG, "max_ids must be >= 0");
         if (a.max_ids > 0 && (st = check_dev(a.leaf_ids, n * (size_t)a.max_ids * 4, t->device, "leaf_ids")) != LQ_OK)
             return st;
@@ -377,8 +378,8 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
 
 lq_status lq_query_trace(const lq_octree *tree, const float *origins, const float *dirs, int64_t n,
                          float *rgb, float *alpha, int model, uint32_t flags, uint32_t *count,
-                         uint64_t *hash, int32_t *term_idx, uint32_t *n_comp, uint32_t *leaf_ids,
-                         int32_t max_ids, void *hip_stream) {
+                         uint64_t *hash, int32_t *term_idx, uint32_t *n_comp, uint32_t *n_steps,
+                         uint32_t *leaf_ids, int32_t max_ids, void *hip_stream) {
     QueryArgs a{};
     a.o = origins;
     a.d = dirs;
@@ -391,6 +392,7 @@ lq_status lq_query_trace(const lq_octree *tree, const float *origins, const floa
     a.hash = hash;
     a.term_idx = term_idx;
     a.n_comp = n_comp;
+    a.n_steps = n_steps;
     a.leaf_ids = leaf_ids;
     a.max_ids = max_ids;
     return query_common(tree, a, true, hip_stream);

@@ -36,6 +36,7 @@ struct QueryArgs {
     uint64_t *hash;
     int32_t *term_idx;
     uint32_t *n_comp;
+    uint32_t *n_steps;
     uint32_t *leaf_ids;
     int32_t max_ids;
 };

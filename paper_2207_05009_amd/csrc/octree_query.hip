@@ -1,479 +1,32 @@
-// octree_query.hip -- the luminaire emission query on gfx950.
+// octree_query.hip -- launch of the emission query on gfx950.
 //
-// One work-item marches one ray through the plenoctree (Sec. 5) and
-// evaluates Eq. 3 exactly over every data leaf it crosses: the leaf's
-// density and emission are constant, so the leaf contributes
-// w = T_in - T_out times Phi (Sec. 4.2, Eq. 6), with T by the linear model
-// (Sec. 4.1, Eq. 4) or Beer-Lambert, alpha = 1 - T (Eq. 5), and the sigma_min
-// skip / alpha_max stop of Sec. 6.2.
-//
-// Geometry.  The marched point is o + t d.  Every traversal decision is the
-// sign of a difference of two plane-crossing parameters
-//     t_a(P) - t_b(Q) = (P - o_a)/d_a - (Q - o_b)/d_b,
-// decided first from float32 approximations with a rigorous error bound and,
-// inside the bound, exactly: the numerator (P - o_a) d_b - (Q - o_b) d_a is
-// expanded into eight FP64 terms by error-free transformations (FP64 products
-// of float32 operands are exact) and summed as a Shewchuk expansion.  The
-// length of each leaf segment is computed from the same numerator with
-// float32 error-free transformations, so it keeps full relative precision
-// even for a leaf the ray only grazes.
-//
-// The march keeps the integer cell q (at max depth) of the point just after
-// the current event (the plane crossing, or the origin, that starts the
-// current segment).  Each step descends from the root by the bits of q,
-// takes the exit of the node found (ties between axes are exact), and
-// re-locates q on the other axes inside the node's extent.
-#include <hip/hip_fp16.h>
-
-#include <type_traits>
-
-#include "lq_internal.h"
+// One work-item per ray; the per-ray march (traversal with exact decisions,
+// float32 compositing) is march_ray() in march.h.
+#include "march.h"
 
 namespace lq {
 namespace {
 
-constexpr float kFilterRel = 0x1p-22f;   // 4 u
-constexpr float kFilterAbs = 0x1p-120f;
-constexpr uint64_t kFnvOffset = 14695981039346656037ull;
-constexpr uint64_t kFnvPrime = 1099511628211ull;
-
-// ------------------------------------------------------------ storage
-template <int S> struct Storage;
-template <> struct Storage<LQ_F32> {
-    static constexpr int bytes = 4;
-    __device__ static float get(const uint32_t *w, int j) { return __uint_as_float(w[j]); }
-};
-template <> struct Storage<LQ_F16> {
-    static constexpr int bytes = 2;
-    __device__ static float get(const uint32_t *w, int j) {
-        uint32_t v = (w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu;
-        return __half2float(__ushort_as_half((unsigned short)v));
-    }
-};
-template <> struct Storage<LQ_BF16> {
-    static constexpr int bytes = 2;
-    __device__ static float get(const uint32_t *w, int j) {
-        uint32_t v = (w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu;
-        return __uint_as_float(v << 16);
-    }
-};
-
-__host__ __device__ constexpr int row_bytes_for(int elem_bytes, int K) {
-    int need = (1 + 3 * K) * elem_bytes;
-    int rb = 64;
-    while (rb < need) rb <<= 1;
-    return rb;
-}
-
-// ------------------------------------------------------------ SH basis
-// Y_lm(x, y, z) = c_lm * poly_lm; the host computes c_lm from the
-// normalisation formula (see api.hip), the polynomials are below.
-template <int DEG>
-__device__ inline void sh_basis(float x, float y, float z, const float *c, float *Y) {
-    Y[0] = c[0];
-    if constexpr (DEG >= 1) {
-        Y[1] = c[1] * y;
-        Y[2] = c[2] * z;
-        Y[3] = c[3] * x;
-    }
-    if constexpr (DEG >= 2) {
-        float x2 = x * x, y2 = y * y, z2 = z * z;
-        Y[4] = c[4] * (x * y);
-        Y[5] = c[5] * (y * z);
-        Y[6] = c[6] * (3.0f * z2 - 1.0f);
-        Y[7] = c[7] * (x * z);
-        Y[8] = c[8] * (x2 - y2);
-        if constexpr (DEG >= 3) {
-            Y[9] = c[9] * (y * (3.0f * x2 - y2));
-            Y[10] = c[10] * (x * y * z);
-            Y[11] = c[11] * (y * (5.0f * z2 - 1.0f));
-            Y[12] = c[12] * (z * (5.0f * z2 - 3.0f));
-            Y[13] = c[13] * (x * (5.0f * z2 - 1.0f));
-            Y[14] = c[14] * (z * (x2 - y2));
-            Y[15] = c[15] * (x * (x2 - 3.0f * y2));
-        }
-        if constexpr (DEG >= 4) {
-            Y[16] = c[16] * (x * y * (x2 - y2));
-            Y[17] = c[17] * (y * z * (3.0f * x2 - y2));
-            Y[18] = c[18] * (x * y * (7.0f * z2 - 1.0f));
-            Y[19] = c[19] * (y * z * (7.0f * z2 - 3.0f));
-            Y[20] = c[20] * ((35.0f * z2 - 30.0f) * z2 + 3.0f);
-            Y[21] = c[21] * (x * z * (7.0f * z2 - 3.0f));
-            Y[22] = c[22] * ((x2 - y2) * (7.0f * z2 - 1.0f));
-            Y[23] = c[23] * (x * z * (x2 - 3.0f * y2));
-            Y[24] = c[24] * (x2 * (x2 - 3.0f * y2) - y2 * (3.0f * x2 - y2));
-        }
-    }
-}
-
-// ------------------------------------------------- exact arithmetic
-__device__ inline void two_sum(double a, double b, double &s, double &e) {
-    s = a + b;
-    double bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-__device__ inline void two_prod(double a, double b, double &p, double &e) {
-    p = a * b;
-    e = fma(a, b, -p);
-}
-__device__ inline void two_sum_f(float a, float b, float &s, float &e) {
-    s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-// exact sign of t[0] + ... + t[7] (grow-expansion, Shewchuk 1997)
-__device__ int exact_sign8(const double (&t)[8]) {
-    double e[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        double q = t[j];
-#pragma unroll
-        for (int i = 0; i < j; ++i) {
-            double s, lo;
-            two_sum(q, e[i], s, lo);
-            e[i] = lo;
-            q = s;
-        }
-        e[j] = q;
-    }
-    int sgn = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        if (e[i] != 0.0) sgn = e[i] > 0.0 ? 1 : -1;   // the last nonzero one dominates
-    return sgn;
-}
-
-struct Ray {
-    float o[3], d[3], inv[3];
-    bool filter_ok;
-};
-
-// one plane crossing (ax >= 0) or the ray origin (ax < 0, t = 0)
-struct Event {
-    int ax, k;
-    float P, t;
-};
-
-__device__ inline float sel3(const float (&v)[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
-
-__device__ inline float tapprox(const Ray &r, int a, float P) { return (P - sel3(r.o, a)) * sel3(r.inv, a); }
-
-// sign((Pa - oa)/da - (Pb - ob)/db), exact, for da, db != 0
-__device__ __noinline__ int cross_cmp_exact(float Pa, float oa, float daf, float Pb, float ob, float dbf) {
-    double A1, A0, B1, B0;
-    two_sum((double)Pa, -(double)oa, A1, A0);
-    two_sum((double)Pb, -(double)ob, B1, B0);
-    double da = daf, db = dbf;
-    double t[8];
-    two_prod(A1, db, t[0], t[1]);
-    two_prod(A0, db, t[2], t[3]);
-    two_prod(-B1, da, t[4], t[5]);
-    two_prod(-B0, da, t[6], t[7]);
-    int s = exact_sign8(t);
-    return ((da > 0.0) == (db > 0.0)) ? s : -s;
-}
-
-// sign(t_a(Pa) - t_b(Pb)); ta/tb are tapprox() of the same planes
-__device__ inline int cross_cmp(const Ray &r, int a, float Pa, float ta, int b, float Pb, float tb) {
-    if (a == b) {
-        if (Pa == Pb) return 0;
-        return ((Pa > Pb) == (sel3(r.d, a) > 0.0f)) ? 1 : -1;
-    }
-    if (r.filter_ok) {
-        float df = ta - tb;
-        float bound = fmaf(kFilterRel, fabsf(ta) + fabsf(tb), kFilterAbs);
-        if (fabsf(df) > bound) return df > 0.0f ? 1 : -1;
-    }
-    return cross_cmp_exact(Pa, sel3(r.o, a), sel3(r.d, a), Pb, sel3(r.o, b), sel3(r.d, b));
-}
-
-// sign(t_b(P) - t_event)
-__device__ inline int cmp_event(const Ray &r, int b, float P, const Event &e) {
-    if (e.ax < 0) {   // t_event = 0: the sign of t_b(P) itself
-        float ob = sel3(r.o, b);
-        if (P == ob) return 0;
-        return ((P > ob) == (sel3(r.d, b) > 0.0f)) ? 1 : -1;
-    }
-    return cross_cmp(r, b, P, tapprox(r, b, P), e.ax, e.P, e.t);
-}
-
-__device__ inline float plane_of(int k, float h) { return fmaf((float)k, h, -1.0f); }
-
-// Cell index along axis b (d_b != 0) of the point just after event e, known
-// to lie in [lo, hi).
-__device__ int locate(const Ray &r, int b, int lo, int hi, const Event &e, float h, int N) {
-    float db = sel3(r.d, b);
-    float p = fmaf(e.t, db, sel3(r.o, b));
-    float g = (p + 1.0f) * (0.5f * (float)N);
-    g = fminf(fmaxf(g, (float)lo), (float)(hi - 1));
-    int k = (int)g;
-    for (int it = 0; it <= hi - lo + 1; ++it) {
-        if (db > 0.0f) {
-            if (k > lo && cmp_event(r, b, plane_of(k, h), e) > 0) { --k; continue; }
-            if (k + 1 < hi && cmp_event(r, b, plane_of(k + 1, h), e) <= 0) { ++k; continue; }
-        } else {
-            if (k + 1 < hi && cmp_event(r, b, plane_of(k + 1, h), e) > 0) { ++k; continue; }
-            if (k > lo && cmp_event(r, b, plane_of(k, h), e) <= 0) { --k; continue; }
-        }
-        break;
-    }
-    return k;
-}
-
-// t(x) - t(e) for the exit crossing x, with full relative precision
-__device__ inline float seg_dt(const Ray &r, const Event &e, int xa, float xP, float xt) {
-    if (e.ax < 0) return xt;
-    if (e.ax == xa) return (xP - e.P) * sel3(r.inv, xa);
-    float dx = sel3(r.d, xa), de = sel3(r.d, e.ax);
-    float X1, X0, V1, V0;
-    two_sum_f(xP, -sel3(r.o, xa), X1, X0);
-    two_sum_f(e.P, -sel3(r.o, e.ax), V1, V0);
-    float p1 = X1 * de, p0 = fmaf(X1, de, -p1);
-    float q1 = V1 * dx, q0 = fmaf(V1, dx, -q1);
-    float num = (p1 - q1) + ((p0 - q0) + (X0 * de - V0 * dx));
-    return num * (sel3(r.inv, xa) * sel3(r.inv, e.ax));
-}
-
-__device__ inline uint32_t spread3(uint32_t v) {
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
-// ------------------------------------------------------------ kernel
 template <int ST, int DEG, bool ACC64, bool TRACE>
 __global__ __launch_bounds__(256) void k_query(const DevTree t, const QueryArgs a) {
-    using S = Storage<ST>;
-    using Acc = typename std::conditional<ACC64, double, float>::type;
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int RB = row_bytes_for(S::bytes, K);
-    constexpr int NE = 1 + 3 * K;
-    constexpr int NCH = (NE * S::bytes + 15) / 16;   // 16-byte chunks holding the row
-
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-
-    Ray r;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        r.o[ax] = a.o[3 * i + ax];
-        r.d[ax] = a.d[3 * i + ax];
-    }
-    Acc L0 = 0, L1 = 0, L2 = 0, T = 1;
-    uint32_t count = 0, ncomp = 0;
-    int32_t term = -1;
-    uint64_t hash = kFnvOffset;
-
-    const int D = t.depth;
-    const int N = 1 << D;
-    const float h = 2.0f / (float)N;
-    const bool no_stop = (a.flags & LQ_NO_EARLY_TERM) != 0;
-    const bool no_skip = (a.flags & LQ_NO_SIGMA_SKIP) != 0;
-
-    bool ok = true;
-    bool anyd = false;
-    r.filter_ok = true;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        ok = ok && isfinite(r.o[ax]) && isfinite(r.d[ax]);
-        anyd = anyd || r.d[ax] != 0.0f;
-        float ad = fabsf(r.d[ax]);
-        r.filter_ok = r.filter_ok && fabsf(r.o[ax]) <= 0x1p60f &&
-                      (ad == 0.0f || (ad >= 0x1p-60f && ad <= 0x1p60f));
-        r.inv[ax] = r.d[ax] != 0.0f ? 1.0f / r.d[ax] : 0.0f;
-    }
-    float dlen = sqrtf(r.d[0] * r.d[0] + r.d[1] * r.d[1] + r.d[2] * r.d[2]);
-    ok = ok && anyd && dlen > 0.0f && isfinite(dlen);
-
-    // ---- clip to the proxy box [-1, 1)^3
-    Event ev{-1, 0, 0.0f, 0.0f};
-    int q[3] = {0, 0, 0};
-    if (ok) {
-        int in_ax = -1;
-        float in_P = 0.0f, in_t = 0.0f;
-        bool origin_start = true;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            float dx = r.d[ax], ox = r.o[ax];
-            if (dx == 0.0f) {
-                ok = ok && (ox >= -1.0f && ox < 1.0f);
-                continue;
-            }
-            float Pn = dx > 0.0f ? -1.0f : 1.0f;
-            // far plane not reached after t = 0?  (origin beyond the box)
-            ok = ok && (dx > 0.0f ? ox < 1.0f : ox > -1.0f);
-            origin_start = origin_start && (dx > 0.0f ? ox >= -1.0f : ox <= 1.0f);
-            float tn = tapprox(r, ax, Pn);
-            if (in_ax < 0 || cross_cmp(r, ax, Pn, tn, in_ax, in_P, in_t) > 0) {
-                in_ax = ax;
-                in_P = Pn;
-                in_t = tn;
-            }
-        }
-        if (ok && !origin_start) {
-            ev = Event{in_ax, r.d[in_ax] > 0.0f ? 0 : N, in_P, in_t};
-            // the far plane of every axis must come strictly after the entry
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                if (r.d[ax] == 0.0f || ax == in_ax) continue;
-                float Pf = r.d[ax] > 0.0f ? 1.0f : -1.0f;
-                ok = ok && cmp_event(r, ax, Pf, ev) > 0;
-            }
-        }
-        if (ok) {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                float dx = r.d[ax], ox = r.o[ax];
-                if (dx == 0.0f || ev.ax < 0) {
-                    // cell of the origin coordinate (half-open cells; moving
-                    // down off a plane puts the point in the lower cell)
-                    float g = fminf(fmaxf((ox + 1.0f) * (0.5f * (float)N), 0.0f), (float)(N - 1));
-                    int k = (int)g;
-                    while (k > 0 && plane_of(k, h) > ox) --k;
-                    while (k + 1 < N && plane_of(k + 1, h) <= ox) ++k;
-                    if (dx < 0.0f && plane_of(k, h) == ox && k > 0) --k;
-                    q[ax] = k;
-                } else if (ax == ev.ax) {
-                    q[ax] = dx > 0.0f ? 0 : N - 1;
-                } else {
-                    q[ax] = locate(r, ax, 0, N, ev, h, N);
-                }
-            }
-        }
-    }
-
-    // ---- emission direction omega = -d/|d| and its SH values
-    float Y[K];
-    {
-        float inv_len = 1.0f / dlen;
-        sh_basis<DEG>(-r.d[0] * inv_len, -r.d[1] * inv_len, -r.d[2] * inv_len, t.ycoef, Y);
-    }
-
-    // ---- march
-    const int max_steps = 3 * N + 8;
-    for (int step = 0; ok && step < max_steps; ++step) {
-        int node = 0, level = 0, c = 0;
-        for (;;) {
-            int sh = D - 1 - level;
-            int oct = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
-            c = t.child[(size_t)node * 8 + oct];
-            ++level;
-            if (c <= 0 || level >= D) break;
-            node = c;
-        }
-        if (c > 0) c = 0;   // malformed table guard: never descend below max depth
-        const int sshift = D - level;
-        const int S = 1 << sshift;
-        int lo[3];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) lo[ax] = (q[ax] >> sshift) << sshift;
-
-        // exit crossing of the node (exact; ties collected in xmask)
-        int xa = -1, xk = 0;
-        float xP = 0.0f, xt = 0.0f;
-        unsigned xmask = 0;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            float dx = r.d[ax];
-            if (dx == 0.0f) continue;
-            int k = dx > 0.0f ? lo[ax] + S : lo[ax];
-            float P = plane_of(k, h);
-            float tt = tapprox(r, ax, P);
-            int cmpv = xa < 0 ? -1 : cross_cmp(r, ax, P, tt, xa, xP, xt);
-            if (cmpv < 0) {
-                xa = ax; xk = k; xP = P; xt = tt;
-                xmask = 1u << ax;
-            } else if (cmpv == 0) {
-                xmask |= 1u << ax;
-            }
-        }
-
-        if (c < 0) {
-            const int leaf = -c - 1;
-            if (TRACE) {
-                uint32_t id = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
-                if ((int32_t)count < a.max_ids) a.leaf_ids[(size_t)i * a.max_ids + count] = id;
-                hash = (hash ^ (uint64_t)id) * kFnvPrime;
-            }
-            ++count;
-            const uint4 *rowp = reinterpret_cast<const uint4 *>(
-                static_cast<const char *>(t.rows) + (size_t)leaf * RB);
-            uint32_t w[NCH * 4];
-            {
-                uint4 c0 = rowp[0];
-                w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
-            }
-            const float sig = S::get(w, 0);
-            if (no_skip || sig >= t.sigma_min) {
-#pragma unroll
-                for (int ch = 1; ch < NCH; ++ch) {
-                    uint4 cc = rowp[ch];
-                    w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
-                }
-                float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    x0 = fmaf(S::get(w, 1 + k), Y[k], x0);
-                    x1 = fmaf(S::get(w, 1 + K + k), Y[k], x1);
-                    x2 = fmaf(S::get(w, 1 + 2 * K + k), Y[k], x2);
-                }
-                const float phi0 = t.l_max / (1.0f + expf(-x0));
-                const float phi1 = t.l_max / (1.0f + expf(-x1));
-                const float phi2 = t.l_max / (1.0f + expf(-x2));
-                const float dt = fmaxf(seg_dt(r, ev, xa, xP, xt), 0.0f);
-                const Acc delta = (Acc)dt * (Acc)dlen;
-                const Acc sd = (Acc)sig * delta;
-                Acc wgt;
-                if (a.model == LQ_EXP) wgt = -T * expm1(-sd);
-                else wgt = sd < T ? sd : T;
-                L0 += wgt * (Acc)phi0;
-                L1 += wgt * (Acc)phi1;
-                L2 += wgt * (Acc)phi2;
-                T -= wgt;
-                ++ncomp;
-                if (!no_stop && (Acc(1) - T) >= (Acc)t.alpha_max) {
-                    term = (int32_t)count - 1;
-                    break;
-                }
-            }
-        }
-
-        // step to the neighbouring node
-        bool out = false;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (!(xmask & (1u << ax))) continue;
-            int nq = r.d[ax] > 0.0f ? lo[ax] + S : lo[ax] - 1;
-            out = out || nq < 0 || nq >= N;
-            q[ax] = nq;
-        }
-        if (out) break;
-        const Event nev{xa, xk, xP, xt};
-        if (S > 1) {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                if ((xmask & (1u << ax)) || r.d[ax] == 0.0f) continue;
-                q[ax] = locate(r, ax, lo[ax], lo[ax] + S, nev, h, N);
-            }
-        }
-        ev = nev;
-    }
-
+    RayOut r;
+    uint32_t *ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)i * a.max_ids : nullptr;
+    march_ray<ST, DEG, ACC64, TRACE>(t, a.o + 3 * i, a.d + 3 * i, a.model, a.flags, r, ids,
+                                     TRACE ? a.max_ids : 0);
     if (a.rgb) {
-        a.rgb[3 * i] = (float)L0;
-        a.rgb[3 * i + 1] = (float)L1;
-        a.rgb[3 * i + 2] = (float)L2;
+        a.rgb[3 * i] = r.rgb[0];
+        a.rgb[3 * i + 1] = r.rgb[1];
+        a.rgb[3 * i + 2] = r.rgb[2];
     }
-    if (a.alpha) a.alpha[i] = (float)(Acc(1) - T);
+    if (a.alpha) a.alpha[i] = r.alpha;
     if (TRACE) {
-        a.count[i] = count;
-        a.hash[i] = hash;
-        a.term_idx[i] = term;
-        a.n_comp[i] = ncomp;
+        a.count[i] = r.count;
+        a.hash[i] = r.hash;
+        a.term_idx[i] = r.term_idx;
+        a.n_comp[i] = r.n_comp;
+        if (a.n_steps) a.n_steps[i] = r.n_steps;
     }
 }
 

@@ -61,7 +61,7 @@ def lib():
             L.lq_octree_info.argtypes = [vp] + [C.c_void_p] * 6
             L.lq_query_radiance.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32, vp]
             L.lq_query_trace.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32,
-                                         vp, vp, vp, vp, vp, i32, vp]
+                                         vp, vp, vp, vp, vp, vp, i32, vp]
             for name in ("lq_load_octree_desc", "lq_load_octree", "lq_octree_info",
                          "lq_query_radiance", "lq_query_trace"):
                 getattr(L, name).restype = C.c_int
@@ -153,12 +153,13 @@ class Octree:
             "hash": torch.empty((n,), dtype=torch.int64, device=dev),
             "term_idx": torch.empty((n,), dtype=torch.int32, device=dev),
             "n_comp": torch.empty((n,), dtype=torch.int32, device=dev),
+            "n_steps": torch.empty((n,), dtype=torch.int32, device=dev),
         }
         ids = torch.zeros((n, max_ids), dtype=torch.int32, device=dev) if max_ids > 0 else None
         check(lib().lq_query_trace(self.handle, _ptr(origins), _ptr(dirs), n, _ptr(out["rgb"]),
                                    _ptr(out["alpha"]), MODEL[model], flags, _ptr(out["count"]),
                                    _ptr(out["hash"]), _ptr(out["term_idx"]), _ptr(out["n_comp"]),
-                                   _ptr(ids), max_ids, _stream(stream)))
+                                   _ptr(out["n_steps"]), _ptr(ids), max_ids, _stream(stream)))
         if ids is not None:
             out["leaf_ids"] = ids
         return out

@@ -30,7 +30,7 @@ def pytest_collection_modifyitems(config, items):
 def _tree(name):
     import inputs
     spec = {"c0": inputs.C0_TREE, "c1": inputs.C1_TREE}[name]
-    return inputs.make_tree(spec)
+    return inputs.cached_tree(spec)
 
 
 @pytest.fixture(scope="session")

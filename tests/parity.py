@@ -46,10 +46,14 @@ def compare(gpu: dict, orc: dict, l_max: float, rtol: float = RTOL, ids: bool = 
         mask = np.arange(m)[None, :] < cnt[:, None]
         same = (gpu["leaf_ids"][:, :m].astype(np.uint32) == orc["leaf_ids"][:, :m]) | ~mask
         id_ok = same.all(1) | use_alt
-    bad = ~seq_ok | ~id_ok | (err.max(1) > rtol) | (aerr > rtol)
+    steps_ok = np.ones(n, bool)
+    if "n_steps" in gpu:
+        steps_ok = (gpu["n_steps"].astype(np.int64) == orc["n_nodes"]) | use_alt
+    bad = ~seq_ok | ~id_ok | ~steps_ok | (err.max(1) > rtol) | (aerr > rtol)
     return {
         "n": n, "ok": not bad.any(), "n_bad": int(bad.sum()), "bad_idx": np.nonzero(bad)[0][:20],
         "n_seq_mismatch": int((~seq_ok).sum()), "n_id_mismatch": int((~id_ok).sum()),
+        "n_steps_mismatch": int((~steps_ok).sum()),
         "n_alt": int(use_alt.sum()), "n_ambiguous": int(orc["alt_valid"].sum()),
         "max_rel": float(err.max()) if n else 0.0,
         "p99_rel": float(np.quantile(err.max(1), 0.99)) if n else 0.0,

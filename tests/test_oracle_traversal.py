@@ -140,3 +140,14 @@ def test_sliding_origin_along_ray(c0_tree):
     b = core.query(c0_tree, o2[out], d[out])
     assert np.array_equal(a["hash"], b["hash"])
     np.testing.assert_allclose(a["L"], b["L"], rtol=1e-11, atol=1e-12)
+
+
+def test_exact_path_records_match_fp64_path(c0_tree):
+    o, d = inputs.rays.sphere_to_cube(400, 37)
+    for model in (core.LINEAR, core.EXP):
+        a = core.query(c0_tree, o, d, model=model, max_ids=160)
+        b = core.query(c0_tree, o, d, model=model, max_ids=160, force_exact=True)
+        assert a["n_exact"] == 0
+        for key in ("count", "hash", "term_idx", "n_comp", "n_nodes", "leaf_ids"):
+            assert np.array_equal(a[key], b[key]), key
+        np.testing.assert_allclose(a["L"], b["L"], rtol=1e-8, atol=1e-300)
