@@ -29,16 +29,20 @@ sys.path.insert(0, ROOT)
 METRIC = "rays/s: octree radiance query FP32 vs FP16 vs MLP surrogate at ≤1% rel err"
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_05009_amd", "csrc", "octree_query.hip")
+CSRC = os.path.join(ROOT, "paper_2207_05009_amd", "csrc")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def src_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+def kernel_sources_hash():
+    """Hash of the sources the query kernel is built from."""
+    h = hashlib.sha1()
+    for name in ("octree_query.hip", "march.h", "lq_internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
 
 
 def time_launches(fn, steps, warmup):
@@ -71,17 +75,21 @@ def alg_bytes(trace, K, elem_bytes):
 
 
 def traffic_from_profiles(kernel_tag):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source (else None)."""
-    p = os.path.join(PROFILE_DIR, f"traffic_{kernel_tag}.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (lines "key: value"), if it was taken on the current kernel sources
+    (else None)."""
+    p = os.path.join(PROFILE_DIR, f"traffic_{kernel_tag}.txt")
     if not os.path.exists(p):
         return None
     try:
-        with open(p) as f:
-            t = json.load(f)
-        if t.get("kernel_src_sha1") != src_hash(KERNEL_SRC):
+        kv = {}
+        for line in open(p):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_src_sha1") != kernel_sources_hash():
             return None
-        return float(t["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"])
     except Exception:
         return None
 
@@ -116,6 +124,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the query shards by rays with no exchange, and this "
@@ -152,6 +162,15 @@ def main():
     value = n / (ms * 1e-3)
     log(f"f32 linear: {ms:.3f} ms/step, {value / 1e6:.1f} Mrays/s (wall {wall:.3f} s)")
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written")
+        del src, dst
+
     tr = oct32.trace(o, d, model="linear")
     torch.cuda.synchronize()
     nbytes, counts = alg_bytes(tr, tree.K, 4)
@@ -160,7 +179,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": nbytes, "per_ray": counts,
-                "kernel": "k_query<F32, SH deg 2, FP32 accumulation>"}
+                "kernel": "k_query<F32, SH deg 2, FP32 accumulation>",
+                "kernel_sources": kernel_sources_hash()}
 
     variants = {}
     if not args.no_variants:

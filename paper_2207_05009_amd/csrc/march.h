@@ -20,9 +20,10 @@
 //
 // The march keeps the integer cell q (at max depth) of the point just after
 // the current event (the plane crossing, or the origin, that starts the
-// current segment).  Each step descends from the root by the bits of q,
-// takes the exit of the node found (ties between axes are exact), and
-// re-locates q on the other axes inside the node's extent.
+// current segment).  Each step descends by the bits of q -- from the
+// deepest common ancestor of the previous and the new cell, whose path is
+// kept per lane -- takes the exit of the node found (ties between axes are
+// exact), and re-locates q on the other axes inside the node's extent.
 //
 // Everything here is __host__ __device__ so that the same code can be
 // compiled for the host when debugging the traversal.
@@ -259,10 +260,14 @@ struct RayOut {
 };
 
 // The whole query for one ray.  ids (may be null) receives up to max_ids
-// Morton ids of the data leaves in order.
+// Morton ids of the data leaves in order.  path[l * path_stride] (l < depth)
+// is scratch for the node indices along the current root-to-node path, so
+// that each step re-descends only from the deepest common ancestor of the
+// old and new cells.
 template <int ST, int DEG, bool ACC64, bool TRACE>
 LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, int model,
-                            uint32_t flags, RayOut &out, uint32_t *ids, int32_t max_ids) {
+                            uint32_t flags, RayOut &out, uint32_t *ids, int32_t max_ids,
+                            int32_t *path, int path_stride) {
     using S = Storage<ST>;
     using Acc = typename std::conditional<ACC64, double, float>::type;
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -371,9 +376,22 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
 
     // ---- march
     const int max_steps = 3 * N + 8;
+    int pq[3] = {0, 0, 0};   // cell at the previous descent
+    int path_top = -1;       // deepest level with a valid path[] entry
     for (int step = 0; ok && step < max_steps; ++step) {
         int node = 0, level = 0, c = 0;
+        if (path_top >= 0) {
+            // the old and new cells share the path down to the level above
+            // their highest differing coordinate bit
+            uint32_t diff = (uint32_t)((q[0] ^ pq[0]) | (q[1] ^ pq[1]) | (q[2] ^ pq[2]));
+            int hb = 31 - __builtin_clz(diff | 1u);
+            level = D - 1 - hb;
+            if (level > path_top) level = path_top;
+            if (level < 0) level = 0;
+            node = path[level * path_stride];
+        }
         for (;;) {
+            path[level * path_stride] = node;
             int sh = D - 1 - level;
             int oct = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
             c = t.child[(size_t)node * 8 + oct];
@@ -382,6 +400,8 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
             node = c;
         }
         if (c > 0) c = 0;   // malformed table guard: never descend below max depth
+        path_top = level - 1;
+        pq[0] = q[0]; pq[1] = q[1]; pq[2] = q[2];
         ++nsteps;
         const int sshift = D - level;
         const int S = 1 << sshift;

@@ -9,12 +9,13 @@ namespace {
 
 template <int ST, int DEG, bool ACC64, bool TRACE>
 __global__ __launch_bounds__(256) void k_query(const DevTree t, const QueryArgs a) {
+    __shared__ int32_t s_path[10 * 256];   // per-lane node path, [level][lane]
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     RayOut r;
     uint32_t *ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)i * a.max_ids : nullptr;
     march_ray<ST, DEG, ACC64, TRACE>(t, a.o + 3 * i, a.d + 3 * i, a.model, a.flags, r, ids,
-                                     TRACE ? a.max_ids : 0);
+                                     TRACE ? a.max_ids : 0, s_path + threadIdx.x, 256);
     if (a.rgb) {
         a.rgb[3 * i] = r.rgb[0];
         a.rgb[3 * i + 1] = r.rgb[1];
