@@ -14,6 +14,7 @@ struct lq_octree {
     int device;
     lq::DevTree t;
     int32_t *d_child;
+    int32_t *d_child_skip;
     void *d_rows;
     int64_t bytes;
 };
@@ -97,7 +98,8 @@ static void sh_constants(float *c) {
 }
 
 // ------------------------------------------------------------ validation
-static lq_status validate_desc(const lq_octree_desc *d) {
+// On success, *bfs (if given) receives the nodes in breadth-first order.
+static lq_status validate_desc(const lq_octree_desc *d, std::vector<int32_t> *bfs = nullptr) {
     if (!d) return fail(LQ_ERR_INVALID_ARG, "descriptor is NULL");
     if (d->max_depth < 1 || d->max_depth > 10) return fail(LQ_ERR_FORMAT, "max_depth must be in [1, 10]");
     if (d->sh_degree < 0 || d->sh_degree > 4) return fail(LQ_ERR_FORMAT, "sh_degree must be in [0, 4]");
@@ -115,6 +117,7 @@ static lq_status validate_desc(const lq_octree_desc *d) {
     std::vector<int32_t> cur{0}, nxt;
     seen_node[0] = 1;
     int64_t nodes_reached = 1;
+    if (bfs) bfs->assign(1, 0);
     for (int level = 0; level < D && !cur.empty(); ++level) {
         nxt.clear();
         for (int32_t node : cur) {
@@ -135,10 +138,45 @@ static lq_status validate_desc(const lq_octree_desc *d) {
                 }
             }
         }
+        if (bfs) bfs->insert(bfs->end(), nxt.begin(), nxt.end());
         cur.swap(nxt);
     }
     if (nodes_reached != d->n_nodes) return fail(LQ_ERR_FORMAT, "unreachable nodes in the child table");
     return LQ_OK;
+}
+
+// Child table without the leaves for which keep_leaf() is false and without
+// the nodes that are left empty; the root stays node 0, order breadth-first.
+template <class Keep>
+static std::vector<int32_t> prune_tree(const lq_octree_desc *d, const std::vector<int32_t> &bfs,
+                                       Keep keep_leaf) {
+    const size_t nn = (size_t)d->n_nodes;
+    std::vector<uint8_t> alive(nn, 0);
+    for (size_t j = bfs.size(); j-- > 0;) {          // children before parents
+        const int32_t node = bfs[j];
+        uint8_t any = 0;
+        for (int oct = 0; oct < 8; ++oct) {
+            const int32_t c = d->child[(size_t)node * 8 + oct];
+            if (c > 0) any |= alive[c];
+            else if (c < 0) any |= keep_leaf(-(int64_t)c - 1) ? 1 : 0;
+        }
+        alive[node] = any;
+    }
+    std::vector<int32_t> new_index(nn, 0);
+    int32_t next = 0;
+    for (int32_t node : bfs)
+        if (node == 0 || alive[node]) new_index[node] = next++;
+    std::vector<int32_t> out((size_t)next * 8, 0);
+    for (int32_t node : bfs) {
+        if (node != 0 && !alive[node]) continue;
+        int32_t *row = out.data() + (size_t)new_index[node] * 8;
+        for (int oct = 0; oct < 8; ++oct) {
+            const int32_t c = d->child[(size_t)node * 8 + oct];
+            if (c > 0 && alive[c]) row[oct] = new_index[c];
+            else if (c < 0 && keep_leaf(-(int64_t)c - 1)) row[oct] = c;
+        }
+    }
+    return out;
 }
 
 }  // namespace lq
@@ -155,7 +193,8 @@ lq_status lq_load_octree_desc(const lq_octree_desc *desc, int storage, int devic
     *out = nullptr;
     if (storage != LQ_F32 && storage != LQ_F16 && storage != LQ_BF16)
         return fail(LQ_ERR_INVALID_ARG, "storage must be LQ_F32, LQ_F16 or LQ_BF16");
-    lq_status st = validate_desc(desc);
+    std::vector<int32_t> bfs;
+    lq_status st = validate_desc(desc, &bfs);
     if (st != LQ_OK) return st;
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -183,33 +222,55 @@ lq_status lq_load_octree_desc(const lq_octree_desc *desc, int storage, int devic
             }
         }
     }
+    // density as stored (after rounding), compared like the kernel does
+    auto stored_sigma = [&](int64_t leaf) -> float {
+        if (storage == LQ_F32) return desc->sigma[leaf];
+        uint16_t b;
+        memcpy(&b, rows.data() + (size_t)leaf * rb, 2);
+        if (storage == LQ_BF16) {
+            uint32_t u = (uint32_t)b << 16;
+            float f;
+            memcpy(&f, &u, 4);
+            return f;
+        }
+        return (float)__builtin_bit_cast(_Float16, b);
+    };
+    const float smin = desc->sigma_min;
+    std::vector<int32_t> skip = prune_tree(desc, bfs, [&](int64_t leaf) { return stored_sigma(leaf) >= smin; });
+
     lq_octree *t = new (std::nothrow) lq_octree();
     if (!t) return fail(LQ_ERR_OOM, "host allocation failed");
     t->device = device;
     const size_t child_bytes = (size_t)desc->n_nodes * 32;
+    const size_t skip_bytes = skip.size() * 4;
     const size_t row_total = rows.size() ? rows.size() : 64;
-    if ((e = hipMalloc((void **)&t->d_child, child_bytes)) != hipSuccess) {
-        delete t;
+    t->d_child = nullptr;
+    t->d_child_skip = nullptr;
+    t->d_rows = nullptr;
+    if (hipMalloc((void **)&t->d_child, child_bytes) != hipSuccess ||
+        hipMalloc((void **)&t->d_child_skip, skip_bytes) != hipSuccess ||
+        hipMalloc(&t->d_rows, row_total) != hipSuccess) {
         (void)hipGetLastError();
-        return fail(LQ_ERR_OOM, "device allocation of the node table failed");
-    }
-    if ((e = hipMalloc(&t->d_rows, row_total)) != hipSuccess) {
         (void)hipFree(t->d_child);
+        (void)hipFree(t->d_child_skip);
+        (void)hipFree(t->d_rows);
         delete t;
-        (void)hipGetLastError();
-        return fail(LQ_ERR_OOM, "device allocation of the leaf table failed");
+        return fail(LQ_ERR_OOM, "device allocation of the tree tables failed");
     }
     e = hipMemcpy(t->d_child, desc->child, child_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t->d_child_skip, skip.data(), skip_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess && rows.size()) e = hipMemcpy(t->d_rows, rows.data(), rows.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(t->d_child);
+        (void)hipFree(t->d_child_skip);
         (void)hipFree(t->d_rows);
         delete t;
         return hip_fail(e, "uploading the tree");
     }
-    t->bytes = (int64_t)(child_bytes + row_total);
+    t->bytes = (int64_t)(child_bytes + skip_bytes + row_total);
     DevTree &dt = t->t;
     dt.child = t->d_child;
+    dt.child_skip = t->d_child_skip;
     dt.rows = t->d_rows;
     dt.depth = desc->max_depth;
     dt.sh_degree = desc->sh_degree;
@@ -280,6 +341,7 @@ void lq_free_octree(lq_octree *t) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
     (void)hipFree(t->d_child);
+    (void)hipFree(t->d_child_skip);
     (void)hipFree(t->d_rows);
     (void)hipSetDevice(cur);
     delete t;

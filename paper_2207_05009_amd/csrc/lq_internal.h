@@ -12,12 +12,18 @@ namespace lq {
 
 // Device image of a plenoctree.
 //  child: [n_nodes][8] int32 (the descriptor's table, unchanged).
+//  child_skip: the same tree with every data leaf whose stored density is
+//         below sigma_min removed, and every node left without children
+//         removed in turn (leaf indices unchanged).  The plain query marches
+//         it: those leaves are never composited (Sec. 6.2, sigma_min), so it
+//         visits the composited leaves with the same segments in fewer steps.
 //  rows:  [n_leaves][row_elems] in the storage type: sigma, then the SH
 //         coefficients of R, G, B (K each), zero padded so that a row is a
 //         power-of-two number of bytes >= 64 (one row never straddles a
 //         128-byte line when it is <= 128 bytes).
 struct DevTree {
     const int32_t *child;
+    const int32_t *child_skip;
     const void *rows;
     int32_t depth, sh_degree, K, storage;
     int32_t n_nodes, n_leaves, row_elems, pad;

@@ -252,6 +252,24 @@ LQ_HD inline uint32_t spread3(uint32_t v) {
     return v;
 }
 
+// float32 helpers for the emission activation: hardware exp2 and reciprocal
+// on the device (relative error ~1e-6 over the logit range of the tables),
+// libm on the host build
+LQ_HD inline float lq_exp_neg(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_exp2f(x * -1.4426950408889634f);
+#else
+    return expf(-x);
+#endif
+}
+LQ_HD inline float lq_rcp(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 struct RayOut {
     float rgb[3], alpha;
     uint32_t count, n_comp, n_steps;
@@ -259,58 +277,74 @@ struct RayOut {
     uint64_t hash;
 };
 
-// The whole query for one ray.  ids (may be null) receives up to max_ids
-// Morton ids of the data leaves in order.  path[l * path_stride] (l < depth)
-// is scratch for the node indices along the current root-to-node path, so
-// that each step re-descends only from the deepest common ancestor of the
-// old and new cells.
-template <int ST, int DEG, bool ACC64, bool TRACE>
-LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, int model,
-                            uint32_t flags, RayOut &out, uint32_t *ids, int32_t max_ids,
-                            int32_t *path, int path_stride) {
+// The query for one ray as a resumable state machine: init() clips the ray
+// and locates its first cell, step() visits one octree node (leaf or empty),
+// result() reads the outputs.  ids (may be null) receives up to max_ids
+// Morton ids of the data leaves in order; path[l * path_stride] (l < depth)
+// holds the node indices along the current root-to-node path, so that each
+// step re-descends only from the deepest common ancestor of the previous and
+// the new cell.  With SKIP the march uses the child table without the
+// leaves below sigma_min (DevTree::child_skip): every leaf it meets is
+// composited, so its whole row is fetched at once.
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP = false>
+struct Marcher {
     using S = Storage<ST>;
     using Acc = typename std::conditional<ACC64, double, float>::type;
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int RB = row_bytes_for(S::bytes, K);
-    constexpr int NE = 1 + 3 * K;
-    constexpr int NCH = (NE * S::bytes + 15) / 16;   // 16-byte chunks holding the row
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    static constexpr int RB = row_bytes_for(S::bytes, K);
+    static constexpr int NE = 1 + 3 * K;
+    static constexpr int NCH = (NE * S::bytes + 15) / 16;   // 16-byte chunks holding the row
 
     Ray r;
+    float dlen;
+    float Y[K];
+    Event ev;
+    int q[3], pq[3];
+    int path_top, steps_left;
+    Acc L0, L1, L2, T;
+    uint32_t count, ncomp, nsteps;
+    int32_t term;
+    uint64_t hash;
+
+    // returns true when the ray has nodes to visit
+    LQ_HD bool init(const DevTree &t, const float *o3, const float *d3) {
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        r.o[ax] = o3[ax];
-        r.d[ax] = d3[ax];
-    }
-    Acc L0 = 0, L1 = 0, L2 = 0, T = 1;
-    uint32_t count = 0, ncomp = 0, nsteps = 0;
-    int32_t term = -1;
-    uint64_t hash = kFnvOffset;
+        for (int ax = 0; ax < 3; ++ax) {
+            r.o[ax] = o3[ax];
+            r.d[ax] = d3[ax];
+        }
+        L0 = L1 = L2 = 0;
+        T = 1;
+        count = ncomp = nsteps = 0;
+        term = -1;
+        hash = kFnvOffset;
+        path_top = -1;
+        q[0] = q[1] = q[2] = 0;
+        pq[0] = pq[1] = pq[2] = 0;
+        ev = Event{-1, 0.0f, 0.0f};
 
-    const int D = t.depth;
-    const int N = 1 << D;
-    const float h = 2.0f / (float)N;
-    const bool no_stop = (flags & LQ_NO_EARLY_TERM) != 0;
-    const bool no_skip = (flags & LQ_NO_SIGMA_SKIP) != 0;
+        const int D = t.depth;
+        const int N = 1 << D;
+        const float h = 2.0f / (float)N;
+        steps_left = 3 * N + 8;
 
-    bool ok = true;
-    bool anyd = false;
-    r.filter_ok = true;
+        bool ok = true;
+        bool anyd = false;
+        r.filter_ok = true;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        ok = ok && isfinite(r.o[ax]) && isfinite(r.d[ax]);
-        anyd = anyd || r.d[ax] != 0.0f;
-        float ad = fabsf(r.d[ax]);
-        r.filter_ok = r.filter_ok && fabsf(r.o[ax]) <= 0x1p60f &&
-                      (ad == 0.0f || (ad >= 0x1p-60f && ad <= 0x1p60f));
-        r.inv[ax] = r.d[ax] != 0.0f ? 1.0f / r.d[ax] : 0.0f;
-    }
-    float dlen = sqrtf(r.d[0] * r.d[0] + r.d[1] * r.d[1] + r.d[2] * r.d[2]);
-    ok = ok && anyd && dlen > 0.0f && isfinite(dlen);
+        for (int ax = 0; ax < 3; ++ax) {
+            ok = ok && isfinite(r.o[ax]) && isfinite(r.d[ax]);
+            anyd = anyd || r.d[ax] != 0.0f;
+            float ad = fabsf(r.d[ax]);
+            r.filter_ok = r.filter_ok && fabsf(r.o[ax]) <= 0x1p60f &&
+                          (ad == 0.0f || (ad >= 0x1p-60f && ad <= 0x1p60f));
+            r.inv[ax] = r.d[ax] != 0.0f ? 1.0f / r.d[ax] : 0.0f;
+        }
+        dlen = sqrtf(r.d[0] * r.d[0] + r.d[1] * r.d[1] + r.d[2] * r.d[2]);
+        ok = ok && anyd && dlen > 0.0f && isfinite(dlen);
+        if (!ok) return false;
 
-    // ---- clip to the proxy box [-1, 1)^3
-    Event ev{-1, 0.0f, 0.0f};
-    int q[3] = {0, 0, 0};
-    if (ok) {
+        // ---- clip to the proxy box [-1, 1)^3
         int in_ax = -1;
         float in_P = 0.0f, in_t = 0.0f;
         bool origin_start = true;
@@ -342,43 +376,44 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
                 ok = ok && cmp_event(r, ax, Pf, ev) > 0;
             }
         }
-        if (ok) {
+        if (!ok) return false;
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                float dx = r.d[ax], ox = r.o[ax];
-                if (dx == 0.0f || ev.ax < 0) {
-                    // cell of the origin coordinate (half-open cells; moving
-                    // down off a plane puts the point in the lower cell)
-                    float g = fminf(fmaxf((ox + 1.0f) * (0.5f * (float)N), 0.0f), (float)(N - 1));
-                    int k = (int)g;
-                    while (k > 0 && plane_of(k, h) > ox) --k;
-                    while (k + 1 < N && plane_of(k + 1, h) <= ox) ++k;
-                    if (dx < 0.0f && plane_of(k, h) == ox && k > 0) --k;
-                    q[ax] = k;
-                } else if (ax == ev.ax) {
-                    q[ax] = dx > 0.0f ? 0 : N - 1;
-                } else {
-                    q[ax] = locate(r, ax, 0, N, ev, h, N);
-                }
+        for (int ax = 0; ax < 3; ++ax) {
+            float dx = r.d[ax], ox = r.o[ax];
+            if (dx == 0.0f || ev.ax < 0) {
+                // cell of the origin coordinate (half-open cells; moving
+                // down off a plane puts the point in the lower cell)
+                float g = fminf(fmaxf((ox + 1.0f) * (0.5f * (float)N), 0.0f), (float)(N - 1));
+                int k = (int)g;
+                while (k > 0 && plane_of(k, h) > ox) --k;
+                while (k + 1 < N && plane_of(k + 1, h) <= ox) ++k;
+                if (dx < 0.0f && plane_of(k, h) == ox && k > 0) --k;
+                q[ax] = k;
+            } else if (ax == ev.ax) {
+                q[ax] = dx > 0.0f ? 0 : N - 1;
+            } else {
+                q[ax] = locate(r, ax, 0, N, ev, h, N);
             }
         }
-    }
 
-    // ---- emission direction omega = -d/|d| and its SH values
-    float Y[K];
-    {
+        // ---- emission direction omega = -d/|d| and its SH values
         float c[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) c[k] = t.ycoef[k];
         float inv_len = 1.0f / dlen;
         sh_basis<DEG>(-r.d[0] * inv_len, -r.d[1] * inv_len, -r.d[2] * inv_len, c, Y);
+        return true;
     }
 
-    // ---- march
-    const int max_steps = 3 * N + 8;
-    int pq[3] = {0, 0, 0};   // cell at the previous descent
-    int path_top = -1;       // deepest level with a valid path[] entry
-    for (int step = 0; ok && step < max_steps; ++step) {
+    // Visit one node; returns true when the march is over.
+    LQ_HD bool step(const DevTree &t, int model, uint32_t flags, uint32_t *ids, int32_t max_ids,
+                    int32_t *path, int path_stride) {
+        const int D = t.depth;
+        const int N = 1 << D;
+        const float h = 2.0f / (float)N;
+        const int32_t *child = SKIP ? t.child_skip : t.child;
+        if (--steps_left < 0) return true;
+
         int node = 0, level = 0, c = 0;
         if (path_top >= 0) {
             // the old and new cells share the path down to the level above
@@ -394,7 +429,7 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
             path[level * path_stride] = node;
             int sh = D - 1 - level;
             int oct = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
-            c = t.child[(size_t)node * 8 + oct];
+            c = child[(size_t)node * 8 + oct];
             ++level;
             if (c <= 0 || level >= D) break;
             node = c;
@@ -404,7 +439,7 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
         pq[0] = q[0]; pq[1] = q[1]; pq[2] = q[2];
         ++nsteps;
         const int sshift = D - level;
-        const int S = 1 << sshift;
+        const int Sz = 1 << sshift;
         int lo[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) lo[ax] = (q[ax] >> sshift) << sshift;
@@ -417,7 +452,7 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
         for (int ax = 0; ax < 3; ++ax) {
             float dx = r.d[ax];
             if (dx == 0.0f) continue;
-            int k = dx > 0.0f ? lo[ax] + S : lo[ax];
+            int k = dx > 0.0f ? lo[ax] + Sz : lo[ax];
             float P = plane_of(k, h);
             float tt = tapprox(r, ax, P);
             int cmpv = xa < 0 ? -1 : cross_cmp(r, ax, P, tt, xa, xP, xt);
@@ -444,10 +479,17 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
                 uint4 c0 = rowp[0];
                 w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
             }
-            const float sig = S::get(w, 0);
-            if (no_skip || sig >= t.sigma_min) {
+            if (SKIP) {
 #pragma unroll
                 for (int ch = 1; ch < NCH; ++ch) {
+                    uint4 cc = rowp[ch];
+                    w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
+                }
+            }
+            const float sig = S::get(w, 0);
+            if (SKIP || (flags & LQ_NO_SIGMA_SKIP) || sig >= t.sigma_min) {
+#pragma unroll
+                for (int ch = 1; ch < NCH && !SKIP; ++ch) {
                     uint4 cc = rowp[ch];
                     w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
                 }
@@ -458,9 +500,9 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
                     x1 = fmaf(S::get(w, 1 + K + k), Y[k], x1);
                     x2 = fmaf(S::get(w, 1 + 2 * K + k), Y[k], x2);
                 }
-                const float phi0 = t.l_max / (1.0f + expf(-x0));
-                const float phi1 = t.l_max / (1.0f + expf(-x1));
-                const float phi2 = t.l_max / (1.0f + expf(-x2));
+                const float phi0 = t.l_max * lq_rcp(1.0f + lq_exp_neg(x0));
+                const float phi1 = t.l_max * lq_rcp(1.0f + lq_exp_neg(x1));
+                const float phi2 = t.l_max * lq_rcp(1.0f + lq_exp_neg(x2));
                 const float dt = fmaxf(seg_dt(r, ev, xa, xP, xt), 0.0f);
                 const Acc delta = (Acc)dt * (Acc)dlen;
                 const Acc sd = (Acc)sig * delta;
@@ -472,9 +514,9 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
                 L2 += wgt * (Acc)phi2;
                 T -= wgt;
                 ++ncomp;
-                if (!no_stop && (Acc(1) - T) >= (Acc)t.alpha_max) {
+                if (!(flags & LQ_NO_EARLY_TERM) && (Acc(1) - T) >= (Acc)t.alpha_max) {
                     term = (int32_t)count - 1;
-                    break;
+                    return true;
                 }
             }
         }
@@ -484,31 +526,46 @@ LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, 
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             if (!(xmask & (1u << ax))) continue;
-            int nq = r.d[ax] > 0.0f ? lo[ax] + S : lo[ax] - 1;
+            int nq = r.d[ax] > 0.0f ? lo[ax] + Sz : lo[ax] - 1;
             leave = leave || nq < 0 || nq >= N;
             q[ax] = nq;
         }
-        if (leave) break;
+        if (leave) return true;
         const Event nev{xa, xP, xt};
-        if (S > 1) {
+        if (Sz > 1) {
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 if ((xmask & (1u << ax)) || r.d[ax] == 0.0f) continue;
-                q[ax] = locate(r, ax, lo[ax], lo[ax] + S, nev, h, N);
+                q[ax] = locate(r, ax, lo[ax], lo[ax] + Sz, nev, h, N);
             }
         }
         ev = nev;
+        return false;
     }
 
-    out.rgb[0] = (float)L0;
-    out.rgb[1] = (float)L1;
-    out.rgb[2] = (float)L2;
-    out.alpha = (float)(Acc(1) - T);
-    out.count = count;
-    out.n_comp = ncomp;
-    out.n_steps = nsteps;
-    out.term_idx = term;
-    out.hash = hash;
+    LQ_HD void result(RayOut &out) const {
+        out.rgb[0] = (float)L0;
+        out.rgb[1] = (float)L1;
+        out.rgb[2] = (float)L2;
+        out.alpha = (float)(Acc(1) - T);
+        out.count = count;
+        out.n_comp = ncomp;
+        out.n_steps = nsteps;
+        out.term_idx = term;
+        out.hash = hash;
+    }
+};
+
+// The whole query for one ray (init, steps until done, result).
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP = false>
+LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, int model,
+                            uint32_t flags, RayOut &out, uint32_t *ids, int32_t max_ids,
+                            int32_t *path, int path_stride) {
+    Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
+    if (m.init(t, o3, d3))
+        while (!m.step(t, model, flags, ids, max_ids, path, path_stride)) {
+        }
+    m.result(out);
 }
 
 }  // namespace lq

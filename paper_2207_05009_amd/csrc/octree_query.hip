@@ -1,28 +1,52 @@
 // octree_query.hip -- launch of the emission query on gfx950.
 //
-// One work-item per ray; the per-ray march (traversal with exact decisions,
-// float32 compositing) is march_ray() in march.h.
+// Persistent waves: the grid holds as many 256-lane blocks as fit on the
+// chip at once.  Every lane marches one ray at a time (Marcher in march.h),
+// one octree node per step.  When fewer than kRefillBelow lanes of a wave
+// still hold a ray, the idle lanes are refilled from a ray counter with one
+// atomic per wave: a 64-bit ballot of the idle lanes, one atomicAdd of its
+// popcount by the lowest idle lane, and each idle lane takes
+// base + (number of idle lanes below it).  Rays of very different lengths
+// then do not leave most of a wave idle until its longest ray is done,
+// while the atomic's latency and the per-ray set-up are paid for many lanes
+// at once.
+//
+// XCD-aware work split: the batch is cut into kXcds contiguous ranges with a
+// counter each.  Workgroups are dispatched to the accelerator dies round
+// robin, so a wave of block b starts on range b % kXcds: the rays one die's
+// L2 sees are neighbours in the batch (for a camera, a band of image rows),
+// not every kXcds-th chunk.  A wave whose range is used up continues on the
+// next ranges, so the tail stays balanced.
+#include <mutex>
+#include <unordered_map>
+
 #include "march.h"
 
 namespace lq {
 namespace {
 
-template <int ST, int DEG, bool ACC64, bool TRACE>
-__global__ __launch_bounds__(256) void k_query(const DevTree t, const QueryArgs a) {
-    __shared__ int32_t s_path[10 * 256];   // per-lane node path, [level][lane]
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+constexpr int kBlock = 256;
+constexpr int kRefillBelow = 48;     // refill when fewer lanes of a wave are busy
+constexpr int kStepsPerCheck = 4;    // steps between refill checks
+constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
+constexpr unsigned kAllRanges = (1u << kXcds) - 1u;
+
+__device__ inline uint64_t lanemask_lt() {
+    const unsigned lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <class M>
+__device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool trace) {
     RayOut r;
-    uint32_t *ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)i * a.max_ids : nullptr;
-    march_ray<ST, DEG, ACC64, TRACE>(t, a.o + 3 * i, a.d + 3 * i, a.model, a.flags, r, ids,
-                                     TRACE ? a.max_ids : 0, s_path + threadIdx.x, 256);
+    m.result(r);
     if (a.rgb) {
         a.rgb[3 * i] = r.rgb[0];
         a.rgb[3 * i + 1] = r.rgb[1];
         a.rgb[3 * i + 2] = r.rgb[2];
     }
     if (a.alpha) a.alpha[i] = r.alpha;
-    if (TRACE) {
+    if (trace) {
         a.count[i] = r.count;
         a.hash[i] = r.hash;
         a.term_idx[i] = r.term_idx;
@@ -31,16 +55,117 @@ __global__ __launch_bounds__(256) void k_query(const DevTree t, const QueryArgs 
     }
 }
 
+__device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; }
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+__global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
+                                                  unsigned long long *queue) {
+    __shared__ int32_t s_path[10 * kBlock];   // per-lane node path, [level][lane]
+    int32_t *path = s_path + threadIdx.x;
+    Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
+    int64_t ray = -1;            // ray held by this lane, -1 when idle
+    uint32_t *ids = nullptr;
+    int cur = blockIdx.x % kXcds;   // range this wave draws from (wave-uniform)
+    unsigned used_up = 0;           // ranges known to be exhausted (wave-uniform)
+    for (;;) {
+        bool want = ray < 0 && used_up != kAllRanges;
+        uint64_t need = __ballot(want);
+        const int busy = __popcll(__ballot(ray >= 0));
+        if (need && busy < kRefillBelow) {
+            for (int tries = 0; need && tries < kXcds; ++tries) {
+                const int cnt = __popcll(need);
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                unsigned long long base = 0;
+                if ((int)__lane_id() == leader) base = atomicAdd(queue + cur, (unsigned long long)cnt);
+                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+                base = ((unsigned long long)hi << 32) | lo;
+                const int64_t start = range_begin(cur, a.n);
+                const int64_t len = range_begin(cur + 1, a.n) - start;
+                if (want) {
+                    const int64_t slot = (int64_t)base + __popcll(need & lanemask_lt());
+                    if (slot < len) {
+                        const int64_t idx = start + slot;
+                        ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)idx * a.max_ids : nullptr;
+                        if (m.init(t, a.o + 3 * idx, a.d + 3 * idx)) {
+                            ray = idx;
+                            want = false;
+                        } else {
+                            write_ray(a, idx, m, TRACE);   // no positive-length overlap: done
+                        }
+                    }
+                }
+                if ((int64_t)base + cnt >= len) {   // this range is used up: move on
+                    used_up |= 1u << cur;
+                    for (int j = 1; j <= kXcds; ++j) {
+                        const int c = (cur + j) % kXcds;
+                        if (!(used_up & (1u << c))) { cur = c; break; }
+                    }
+                }
+                want = want && used_up != kAllRanges;
+                need = __ballot(want);
+            }
+        }
+        if (__all(ray < 0 && used_up == kAllRanges)) break;
+        for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
+            if (m.step(t, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock)) {
+                write_ray(a, ray, m, TRACE);
+                ray = -1;
+            }
+        }
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
+
+// resident blocks of a kernel on the current device (cached)
+template <class Kern>
+int resident_blocks(Kern kern) {
+    static std::mutex mu;
+    static std::unordered_map<int, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 1;
+    (void)hipGetLastError();
+    int nb = per_cu * cus;
+    cache[dev] = nb;
+    return nb;
+}
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+hipError_t launch_one(const DevTree &t, const QueryArgs &a, hipStream_t s) {
+    auto kern = k_query<ST, DEG, ACC64, TRACE, SKIP>;
+    const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
+    const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
+    unsigned long long *queue = nullptr;
+    hipError_t e = hipMallocAsync((void **)&queue, kXcds * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kXcds), 0, s, queue);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, t, a, queue);
+    e = hipGetLastError();
+    hipError_t f = hipFreeAsync(queue, s);
+    return e != hipSuccess ? e : f;
+}
+
 template <int ST, int DEG>
 hipError_t launch_deg(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s) {
-    const int block = 256;
-    const int64_t grid = (a.n + block - 1) / block;
+    // traces record every data leaf, so they march the full table; so do
+    // queries that composite every leaf
     const bool acc64 = (a.flags & LQ_FP64_ACCUM) != 0;
-    if (trace && acc64) hipLaunchKernelGGL((k_query<ST, DEG, true, true>), dim3(grid), dim3(block), 0, s, t, a);
-    else if (trace) hipLaunchKernelGGL((k_query<ST, DEG, false, true>), dim3(grid), dim3(block), 0, s, t, a);
-    else if (acc64) hipLaunchKernelGGL((k_query<ST, DEG, true, false>), dim3(grid), dim3(block), 0, s, t, a);
-    else hipLaunchKernelGGL((k_query<ST, DEG, false, false>), dim3(grid), dim3(block), 0, s, t, a);
-    return hipGetLastError();
+    const bool full = trace || (a.flags & LQ_NO_SIGMA_SKIP) != 0;
+    if (trace) return acc64 ? launch_one<ST, DEG, true, true, false>(t, a, s)
+                            : launch_one<ST, DEG, false, true, false>(t, a, s);
+    if (full) return acc64 ? launch_one<ST, DEG, true, false, false>(t, a, s)
+                           : launch_one<ST, DEG, false, false, false>(t, a, s);
+    return acc64 ? launch_one<ST, DEG, true, false, true>(t, a, s)
+                 : launch_one<ST, DEG, false, false, true>(t, a, s);
 }
 
 template <int ST>

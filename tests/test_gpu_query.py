@@ -87,14 +87,48 @@ def test_flags_and_fp64_accumulation(lq, c0_tree):
 
 
 def test_radiance_kernel_matches_trace_kernel(lq, c0_tree):
+    """The plain query marches the table without sub-sigma_min leaves; it
+    composites the same leaves over the same segments as the trace, so the
+    outputs agree (bit-exactly except where a segment's entry is an edge or
+    corner crossing, whose tie may be represented by another axis)."""
     import torch
     o, d = inputs.rays.sphere_to_cube(65536, 3)
     oct_ = lq.Octree(c0_tree, "f32")
     _say("query vs trace outputs")
-    rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")
-    t = oct_.trace(_dev(o), _dev(d), model="linear")
-    torch.cuda.synchronize()
-    assert torch.equal(rgb, t["rgb"]) and torch.equal(alpha, t["alpha"])
+    for model in ("linear", "exp"):
+        rgb, alpha = oct_.query(_dev(o), _dev(d), model=model)
+        t = oct_.trace(_dev(o), _dev(d), model=model)
+        torch.cuda.synchronize()
+        err = parity.rel_err(rgb.cpu().numpy().astype(np.float64), t["rgb"].cpu().numpy(), c0_tree.l_max)
+        assert err.max() < 1e-6, err.max()
+        assert float((alpha - t["alpha"]).abs().max()) < 1e-6
+        same = (rgb == t["rgb"]).all(1)
+        assert float(same.float().mean()) > 0.999
+        # with every leaf composited both march the full table: bit-identical
+        f = lq.LQ_NO_SIGMA_SKIP
+        rgb, alpha = oct_.query(_dev(o), _dev(d), model=model, flags=f)
+        t = oct_.trace(_dev(o), _dev(d), model=model, flags=f)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb, t["rgb"]) and torch.equal(alpha, t["alpha"])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_plain_query_parity(lq, c0_tree, storage):
+    """The production entry point (no records) against the oracle."""
+    import torch
+    o, d = inputs.rays.sphere_to_cube(65536, 8)
+    oct_ = lq.Octree(c0_tree, storage)
+    for model, m in (("linear", 0), ("exp", 1)):
+        _say(f"plain query {storage} {model}")
+        rgb, alpha = oct_.query(_dev(o), _dev(d), model=model)
+        torch.cuda.synchronize()
+        orc = core.query(c0_tree, o, d, model=m, storage=storage)
+        g = {"rgb": rgb.cpu().numpy(), "alpha": alpha.cpu().numpy()}
+        amb = orc["alt_valid"].astype(bool)
+        e_main = parity.rel_err(g["rgb"].astype(np.float64), orc["L"], c0_tree.l_max).max(1)
+        e_alt = parity.rel_err(g["rgb"].astype(np.float64), orc["alt_L"], c0_tree.l_max).max(1)
+        err = np.where(amb, np.minimum(e_main, e_alt), e_main)
+        assert err.max() < parity.RTOL, (storage, model, err.max())
 
 
 def test_empty_tree_and_misses(lq):
@@ -177,12 +211,18 @@ def test_full_size_camera_sampled_parity(lq, c1_tree):
     _say(f"full-size camera batch: {len(o)} rays, {c1_tree.n_leaves} leaves")
     oct_ = lq.Octree(c1_tree, "f32")
     out = parity.to_numpy(oct_.trace(_dev(o), _dev(d), model="linear"))
+    rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")     # the timed entry point
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(7).choice(len(o), 20000, replace=False))
     orc = core.query(c1_tree, o[idx], d[idx], model=0)
     g = {k: v[idx] for k, v in out.items()}
     rep = parity.compare(g, orc, c1_tree.l_max, ids=False)
     _say(f"report {rep}")
+    assert rep["ok"], rep
+    q = {"count": g["count"], "hash": g["hash"], "term_idx": g["term_idx"],
+         "rgb": rgb.cpu().numpy()[idx], "alpha": alpha.cpu().numpy()[idx]}
+    rep = parity.compare(q, orc, c1_tree.l_max, ids=False)
+    _say(f"plain query report {rep}")
     assert rep["ok"], rep
     # properties on every ray
     assert np.all(np.isfinite(out["rgb"])) and np.all(out["rgb"] >= 0)
