@@ -146,6 +146,106 @@ lq_status lq_query_trace(const lq_octree *tree, const float *origins, const floa
                          uint32_t *n_steps, uint32_t *leaf_ids, int32_t max_ids,
                          void *hip_stream);
 
+/*
+ * Multi-luminaire batch: rays [ray_offsets[k], ray_offsets[k+1]) query
+ * trees[k], all in one persistent launch.  ray_offsets is a HOST array of
+ * n_trees + 1 non-decreasing values starting at 0; origins/dirs/rgb/alpha
+ * are device arrays of ray_offsets[n_trees] rays.  Every tree must live on
+ * the same device.  Same per-ray semantics as lq_query_radiance.
+ */
+lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees,
+                                  const int64_t *ray_offsets, const float *origins,
+                                  const float *dirs, float *rgb, float *alpha, int model,
+                                  uint32_t flags, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate.  A ray is reduced to the point where its line enters
+ * the sphere of radius sqrt(3) bounding the proxy box and its unit direction
+ * (the 5D light-field coordinates of Sec. 3, Eq. 1), encoded with 10
+ * frequencies of Fourier features (the positional encoding of Sec. 4.2),
+ * and mapped by a 4 x 64 ReLU MLP to y = log(L + 0.01).  Training minimises
+ * the HDR relative loss of Sec. 4.3, Eq. 8 (lambda = 1, epsilon = 0.01, the
+ * channel mean of the prediction as luminance, held constant in the
+ * gradient) with Adam and an exponentially decaying learning rate
+ * (Sec. 4.4).  GEMMs run on MFMA in bfloat16 with float32 accumulation;
+ * master weights and Adam moments are float32.  A line that misses the
+ * sphere has radiance 0.  Parameters are one float32 vector of
+ * lq_mlp_num_params() values: per layer W[out][in] row-major then b[out],
+ * layers 128->64, 64->64, 64->64, 64->64, 64->3.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_freq;           /* must be 10 */
+    int32_t hidden;           /* must be 64 */
+    int32_t n_hidden_layers;  /* must be 4  */
+} lq_mlp_config;
+
+typedef struct {
+    int32_t steps;        /* optimiser steps to run in this call                  */
+    int32_t total_steps;  /* length of the learning-rate schedule                 */
+    int32_t batch;        /* samples per step, a positive multiple of 64          */
+    float lr0, lr1;       /* learning rate decays from lr0 (step 0) to lr1 (total) */
+    float beta1, beta2, eps;
+} lq_train_config;
+
+/* Create a surrogate on `device` with He-uniform weights drawn from `seed`
+ * (cfg may be NULL).  Errors: LQ_ERR_UNSUPPORTED for another shape. */
+lq_status lq_mlp_create(const lq_mlp_config *cfg, uint64_t seed, int device, lq_mlp **out);
+void lq_mlp_free(lq_mlp *mlp);
+int32_t lq_mlp_num_params(void);
+/* Copy the float32 master parameters to / from host memory; set also
+ * clears the Adam state and the step counter. */
+lq_status lq_mlp_get_params(const lq_mlp *mlp, float *host_params);
+lq_status lq_mlp_set_params(lq_mlp *mlp, const float *host_params);
+
+/*
+ * Train on n_pairs (ray, radiance) pairs (device arrays origins/dirs [n][3],
+ * rgb [n][3] float32).  Step k of the run (counted over all calls) uses the
+ * `batch` pairs starting at (k * batch) mod n_pairs, so the pair set should
+ * be in random order.  Deterministic: the batch-gradient reduction has a
+ * fixed order.  loss_log_host (nullable, host) receives one batch loss per
+ * step of this call.  Synchronises the stream when loss_log_host is given.
+ */
+lq_status lq_mlp_train(lq_mlp *mlp, const float *origins, const float *dirs, const float *rgb,
+                       int64_t n_pairs, const lq_train_config *cfg, float *loss_log_host,
+                       void *hip_stream);
+
+/* Batch loss (host, nullable) and its gradient (device float32 [n_params])
+ * at the current parameters over n pairs; no update.  Synchronises. */
+lq_status lq_mlp_grad(lq_mlp *mlp, const float *origins, const float *dirs, const float *rgb,
+                      int64_t n, float *grad, float *loss_host, void *hip_stream);
+
+/* Surrogate radiance rgb[n][3] = max(exp(y) - 0.01, 0) for every ray. */
+lq_status lq_mlp_forward(const lq_mlp *mlp, const float *origins, const float *dirs, int64_t n,
+                         float *rgb, void *hip_stream);
+
+/*
+ * Trust map: held-out (ray, reference radiance) pairs are binned by the
+ * octahedral cells (16 x 16) of the entry direction and of the ray
+ * direction; a bin is trusted when it holds at least 4 pairs and its
+ * squared error sum is within max_rel_err^2 of its squared reference sum
+ * (plus (1e-3)^2 per pair).  Synchronises the stream.
+ */
+lq_status lq_mlp_build_trust(lq_mlp *mlp, const float *origins, const float *dirs,
+                             const float *rgb_ref, int64_t n, float max_rel_err, void *hip_stream);
+/* Copy the trust map (host, nullable) and report its size (0 if none). */
+lq_status lq_mlp_trust_map(const lq_mlp *mlp, uint8_t *host_map, int32_t *n_bins);
+
+/*
+ * Surrogate with octree fallback: rays in untrusted bins are compacted on
+ * the device and answered by lq_query_radiance on `fallback` (linear model,
+ * default flags); used_fallback[n] (device, nullable) marks them.  Without
+ * a trust map or a fallback tree this is lq_mlp_forward.
+ */
+lq_status lq_mlp_infer(const lq_mlp *mlp, const lq_octree *fallback, const float *origins,
+                       const float *dirs, int64_t n, float *rgb, uint8_t *used_fallback,
+                       void *hip_stream);
+
+/* Checkpoint: parameters, Adam moments, step counter and trust map.
+ * Resuming from a checkpoint and training N more steps is bit-identical to
+ * training without the interruption. */
+lq_status lq_mlp_save(const lq_mlp *mlp, const char *path);
+lq_status lq_mlp_load(const char *path, int device, lq_mlp **out);
+
 /* Text of the last error on this thread ("" if none). */
 const char *lq_last_error(void);
 /* Library version string. */

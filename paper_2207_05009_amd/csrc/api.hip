@@ -421,6 +421,22 @@ static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace
     return LQ_OK;
 }
 
+lq_status query_indexed(const lq_octree *t, const float *o, const float *d, int64_t n_max, const int64_t *index,
+                        const unsigned long long *n_dev, float *rgb, hipStream_t s) {
+    if (!t) return fail(LQ_ERR_INVALID_ARG, "fallback tree is NULL");
+    QueryArgs a{};
+    a.o = o;
+    a.d = d;
+    a.n = n_max;
+    a.rgb = rgb;
+    a.model = LQ_LINEAR;
+    a.index = index;
+    a.n_dev = n_dev;
+    hipError_t e = launch_query(t->t, a, false, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the fallback query");
+    return LQ_OK;
+}
+
 }  // namespace lq
 
 extern "C" {
@@ -436,6 +452,60 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
     a.model = model;
     a.flags = flags;
     return query_common(tree, a, false, hip_stream);
+}
+
+lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees, const int64_t *ray_offsets,
+                                  const float *origins, const float *dirs, float *rgb, float *alpha, int model,
+                                  uint32_t flags, void *hip_stream) {
+    if (!trees || n_trees <= 0 || !ray_offsets) return fail(LQ_ERR_INVALID_ARG, "trees/ray_offsets missing");
+    if (n_trees > 65536) return fail(LQ_ERR_INVALID_ARG, "too many trees");
+    if (ray_offsets[0] != 0) return fail(LQ_ERR_INVALID_ARG, "ray_offsets[0] must be 0");
+    for (int k = 0; k < n_trees; ++k) {
+        if (!trees[k]) return fail(LQ_ERR_INVALID_ARG, "a tree is NULL");
+        if (ray_offsets[k + 1] < ray_offsets[k]) return fail(LQ_ERR_INVALID_ARG, "ray_offsets must not decrease");
+        if (trees[k]->device != trees[0]->device || trees[k]->t.storage != trees[0]->t.storage ||
+            trees[k]->t.sh_degree != trees[0]->t.sh_degree)
+            return fail(LQ_ERR_UNSUPPORTED, "all trees must share device, storage and SH degree");
+    }
+    if (trees[0]->t.sh_degree != 2 && trees[0]->t.sh_degree != 3)
+        return fail(LQ_ERR_UNSUPPORTED, "the multi-tree query is built for SH degrees 2 and 3");
+    const int64_t n = ray_offsets[n_trees];
+    QueryArgs a{};
+    a.o = origins;
+    a.d = dirs;
+    a.n = n;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.model = model;
+    a.flags = flags;
+    if (a.model != LQ_LINEAR && a.model != LQ_EXP) return fail(LQ_ERR_INVALID_ARG, "bad model");
+    if (a.flags & ~(uint32_t)(LQ_NO_EARLY_TERM | LQ_FP64_ACCUM | LQ_NO_SIGMA_SKIP))
+        return fail(LQ_ERR_INVALID_ARG, "unknown flag bits");
+    if (n == 0) return LQ_OK;
+    const int dev = trees[0]->device;
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    lq_status st;
+    if ((st = check_dev(origins, n * 12, dev, "origins")) != LQ_OK) return st;
+    if ((st = check_dev(dirs, n * 12, dev, "dirs")) != LQ_OK) return st;
+    if ((st = check_dev(rgb, n * 12, dev, "rgb")) != LQ_OK) return st;
+    if (alpha && (st = check_dev(alpha, n * 4, dev, "alpha")) != LQ_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<DevTree> host_trees(n_trees);
+    for (int k = 0; k < n_trees; ++k) host_trees[k] = trees[k]->t;
+    const size_t tb = sizeof(DevTree) * (size_t)n_trees, ob = sizeof(int64_t) * (size_t)(n_trees + 1);
+    unsigned char *buf = nullptr;
+    if ((e = hipMallocAsync((void **)&buf, tb + ob, s)) != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    e = hipMemcpyAsync(buf, host_trees.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf + tb, ray_offsets, ob, hipMemcpyHostToDevice, s);
+    // the host copies above are staged from pageable memory: keep them alive
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = launch_query_multi(trees[0]->t.storage, trees[0]->t.sh_degree, reinterpret_cast<DevTree *>(buf),
+                               reinterpret_cast<int64_t *>(buf + tb), n_trees, a, s);
+    (void)hipFreeAsync(buf, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the multi-tree query");
+    return LQ_OK;
 }
 
 lq_status lq_query_trace(const lq_octree *tree, const float *origins, const float *dirs, int64_t n,

@@ -45,15 +45,28 @@ struct QueryArgs {
     uint32_t *n_steps;
     uint32_t *leaf_ids;
     int32_t max_ids;
+    // ray i of the launch is index[i] of the arrays (null: i itself), and
+    // the launch covers *n_dev rays when n_dev is set (n is then a bound)
+    const int64_t *index;
+    const unsigned long long *n_dev;
 };
 
 // launch the emission query; returns hipSuccess or the launch error
 hipError_t launch_query(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s);
+// several trees of one storage type and SH degree (2 or 3) in one launch;
+// trees/offsets are device arrays
+hipError_t launch_query_multi(int storage, int sh_degree, const DevTree *trees, const int64_t *offsets,
+                              int n_trees, const QueryArgs &a, hipStream_t s);
 
 // FP32 -> storage conversions used by the loader (round to nearest even)
 uint16_t f32_to_f16_rne(float x);
 uint16_t f32_to_bf16_rne(float x);
 
 void set_error(const std::string &msg);
+
+// emission query (linear model, default flags) of the rays listed in
+// index[0 .. *n_dev) of origins/dirs, writing rgb at those rays
+lq_status query_indexed(const lq_octree *tree, const float *o, const float *d, int64_t n_max,
+                        const int64_t *index, const unsigned long long *n_dev, float *rgb, hipStream_t s);
 
 }  // namespace lq

@@ -1,0 +1,961 @@
+// mlp.hip -- training and inference of the learned surrogate on gfx950.
+//
+// Training step (one launch + one reduction launch):
+//   k_train_step: a workgroup of 4 waves stages the bfloat16 weight image in
+//   LDS and processes tiles of 64 samples.  Per tile, each wave takes 16
+//   samples through the sphere parameterisation, the Fourier features, the
+//   forward GEMMs (MFMA 16x16x16 bf16, weights as the A operand so that a
+//   layer's output blocks are the next layer's B operand), the loss of Eq. 8
+//   and the backward data GEMMs; activations and output gradients stay in
+//   LDS.  Then the 84 16x16 blocks of the weight gradients (K = the tile's
+//   samples) are split over the 4 waves and accumulate in registers across
+//   the workgroup's tiles.  Each workgroup writes one partial gradient row.
+//   k_reduce_adam: sums the rows in a fixed order (deterministic), applies
+//   Adam to the float32 master weights and refreshes the bfloat16 image.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lq_internal.h"
+#include "mlp_common.h"
+
+using namespace lq::mlp;
+
+namespace lq {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kTile = 64;                   // samples per tile (16 per wave)
+constexpr int kSF = kFeat + 4;              // padded LDS row strides (bf16 elements)
+constexpr int kSH = kHidden + 4;
+constexpr int kSD = kOutPad + 4;
+
+// LDS image of the weights: layer l rows of padded stride
+constexpr int kLW1 = 0;
+constexpr int kLW2 = kLW1 + kHidden * kSF;
+constexpr int kLW3 = kLW2 + kHidden * kSH;
+constexpr int kLW4 = kLW3 + kHidden * kSH;
+constexpr int kLW5 = kLW4 + kHidden * kSH;
+constexpr int kLWEnd = kLW5 + kOutPad * kSH;    // bf16 elements
+
+// training-kernel LDS carve (bytes)
+constexpr int kOffW = 0;
+constexpr int kOffB = kOffW + kLWEnd * 2;
+constexpr int kOffF = kOffB + kBiasPad * 4;
+constexpr int kOffH = kOffF + kTile * kSF * 2;            // 4 x [64][kSH]
+constexpr int kOffDZ = kOffH + 4 * kTile * kSH * 2;       // 4 x [64][kSH]
+constexpr int kOffDY = kOffDZ + 4 * kTile * kSH * 2;      // [64][kSD]
+constexpr int kOffAct = kOffDY + kTile * kSD * 2;         // [64] float
+constexpr int kOffLoss = kOffAct + kTile * 4;             // [kWaves] float
+constexpr int kTrainLds = kOffLoss + kWaves * 4;
+
+// inference-kernel LDS carve: weights + per wave [16][kSF] + 2 x [16][kSH]
+constexpr int kInfWave = 16 * kSF * 2 + 2 * 16 * kSH * 2;
+constexpr int kInfLds = kOffF + kWaves * kInfWave;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline bf16x4 ld4(const uint16_t *p) { return *reinterpret_cast<const bf16x4 *>(p); }
+
+__device__ inline bf16x4 ld4_strided(const uint16_t *p, int stride) {
+    bf16x4 v;
+    v[0] = (short)p[0];
+    v[1] = (short)p[stride];
+    v[2] = (short)p[2 * stride];
+    v[3] = (short)p[3 * stride];
+    return v;
+}
+
+// stage the bfloat16 weight image and the biases in LDS
+__device__ void stage_weights(const uint16_t *wimg, const float *bias, uint16_t *sW, float *sB) {
+    for (int i = threadIdx.x; i < kImage; i += blockDim.x) {
+        int dst;
+        if (i < kI2) dst = kLW1 + (i / kFeat) * kSF + i % kFeat;
+        else if (i < kI3) dst = kLW2 + ((i - kI2) / kHidden) * kSH + (i - kI2) % kHidden;
+        else if (i < kI4) dst = kLW3 + ((i - kI3) / kHidden) * kSH + (i - kI3) % kHidden;
+        else if (i < kI5) dst = kLW4 + ((i - kI4) / kHidden) * kSH + (i - kI4) % kHidden;
+        else dst = kLW5 + ((i - kI5) / kHidden) * kSH + (i - kI5) % kHidden;
+        sW[dst] = wimg[i];
+    }
+    for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
+}
+
+// features of the 16 samples of a wave: lane l does sample l % 16, feature
+// columns 32 (l / 16) .. + 31.  Returns whether the lane's sample is active.
+__device__ bool wave_features(const float *o, const float *d, int64_t ray, bool valid, uint16_t *sF,
+                              int row) {
+    const int lane = __lane_id();
+    float x6[6] = {0, 0, 0, 0, 0, 0};
+    bool act = false;
+    if (valid) {
+        float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
+        float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
+        act = sphere_x6(oo, dd, x6);
+    }
+    const int c0 = (lane >> 4) * 32;
+    uint16_t *dst = sF + row * kSF + c0;
+#pragma unroll 4
+    for (int c = 0; c < 32; ++c) dst[c] = f2bf(act ? feature(x6, c0 + c) : 0.0f);
+    return act;
+}
+
+// forward layer for the 16 samples whose rows start at s0:
+// Z[s][f] = sum_k X[s][k] W[f][k] + b[f]; H = relu(Z) in bfloat16
+template <int K, int OUTB>
+__device__ void fwd_layer(const uint16_t *X, int xs, const uint16_t *W, int ws, const float *b, uint16_t *H,
+                          int hs, int s0) {
+    const int lane = __lane_id();
+    const int r16 = lane & 15, q4 = lane >> 4;
+#pragma unroll
+    for (int fb = 0; fb < OUTB; ++fb) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < K / 16; ++kb) {
+            const bf16x4 a = ld4(W + (fb * 16 + r16) * ws + kb * 16 + 4 * q4);
+            const bf16x4 x = ld4(X + (s0 + r16) * xs + kb * 16 + 4 * q4);
+            acc = mfma16(a, x, acc);
+        }
+        uint16_t *dst = H + (s0 + r16) * hs + fb * 16 + 4 * q4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = f2bf(fmaxf(acc[i] + b[fb * 16 + 4 * q4 + i], 0.0f));
+    }
+}
+
+// last layer: returns y (lanes 0..15 hold outputs 0..3 of sample s0 + lane)
+__device__ f32x4 out_layer(const uint16_t *X, int xs, const uint16_t *W5, const float *b5, int s0) {
+    const int lane = __lane_id();
+    const int r16 = lane & 15, q4 = lane >> 4;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < kHidden / 16; ++kb) {
+        const bf16x4 a = ld4(W5 + r16 * kSH + kb * 16 + 4 * q4);
+        const bf16x4 x = ld4(X + (s0 + r16) * xs + kb * 16 + 4 * q4);
+        acc = mfma16(a, x, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int f = 4 * q4 + i;
+        acc[i] += f < kOut ? b5[f] : 0.0f;
+    }
+    return acc;
+}
+
+// backward data: dX[s][in] = sum_out G[s][out] W[out][in], masked by H > 0
+template <int OUTK, int INB>
+__device__ void bwd_layer(const uint16_t *G, int gs, const uint16_t *W, int ws, const uint16_t *Hm, int hs,
+                          uint16_t *DX, int dxs, int s0) {
+    const int lane = __lane_id();
+    const int r16 = lane & 15, q4 = lane >> 4;
+#pragma unroll
+    for (int ib = 0; ib < INB; ++ib) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < OUTK / 16; ++kb) {
+            const bf16x4 a = ld4_strided(W + (kb * 16 + 4 * q4) * ws + ib * 16 + r16, ws);
+            const bf16x4 g = ld4(G + (s0 + r16) * gs + kb * 16 + 4 * q4);
+            acc = mfma16(a, g, acc);
+        }
+        const uint16_t *hm = Hm + (s0 + r16) * hs + ib * 16 + 4 * q4;
+        uint16_t *dst = DX + (s0 + r16) * dxs + ib * 16 + 4 * q4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint16_t hb = hm[i];
+            const bool on = hb != 0 && !(hb & 0x8000u);
+            dst[i] = f2bf(on ? acc[i] : 0.0f);
+        }
+    }
+}
+
+// ------------------------------------------------------------ training
+__global__ __launch_bounds__(256) void k_train_step(const float *o, const float *d, const float *tgt,
+                                                    int64_t n_pairs, int64_t base, int64_t count,
+                                                    int tiles, float inv_batch, const uint16_t *wimg,
+                                                    const float *bias, float *part, float *loss_part) {
+    extern __shared__ __align__(16) char smem[];
+    uint16_t *sW = reinterpret_cast<uint16_t *>(smem + kOffW);
+    float *sB = reinterpret_cast<float *>(smem + kOffB);
+    uint16_t *sF = reinterpret_cast<uint16_t *>(smem + kOffF);
+    uint16_t *sH = reinterpret_cast<uint16_t *>(smem + kOffH);
+    uint16_t *sDZ = reinterpret_cast<uint16_t *>(smem + kOffDZ);
+    uint16_t *sDY = reinterpret_cast<uint16_t *>(smem + kOffDY);
+    float *sAct = reinterpret_cast<float *>(smem + kOffAct);
+    float *sLoss = reinterpret_cast<float *>(smem + kOffLoss);
+    auto Hl = [&](int l) { return sH + (l - 1) * kTile * kSH; };    // H_1..H_4
+    auto DZl = [&](int l) { return sDZ + (l - 1) * kTile * kSH; };  // dZ_1..dZ_4
+
+    stage_weights(wimg, bias, sW, sB);
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = __lane_id();
+    const int r16 = lane & 15, q4 = lane >> 4;
+    const int s0 = wave * 16;
+
+    f32x4 gacc[21];
+#pragma unroll
+    for (int j = 0; j < 21; ++j) gacc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float gbias = 0.0f, gb5 = 0.0f, lsum = 0.0f;
+
+    for (int tile = 0; tile < tiles; ++tile) {
+        const int64_t local0 = ((int64_t)blockIdx.x * tiles + tile) * kTile;
+        // ---- phase A: this wave's 16 samples
+        const int64_t local = local0 + s0 + r16;
+        const bool valid = local < count;
+        const int64_t ray = (base + local) % n_pairs;
+        const bool act = wave_features(o, d, ray, valid, sF, s0 + r16);
+        if (q4 == 0) sAct[s0 + r16] = act ? 1.0f : 0.0f;
+        wave_sync();
+        fwd_layer<kFeat, 4>(sF, kSF, sW + kLW1, kSF, sB, Hl(1), kSH, s0);
+        wave_sync();
+        fwd_layer<kHidden, 4>(Hl(1), kSH, sW + kLW2, kSH, sB + 64, Hl(2), kSH, s0);
+        wave_sync();
+        fwd_layer<kHidden, 4>(Hl(2), kSH, sW + kLW3, kSH, sB + 128, Hl(3), kSH, s0);
+        wave_sync();
+        fwd_layer<kHidden, 4>(Hl(3), kSH, sW + kLW4, kSH, sB + 192, Hl(4), kSH, s0);
+        wave_sync();
+        const f32x4 y = out_layer(Hl(4), kSH, sW + kLW5, sB + 256, s0);
+        // loss (Eq. 8, channel-mean luminance held constant) and dL/dy
+        if (q4 == 0) {
+            float g[kOutPad];
+#pragma unroll
+            for (int c = 0; c < kOutPad; ++c) g[c] = 0.0f;
+            if (act) {
+                float e[3], lh[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    e[c] = expf(y[c]);
+                    lh[c] = e[c] - kEpsOut;
+                }
+                const float den = (lh[0] + lh[1] + lh[2]) * (1.0f / 3.0f) + kLossEps;
+                const float id2 = 1.0f / (den * den);
+                float l = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float diff = lh[c] - tgt[3 * ray + c];
+                    l += diff * diff * id2;
+                    g[c] = 2.0f * diff * e[c] * id2 * inv_batch;
+                }
+                lsum += l;
+            }
+            uint16_t *dst = sDY + (s0 + r16) * kSD;
+#pragma unroll
+            for (int c = 0; c < kOutPad; ++c) dst[c] = f2bf(g[c]);
+        }
+        wave_sync();
+        bwd_layer<kOutPad, 4>(sDY, kSD, sW + kLW5, kSH, Hl(4), kSH, DZl(4), kSH, s0);
+        wave_sync();
+        bwd_layer<kHidden, 4>(DZl(4), kSH, sW + kLW4, kSH, Hl(3), kSH, DZl(3), kSH, s0);
+        wave_sync();
+        bwd_layer<kHidden, 4>(DZl(3), kSH, sW + kLW3, kSH, Hl(2), kSH, DZl(2), kSH, s0);
+        wave_sync();
+        bwd_layer<kHidden, 4>(DZl(2), kSH, sW + kLW2, kSH, Hl(1), kSH, DZl(1), kSH, s0);
+        __syncthreads();
+
+        // ---- phase B: weight-gradient blocks over the tile's 64 samples
+#pragma unroll
+        for (int slot = 0; slot < 21; ++slot) {
+            const int j = slot * kWaves + wave;   // block 0..83
+            const uint16_t *G, *X;
+            int gs, xs, ob, ib;
+            if (j < 32) { G = DZl(1); gs = kSH; X = sF; xs = kSF; ob = j >> 3; ib = j & 7; }
+            else if (j < 80) {
+                const int l = 2 + (j - 32) / 16, jj = (j - 32) % 16;
+                G = DZl(l); gs = kSH; X = Hl(l - 1); xs = kSH; ob = jj >> 2; ib = jj & 3;
+            } else { G = sDY; gs = kSD; X = Hl(4); xs = kSH; ob = 0; ib = j - 80; }
+            f32x4 acc = gacc[slot];
+#pragma unroll
+            for (int kb = 0; kb < kTile / 16; ++kb) {
+                const bf16x4 a = ld4_strided(G + (kb * 16 + 4 * q4) * gs + ob * 16 + r16, gs);
+                const bf16x4 b = ld4_strided(X + (kb * 16 + 4 * q4) * xs + ib * 16 + r16, xs);
+                acc = mfma16(a, b, acc);
+            }
+            gacc[slot] = acc;
+        }
+        // bias gradients: thread t owns b_{t/64 + 1}[t % 64]; threads 0..2 b_5
+        {
+            const int t = threadIdx.x;
+            const uint16_t *G = DZl(t / 64 + 1);
+            float s = 0.0f;
+            for (int smp = 0; smp < kTile; ++smp) s += bf2f(G[smp * kSH + (t & 63)]);
+            gbias += s;
+            if (t < kOut) {
+                float s5 = 0.0f;
+                for (int smp = 0; smp < kTile; ++smp) s5 += bf2f(sDY[smp * kSD + t]);
+                gb5 += s5;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write this workgroup's partial gradient row
+    float *P = part + (size_t)blockIdx.x * kParams;
+#pragma unroll
+    for (int slot = 0; slot < 21; ++slot) {
+        const int j = slot * kWaves + wave;
+        int woff, in_dim, out_dim, ob, ib;
+        if (j < 32) { woff = kW1; in_dim = kFeat; out_dim = kHidden; ob = j >> 3; ib = j & 7; }
+        else if (j < 80) {
+            const int l = 2 + (j - 32) / 16, jj = (j - 32) % 16;
+            woff = l == 2 ? kW2 : (l == 3 ? kW3 : kW4);
+            in_dim = kHidden; out_dim = kHidden; ob = jj >> 2; ib = jj & 3;
+        } else { woff = kW5; in_dim = kHidden; out_dim = kOut; ob = 0; ib = j - 80; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int out = ob * 16 + 4 * q4 + i;
+            const int in = ib * 16 + r16;
+            if (out < out_dim) P[woff + out * in_dim + in] = gacc[slot][i];
+        }
+    }
+    {
+        const int t = threadIdx.x;
+        const int boff = t < 64 ? kB1 : (t < 128 ? kB2 : (t < 192 ? kB3 : kB4));
+        P[boff + (t & 63)] = gbias;
+        if (t < kOut) P[kB5 + t] = gb5;
+    }
+    // loss partial: lanes 0..15 of each wave hold per-sample sums
+    float l = lsum;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    if (lane == 0) sLoss[wave] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int w = 0; w < kWaves; ++w) s += sLoss[w];
+        loss_part[blockIdx.x] = s * inv_batch;
+    }
+}
+
+__device__ inline int image_index(int p) {
+    if (p < kB1) return kI1 + p;
+    if (p >= kW2 && p < kB2) return kI2 + (p - kW2);
+    if (p >= kW3 && p < kB3) return kI3 + (p - kW3);
+    if (p >= kW4 && p < kB4) return kI4 + (p - kW4);
+    if (p >= kW5 && p < kB5) return kI5 + (p - kW5);
+    return -1;
+}
+__device__ inline int bias_index(int p) {
+    if (p >= kB1 && p < kW2) return p - kB1;
+    if (p >= kB2 && p < kW3) return 64 + p - kB2;
+    if (p >= kB3 && p < kW4) return 128 + p - kB3;
+    if (p >= kB4 && p < kW5) return 192 + p - kB4;
+    if (p >= kB5) return 256 + p - kB5;
+    return -1;
+}
+
+// sum the partial rows in a fixed order; optional Adam update
+__global__ void k_reduce_adam(const float *part, int rows, float *theta, float *m, float *v, uint16_t *wimg,
+                              float *bias, const float *loss_part, float *loss_out, float *grad_out,
+                              int update, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        float s = 0.0f;
+        for (int r = 0; r < rows; ++r) s += loss_part[r];
+        *loss_out = s;
+    }
+    if (p >= kParams) return;
+    float g = 0.0f;
+    for (int r = 0; r < rows; ++r) g += part[(size_t)r * kParams + p];
+    if (grad_out) grad_out[p] = g;
+    if (!update) return;
+    const float mm = b1 * m[p] + (1.0f - b1) * g;
+    const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float th = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    theta[p] = th;
+    const int ii = image_index(p);
+    if (ii >= 0) wimg[ii] = f2bf(th);
+    const int bi = bias_index(p);
+    if (bi >= 0) bias[bi] = th;
+}
+
+// parameter that an image / bias slot holds (-1: padding, stays zero)
+__device__ inline int param_of_image(int i) {
+    if (i < kI2) return kW1 + i;
+    if (i < kI3) return kW2 + (i - kI2);
+    if (i < kI4) return kW3 + (i - kI3);
+    if (i < kI5) return kW4 + (i - kI4);
+    return i - kI5 < kOut * kHidden ? kW5 + (i - kI5) : -1;
+}
+__device__ inline int param_of_bias(int i) {
+    if (i < 64) return kB1 + i;
+    if (i < 128) return kB2 + i - 64;
+    if (i < 192) return kB3 + i - 128;
+    if (i < 256) return kB4 + i - 192;
+    return i - 256 < kOut ? kB5 + i - 256 : -1;
+}
+
+__global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kImage) {
+        const int p = param_of_image(i);
+        wimg[i] = p >= 0 ? f2bf(theta[p]) : (uint16_t)0;
+    }
+    if (i < kBiasPad) {
+        const int p = param_of_bias(i);
+        bias[i] = p >= 0 ? theta[p] : 0.0f;
+    }
+}
+
+// ------------------------------------------------------------ inference
+// Forward pass for 16 rays per wave iteration.  mode 0: radiance only;
+// mode 1: radiance, trust lookup and compaction of untrusted rays; mode 2:
+// accumulate trust statistics against reference radiance.
+__global__ __launch_bounds__(256) void k_infer(const float *o, const float *d, int64_t n, const uint16_t *wimg,
+                                               const float *bias, int mode, const uint8_t *trust, float *rgb,
+                                               uint8_t *used_fb, int64_t *fb_list, unsigned long long *fb_count,
+                                               const float *ref, double *terr, double *tref, unsigned *tcnt) {
+    extern __shared__ __align__(16) char smem[];
+    uint16_t *sW = reinterpret_cast<uint16_t *>(smem + kOffW);
+    float *sB = reinterpret_cast<float *>(smem + kOffB);
+    stage_weights(wimg, bias, sW, sB);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int lane = __lane_id();
+    const int r16 = lane & 15, q4 = lane >> 4;
+    char *mine = smem + kOffF + wave * kInfWave;
+    uint16_t *sF = reinterpret_cast<uint16_t *>(mine);
+    uint16_t *sHa = reinterpret_cast<uint16_t *>(mine + 16 * kSF * 2);
+    uint16_t *sHb = reinterpret_cast<uint16_t *>(mine + 16 * kSF * 2 + 16 * kSH * 2);
+    const int64_t nblk = (n + 15) / 16;
+    for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < nblk; blk += (int64_t)gridDim.x * kWaves) {
+        const int64_t ray = blk * 16 + r16;
+        const bool valid = ray < n;
+        wave_sync();
+        const bool act = wave_features(o, d, valid ? ray : 0, valid, sF, r16);
+        wave_sync();
+        fwd_layer<kFeat, 4>(sF, kSF, sW + kLW1, kSF, sB, sHa, kSH, 0);
+        wave_sync();
+        fwd_layer<kHidden, 4>(sHa, kSH, sW + kLW2, kSH, sB + 64, sHb, kSH, 0);
+        wave_sync();
+        fwd_layer<kHidden, 4>(sHb, kSH, sW + kLW3, kSH, sB + 128, sHa, kSH, 0);
+        wave_sync();
+        fwd_layer<kHidden, 4>(sHa, kSH, sW + kLW4, kSH, sB + 192, sHb, kSH, 0);
+        wave_sync();
+        const f32x4 y = out_layer(sHb, kSH, sW + kLW5, sB + 256, 0);
+        bool fb = false;
+        if (q4 == 0 && valid) {
+            float L[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) L[c] = act ? fmaxf(expf(y[c]) - kEpsOut, 0.0f) : 0.0f;
+            int bin = 0;
+            if (act && mode != 0) {
+                float x6[6];
+                float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
+                float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
+                sphere_x6(oo, dd, x6);
+                bin = trust_bin(x6);
+            }
+            if (mode == 2) {
+                if (act) {
+                    double e2 = 0.0, r2 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double rc = ref[3 * ray + c];
+                        e2 += ((double)L[c] - rc) * ((double)L[c] - rc);
+                        r2 += rc * rc;
+                    }
+                    atomicAdd(terr + bin, e2);
+                    atomicAdd(tref + bin, r2);
+                    atomicAdd(tcnt + bin, 1u);
+                }
+            } else {
+                fb = mode == 1 && act && !trust[bin];
+                if (!fb) {
+                    rgb[3 * ray] = L[0];
+                    rgb[3 * ray + 1] = L[1];
+                    rgb[3 * ray + 2] = L[2];
+                }
+                if (used_fb) used_fb[ray] = fb ? 1 : 0;
+            }
+        }
+        if (mode == 1) {
+            const uint64_t mask = __ballot(fb);
+            if (mask) {
+                const int leader = __ffsll((unsigned long long)mask) - 1;
+                unsigned long long b = 0;
+                if (lane == leader) b = atomicAdd(fb_count, (unsigned long long)__popcll(mask));
+                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, leader);
+                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), leader);
+                b = ((unsigned long long)hi << 32) | lo;
+                const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
+                if (fb) fb_list[b + __popcll(below)] = ray;
+            }
+        }
+    }
+}
+
+__global__ void k_trust_finalize(const double *terr, const double *tref, const unsigned *tcnt, float max_rel,
+                                 float abs_floor, unsigned min_count, uint8_t *trust) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= kTrustBins) return;
+    const double cnt = tcnt[b];
+    const bool ok = tcnt[b] >= min_count &&
+                    terr[b] <= (double)max_rel * max_rel * tref[b] + (double)abs_floor * abs_floor * cnt;
+    trust[b] = ok ? 1 : 0;
+}
+
+__global__ void k_zero_bytes(unsigned char *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+}  // namespace
+}  // namespace lq
+
+// ====================================================================== host
+struct lq_mlp {
+    int device;
+    float *theta, *m, *v;
+    uint16_t *wimg;
+    float *bias;
+    float *part;
+    int part_rows;
+    float *loss_part;
+    float *loss_dev;   // one float per step of the current training call
+    int64_t loss_cap;
+    uint8_t *trust;
+    bool has_trust;
+    int64_t step;
+    uint64_t seed;
+    int max_wg_train;
+};
+
+namespace lq {
+
+static lq_status mfail(lq_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+static lq_status mhip(hipError_t e, const char *what) {
+    return mfail(LQ_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// SplitMix64: a counter-based generator, one draw per parameter index
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static void he_uniform_init(uint64_t seed, std::vector<float> &th) {
+    th.assign(kParams, 0.0f);
+    const int ins[5] = {kFeat, kHidden, kHidden, kHidden, kHidden};
+    const int outs[5] = {kHidden, kHidden, kHidden, kHidden, kOut};
+    const int woff[5] = {kW1, kW2, kW3, kW4, kW5};
+    for (int l = 0; l < 5; ++l) {
+        const double lim = sqrt(6.0 / ins[l]);
+        for (int i = 0; i < ins[l] * outs[l]; ++i) {
+            const uint64_t r = splitmix64(seed * 0x100000001B3ull + (uint64_t)(woff[l] + i));
+            const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
+            th[woff[l] + i] = (float)((2.0 * u - 1.0) * lim);
+        }
+    }
+}
+
+static void free_mlp(lq_mlp *p) {
+    if (!p) return;
+    (void)hipFree(p->theta);
+    (void)hipFree(p->m);
+    (void)hipFree(p->v);
+    (void)hipFree(p->wimg);
+    (void)hipFree(p->bias);
+    (void)hipFree(p->part);
+    (void)hipFree(p->loss_part);
+    (void)hipFree(p->loss_dev);
+    (void)hipFree(p->trust);
+    delete p;
+}
+
+static lq_status alloc_mlp(int device, lq_mlp **out) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return mfail(LQ_ERR_HIP, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev) return mfail(LQ_ERR_INVALID_ARG, "device index out of range");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return mhip(e, "hipSetDevice");
+    lq_mlp *p = new (std::nothrow) lq_mlp();
+    if (!p) return mfail(LQ_ERR_OOM, "host allocation failed");
+    memset(p, 0, sizeof(*p));
+    p->device = device;
+    int cus = 1;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    p->max_wg_train = cus > 0 ? cus : 1;
+    p->part_rows = p->max_wg_train;
+    bool ok = hipMalloc((void **)&p->theta, kParams * 4) == hipSuccess &&
+              hipMalloc((void **)&p->m, kParams * 4) == hipSuccess &&
+              hipMalloc((void **)&p->v, kParams * 4) == hipSuccess &&
+              hipMalloc((void **)&p->wimg, kImage * 2) == hipSuccess &&
+              hipMalloc((void **)&p->bias, kBiasPad * 4) == hipSuccess &&
+              hipMalloc((void **)&p->part, (size_t)p->part_rows * kParams * 4) == hipSuccess &&
+              hipMalloc((void **)&p->loss_part, (size_t)p->part_rows * 4) == hipSuccess &&
+              hipMalloc((void **)&p->trust, kTrustBins) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_mlp(p);
+        return mfail(LQ_ERR_OOM, "device allocation for the surrogate failed");
+    }
+    if (hipFuncSetAttribute((const void *)k_train_step, hipFuncAttributeMaxDynamicSharedMemorySize, kTrainLds) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, kInfLds) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        free_mlp(p);
+        return mfail(LQ_ERR_UNSUPPORTED, "the device cannot give the kernels their LDS");
+    }
+    *out = p;
+    return LQ_OK;
+}
+
+static lq_status upload_params(lq_mlp *p, const float *host_theta, bool reset_moments) {
+    hipError_t e = hipMemcpy(p->theta, host_theta, kParams * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && reset_moments) e = hipMemset(p->m, 0, kParams * 4);
+    if (e == hipSuccess && reset_moments) e = hipMemset(p->v, 0, kParams * 4);
+    if (e != hipSuccess) return mhip(e, "uploading parameters");
+    hipLaunchKernelGGL(k_pack, dim3((kImage + 255) / 256), dim3(256), 0, 0, p->theta, p->wimg, p->bias);
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return mhip(e, "packing parameters");
+    return LQ_OK;
+}
+
+static lq_status check_dev_ptr(const void *ptr, size_t bytes, int device, const char *name) {
+    if (!ptr) return mfail(LQ_ERR_INVALID_ARG, std::string(name) + " is NULL");
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return mfail(LQ_ERR_INVALID_ARG, std::string(name) + " is not a device pointer");
+    }
+    if ((at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) || at.device != device)
+        return mfail(LQ_ERR_INVALID_ARG, std::string(name) + " is not a device pointer on the surrogate's device");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return mfail(LQ_ERR_INVALID_ARG, std::string(name) + ": allocation range unknown");
+    }
+    if ((const char *)ptr + bytes > (const char *)base + size)
+        return mfail(LQ_ERR_INVALID_ARG, std::string(name) + " is smaller than the batch needs");
+    if ((uintptr_t)ptr % 4) return mfail(LQ_ERR_INVALID_ARG, std::string(name) + " is not 4-byte aligned");
+    return LQ_OK;
+}
+
+// one forward/backward over samples [base, base + count) of the pair set
+static hipError_t launch_step(lq_mlp *p, const float *o, const float *d, const float *t, int64_t n_pairs,
+                              int64_t base, int64_t count, int &rows, hipStream_t s) {
+    const int64_t tiles_total = (count + kTile - 1) / kTile;
+    int64_t wg = std::min<int64_t>(tiles_total, p->max_wg_train);
+    const int tiles = (int)((tiles_total + wg - 1) / wg);
+    wg = (tiles_total + tiles - 1) / tiles;
+    rows = (int)wg;
+    hipLaunchKernelGGL(k_train_step, dim3((unsigned)wg), dim3(256), kTrainLds, s, o, d, t, n_pairs, base, count,
+                       tiles, 1.0f / (float)count, p->wimg, p->bias, p->part, p->loss_part);
+    return hipGetLastError();
+}
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" {
+
+lq_status lq_mlp_create(const lq_mlp_config *cfg, uint64_t seed, int device, lq_mlp **out) {
+    if (!out) return mfail(LQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (cfg && (cfg->n_freq != kFreq || cfg->hidden != kHidden || cfg->n_hidden_layers != 4))
+        return mfail(LQ_ERR_UNSUPPORTED, "the surrogate is built for 10 frequencies and 4 x 64 hidden units");
+    lq_mlp *p = nullptr;
+    lq_status st = alloc_mlp(device, &p);
+    if (st != LQ_OK) return st;
+    p->seed = seed;
+    std::vector<float> th;
+    he_uniform_init(seed, th);
+    st = upload_params(p, th.data(), true);
+    if (st != LQ_OK) {
+        free_mlp(p);
+        return st;
+    }
+    *out = p;
+    return LQ_OK;
+}
+
+void lq_mlp_free(lq_mlp *p) {
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    free_mlp(p);
+    (void)hipSetDevice(cur);
+}
+
+int32_t lq_mlp_num_params(void) { return kParams; }
+
+lq_status lq_mlp_get_params(const lq_mlp *p, float *host_theta) {
+    if (!p || !host_theta) return mfail(LQ_ERR_INVALID_ARG, "NULL argument");
+    (void)hipSetDevice(p->device);
+    hipError_t e = hipMemcpy(host_theta, p->theta, kParams * 4, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? LQ_OK : mhip(e, "reading parameters");
+}
+
+lq_status lq_mlp_set_params(lq_mlp *p, const float *host_theta) {
+    if (!p || !host_theta) return mfail(LQ_ERR_INVALID_ARG, "NULL argument");
+    (void)hipSetDevice(p->device);
+    p->step = 0;
+    return upload_params(p, host_theta, true);
+}
+
+lq_status lq_mlp_grad(lq_mlp *p, const float *o, const float *d, const float *rgb, int64_t n, float *grad,
+                      float *loss_host, void *stream) {
+    if (!p) return mfail(LQ_ERR_INVALID_ARG, "surrogate is NULL");
+    if (n <= 0) return mfail(LQ_ERR_INVALID_ARG, "n must be > 0");
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return mhip(e, "hipSetDevice");
+    lq_status st;
+    if ((st = check_dev_ptr(o, n * 12, p->device, "origins")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(grad, kParams * 4, p->device, "grad")) != LQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    float *loss_dev = nullptr;
+    if ((e = hipMallocAsync((void **)&loss_dev, 4, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
+    int rows = 0;
+    e = launch_step(p, o, d, rgb, n, 0, n, rows, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, p->part, rows, p->theta,
+                           p->m, p->v, p->wimg, p->bias, p->loss_part, loss_dev, grad, 0, 0.0f, 0.0f, 0.0f, 0.0f,
+                           0.0f, 0.0f);
+        e = hipGetLastError();
+    }
+    float lh = 0.0f;
+    if (e == hipSuccess && loss_host) e = hipMemcpyAsync(&lh, loss_dev, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(loss_dev, s);
+    if (e != hipSuccess) return mhip(e, "surrogate gradient");
+    if (loss_host) *loss_host = lh;
+    return LQ_OK;
+}
+
+lq_status lq_mlp_train(lq_mlp *p, const float *o, const float *d, const float *rgb, int64_t n_pairs,
+                       const lq_train_config *cfg, float *loss_log_host, void *stream) {
+    if (!p || !cfg) return mfail(LQ_ERR_INVALID_ARG, "NULL argument");
+    if (n_pairs <= 0) return mfail(LQ_ERR_INVALID_ARG, "n_pairs must be > 0");
+    if (cfg->steps < 0 || cfg->batch <= 0 || cfg->batch % kTile || cfg->total_steps <= 0)
+        return mfail(LQ_ERR_INVALID_ARG, "steps >= 0, batch a positive multiple of 64, total_steps > 0");
+    if (!(cfg->lr0 > 0.0f) || !(cfg->lr1 > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+        return mfail(LQ_ERR_INVALID_ARG, "bad optimiser settings");
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return mhip(e, "hipSetDevice");
+    lq_status st;
+    if ((st = check_dev_ptr(o, n_pairs * 12, p->device, "origins")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(d, n_pairs * 12, p->device, "dirs")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(rgb, n_pairs * 12, p->device, "rgb")) != LQ_OK) return st;
+    if (cfg->steps == 0) return LQ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    float *loss_dev = nullptr;
+    if ((e = hipMallocAsync((void **)&loss_dev, (size_t)cfg->steps * 4, s)) != hipSuccess)
+        return mhip(e, "hipMallocAsync");
+    for (int k = 0; k < cfg->steps && e == hipSuccess; ++k) {
+        const int64_t gstep = p->step;   // global step index (0-based)
+        const int64_t base = (int64_t)((gstep * (int64_t)cfg->batch) % n_pairs);
+        int rows = 0;
+        e = launch_step(p, o, d, rgb, n_pairs, base, cfg->batch, rows, s);
+        if (e != hipSuccess) break;
+        const double frac = (double)gstep / (double)cfg->total_steps;
+        const float lr = (float)(cfg->lr0 * pow((double)cfg->lr1 / cfg->lr0, frac));
+        const double t = (double)(gstep + 1);
+        const float c1 = (float)(1.0 / (1.0 - pow((double)cfg->beta1, t)));
+        const float c2 = (float)(1.0 / (1.0 - pow((double)cfg->beta2, t)));
+        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, p->part, rows, p->theta,
+                           p->m, p->v, p->wimg, p->bias, p->loss_part, loss_dev + k, (float *)nullptr, 1, lr,
+                           cfg->beta1, cfg->beta2, cfg->eps, c1, c2);
+        e = hipGetLastError();
+        p->step++;
+    }
+    if (e == hipSuccess && loss_log_host)
+        e = hipMemcpyAsync(loss_log_host, loss_dev, (size_t)cfg->steps * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && loss_log_host) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(loss_dev, s);
+    if (e != hipSuccess) return mhip(e, "surrogate training");
+    return LQ_OK;
+}
+
+}  // extern "C"
+
+namespace lq {
+
+static int infer_grid(int device) {
+    int cus = 1;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    return (cus > 0 ? cus : 1) * 2;
+}
+
+}  // namespace lq
+
+extern "C" {
+
+lq_status lq_mlp_forward(const lq_mlp *p, const float *o, const float *d, int64_t n, float *rgb, void *stream) {
+    if (!p) return mfail(LQ_ERR_INVALID_ARG, "surrogate is NULL");
+    if (n < 0) return mfail(LQ_ERR_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return LQ_OK;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return mhip(e, "hipSetDevice");
+    lq_status st;
+    if ((st = check_dev_ptr(o, n * 12, p->device, "origins")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), kInfLds, (hipStream_t)stream, o, d, n,
+                       p->wimg, p->bias, 0, (const uint8_t *)nullptr, rgb, (uint8_t *)nullptr, (int64_t *)nullptr,
+                       (unsigned long long *)nullptr, (const float *)nullptr, (double *)nullptr, (double *)nullptr,
+                       (unsigned *)nullptr);
+    e = hipGetLastError();
+    return e == hipSuccess ? LQ_OK : mhip(e, "surrogate forward");
+}
+
+lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const float *rgb_ref, int64_t n,
+                             float max_rel_err, void *stream) {
+    if (!p) return mfail(LQ_ERR_INVALID_ARG, "surrogate is NULL");
+    if (n <= 0 || !(max_rel_err > 0.0f)) return mfail(LQ_ERR_INVALID_ARG, "n > 0 and max_rel_err > 0 required");
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return mhip(e, "hipSetDevice");
+    lq_status st;
+    if ((st = check_dev_ptr(o, n * 12, p->device, "origins")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(rgb_ref, n * 12, p->device, "rgb_ref")) != LQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)kTrustBins * (8 + 8 + 4);
+    unsigned char *acc = nullptr;
+    if ((e = hipMallocAsync((void **)&acc, bytes, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
+    double *terr = reinterpret_cast<double *>(acc);
+    double *tref = terr + kTrustBins;
+    unsigned *tcnt = reinterpret_cast<unsigned *>(tref + kTrustBins);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), kInfLds, s, o, d, n, p->wimg, p->bias, 2,
+                       (const uint8_t *)nullptr, (float *)nullptr, (uint8_t *)nullptr, (int64_t *)nullptr,
+                       (unsigned long long *)nullptr, rgb_ref, terr, tref, tcnt);
+    hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tref, tcnt,
+                       max_rel_err, 1e-3f, 4u, p->trust);
+    e = hipGetLastError();
+    (void)hipFreeAsync(acc, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return mhip(e, "building the trust map");
+    p->has_trust = true;
+    return LQ_OK;
+}
+
+lq_status lq_mlp_trust_map(const lq_mlp *p, uint8_t *host_map, int32_t *n_bins) {
+    if (!p) return mfail(LQ_ERR_INVALID_ARG, "surrogate is NULL");
+    if (n_bins) *n_bins = p->has_trust ? kTrustBins : 0;
+    if (!host_map || !p->has_trust) return LQ_OK;
+    (void)hipSetDevice(p->device);
+    hipError_t e = hipMemcpy(host_map, p->trust, kTrustBins, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? LQ_OK : mhip(e, "reading the trust map");
+}
+
+lq_status lq_mlp_infer(const lq_mlp *p, const lq_octree *fallback, const float *o, const float *d, int64_t n,
+                       float *rgb, uint8_t *used_fallback, void *stream) {
+    if (!p) return mfail(LQ_ERR_INVALID_ARG, "surrogate is NULL");
+    if (n < 0) return mfail(LQ_ERR_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return LQ_OK;
+    if (!p->has_trust || !fallback) {
+        if (used_fallback) return mfail(LQ_ERR_STATE, "no trust map or fallback tree: nothing falls back");
+        return lq_mlp_forward(p, o, d, n, rgb, stream);
+    }
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return mhip(e, "hipSetDevice");
+    lq_status st;
+    if ((st = check_dev_ptr(o, n * 12, p->device, "origins")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
+    if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
+    if (used_fallback && (st = check_dev_ptr(used_fallback, n, p->device, "used_fallback")) != LQ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *scratch = nullptr;
+    const size_t bytes = 8 + (size_t)n * 8;
+    if ((e = hipMallocAsync((void **)&scratch, bytes, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(scratch);
+    int64_t *list = reinterpret_cast<int64_t *>(scratch + 8);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, s, scratch, (size_t)8);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), kInfLds, s, o, d, n, p->wimg, p->bias, 1,
+                       p->trust, rgb, used_fallback, list, cnt, (const float *)nullptr, (double *)nullptr,
+                       (double *)nullptr, (unsigned *)nullptr);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        lq_status q = query_indexed(fallback, o, d, n, list, cnt, rgb, s);
+        if (q != LQ_OK) {
+            (void)hipFreeAsync(scratch, s);
+            return q;
+        }
+    }
+    (void)hipFreeAsync(scratch, s);
+    return e == hipSuccess ? LQ_OK : mhip(e, "surrogate inference");
+}
+
+lq_status lq_mlp_save(const lq_mlp *p, const char *path) {
+    if (!p || !path) return mfail(LQ_ERR_INVALID_ARG, "NULL argument");
+    (void)hipSetDevice(p->device);
+    std::vector<float> buf((size_t)3 * kParams);
+    std::vector<uint8_t> trust(kTrustBins, 0);
+    hipError_t e = hipMemcpy(buf.data(), p->theta, kParams * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(buf.data() + kParams, p->m, kParams * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(buf.data() + 2 * kParams, p->v, kParams * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && p->has_trust) e = hipMemcpy(trust.data(), p->trust, kTrustBins, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return mhip(e, "reading the surrogate");
+    FILE *f = fopen(path, "wb");
+    if (!f) return mfail(LQ_ERR_IO, std::string("cannot write ") + path);
+    const uint32_t hdr[4] = {0x504D514Cu /* "LQMP" */, 1u, (uint32_t)kParams, p->has_trust ? 1u : 0u};
+    const int64_t meta[2] = {p->step, (int64_t)p->seed};
+    bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(meta, sizeof(meta), 1, f) == 1 &&
+              fwrite(buf.data(), 4, buf.size(), f) == buf.size() &&
+              fwrite(trust.data(), 1, trust.size(), f) == trust.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? LQ_OK : mfail(LQ_ERR_IO, std::string("short write to ") + path);
+}
+
+lq_status lq_mlp_load(const char *path, int device, lq_mlp **out) {
+    if (!out || !path) return mfail(LQ_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return mfail(LQ_ERR_IO, std::string("cannot open ") + path);
+    uint32_t hdr[4];
+    int64_t meta[2];
+    std::vector<float> buf((size_t)3 * kParams);
+    std::vector<uint8_t> trust(kTrustBins);
+    bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x504D514Cu && hdr[1] == 1u &&
+              hdr[2] == (uint32_t)kParams && fread(meta, sizeof(meta), 1, f) == 1 &&
+              fread(buf.data(), 4, buf.size(), f) == buf.size() &&
+              fread(trust.data(), 1, trust.size(), f) == trust.size();
+    fclose(f);
+    if (!ok) return mfail(LQ_ERR_FORMAT, std::string("not a surrogate file: ") + path);
+    lq_mlp *p = nullptr;
+    lq_status st = alloc_mlp(device, &p);
+    if (st != LQ_OK) return st;
+    p->step = meta[0];
+    p->seed = (uint64_t)meta[1];
+    hipError_t e = hipMemcpy(p->m, buf.data() + kParams, kParams * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->v, buf.data() + 2 * kParams, kParams * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->trust, trust.data(), kTrustBins, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_mlp(p);
+        return mhip(e, "uploading the surrogate");
+    }
+    st = upload_params(p, buf.data(), false);
+    if (st != LQ_OK) {
+        free_mlp(p);
+        return st;
+    }
+    p->has_trust = hdr[3] != 0;
+    *out = p;
+    return LQ_OK;
+}
+
+}  // extern "C"

@@ -57,9 +57,10 @@ __device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool
 
 __device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; }
 
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
-__global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
-                                                  unsigned long long *queue) {
+// the persistent loop shared by the single- and multi-tree kernels;
+// tree_of(ray) returns the DevTree a ray queries
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, class TreeOf>
+__device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeOf tree_of) {
     __shared__ int32_t s_path[10 * kBlock];   // per-lane node path, [level][lane]
     int32_t *path = s_path + threadIdx.x;
     Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryAr
     uint32_t *ids = nullptr;
     int cur = blockIdx.x % kXcds;   // range this wave draws from (wave-uniform)
     unsigned used_up = 0;           // ranges known to be exhausted (wave-uniform)
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
     for (;;) {
         bool want = ray < 0 && used_up != kAllRanges;
         uint64_t need = __ballot(want);
@@ -80,14 +82,14 @@ __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryAr
                 const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
                 const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
                 base = ((unsigned long long)hi << 32) | lo;
-                const int64_t start = range_begin(cur, a.n);
-                const int64_t len = range_begin(cur + 1, a.n) - start;
+                const int64_t start = range_begin(cur, n);
+                const int64_t len = range_begin(cur + 1, n) - start;
                 if (want) {
                     const int64_t slot = (int64_t)base + __popcll(need & lanemask_lt());
                     if (slot < len) {
-                        const int64_t idx = start + slot;
+                        const int64_t idx = a.index ? a.index[start + slot] : start + slot;
                         ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)idx * a.max_ids : nullptr;
-                        if (m.init(t, a.o + 3 * idx, a.d + 3 * idx)) {
+                        if (m.init(tree_of(idx), a.o + 3 * idx, a.d + 3 * idx)) {
                             ray = idx;
                             want = false;
                         } else {
@@ -108,12 +110,35 @@ __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryAr
         }
         if (__all(ray < 0 && used_up == kAllRanges)) break;
         for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
-            if (m.step(t, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock)) {
+            if (m.step(tree_of(ray), a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock)) {
                 write_ray(a, ray, m, TRACE);
                 ray = -1;
             }
         }
     }
+}
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+__global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
+                                                  unsigned long long *queue) {
+    persistent_query<ST, DEG, ACC64, TRACE, SKIP>(a, queue, [&](int64_t) -> const DevTree & { return t; });
+}
+
+// several trees: rays [offsets[k], offsets[k+1]) query trees[k]
+template <int ST, int DEG, bool ACC64, bool SKIP>
+__global__ __launch_bounds__(kBlock) void k_query_multi(const DevTree *trees, const int64_t *offsets,
+                                                        int n_trees, const QueryArgs a,
+                                                        unsigned long long *queue) {
+    auto tree_of = [&](int64_t ray) -> const DevTree & {
+        int lo = 0, hi = n_trees;            // offsets[lo] <= ray < offsets[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (offsets[mid] <= ray) lo = mid;
+            else hi = mid;
+        }
+        return trees[lo];
+    };
+    persistent_query<ST, DEG, ACC64, false, SKIP>(a, queue, tree_of);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
@@ -180,9 +205,57 @@ hipError_t launch_st(const DevTree &t, const QueryArgs &a, bool trace, hipStream
     return hipErrorInvalidValue;
 }
 
+template <int ST, int DEG, bool ACC64, bool SKIP>
+hipError_t launch_multi_one(const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                            hipStream_t s) {
+    auto kern = k_query_multi<ST, DEG, ACC64, SKIP>;
+    const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
+    const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
+    unsigned long long *queue = nullptr;
+    hipError_t e = hipMallocAsync((void **)&queue, kXcds * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kXcds), 0, s, queue);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, trees, offsets, n_trees, a, queue);
+    e = hipGetLastError();
+    hipError_t f = hipFreeAsync(queue, s);
+    return e != hipSuccess ? e : f;
+}
+
+template <int ST, int DEG>
+hipError_t launch_multi_deg(const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                            hipStream_t s) {
+    const bool acc64 = (a.flags & LQ_FP64_ACCUM) != 0;
+    const bool full = (a.flags & LQ_NO_SIGMA_SKIP) != 0;
+    if (full) return acc64 ? launch_multi_one<ST, DEG, true, false>(trees, offsets, n_trees, a, s)
+                           : launch_multi_one<ST, DEG, false, false>(trees, offsets, n_trees, a, s);
+    return acc64 ? launch_multi_one<ST, DEG, true, true>(trees, offsets, n_trees, a, s)
+                 : launch_multi_one<ST, DEG, false, true>(trees, offsets, n_trees, a, s);
+}
+
+template <int ST>
+hipError_t launch_multi_st(int deg, const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                           hipStream_t s) {
+    switch (deg) {
+        case 2: return launch_multi_deg<ST, 2>(trees, offsets, n_trees, a, s);
+        case 3: return launch_multi_deg<ST, 3>(trees, offsets, n_trees, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 int row_bytes(int storage, int K) { return row_bytes_for(storage == LQ_F32 ? 4 : 2, K); }
+
+hipError_t launch_query_multi(int storage, int sh_degree, const DevTree *trees, const int64_t *offsets, int n_trees,
+                              const QueryArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    switch (storage) {
+        case LQ_F32: return launch_multi_st<LQ_F32>(sh_degree, trees, offsets, n_trees, a, s);
+        case LQ_F16: return launch_multi_st<LQ_F16>(sh_degree, trees, offsets, n_trees, a, s);
+        case LQ_BF16: return launch_multi_st<LQ_BF16>(sh_degree, trees, offsets, n_trees, a, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_query(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s) {
     if (a.n == 0) return hipSuccess;

@@ -167,3 +167,156 @@ class Octree:
 
 def version() -> str:
     return lib().lq_version().decode()
+
+
+# ------------------------------------------------------------------ surrogate
+class MlpConfig(C.Structure):
+    _fields_ = [("n_freq", C.c_int32), ("hidden", C.c_int32), ("n_hidden_layers", C.c_int32)]
+
+
+class TrainConfig(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("total_steps", C.c_int32), ("batch", C.c_int32),
+                ("lr0", C.c_float), ("lr1", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+_mlp_ready = False
+
+
+def _mlp_lib():
+    global _mlp_ready
+    L = lib()
+    if not _mlp_ready:
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.lq_mlp_create.argtypes = [C.POINTER(MlpConfig), C.c_uint64, C.c_int, C.POINTER(vp)]
+        L.lq_mlp_free.argtypes = [vp]
+        L.lq_mlp_free.restype = None
+        L.lq_mlp_num_params.restype = C.c_int32
+        L.lq_mlp_get_params.argtypes = [vp, vp]
+        L.lq_mlp_set_params.argtypes = [vp, vp]
+        L.lq_mlp_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(TrainConfig), vp, vp]
+        L.lq_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, C.POINTER(C.c_float), vp]
+        L.lq_mlp_forward.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.lq_mlp_build_trust.argtypes = [vp, vp, vp, vp, i64, C.c_float, vp]
+        L.lq_mlp_trust_map.argtypes = [vp, vp, C.POINTER(i32)]
+        L.lq_mlp_infer.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+        L.lq_mlp_save.argtypes = [vp, C.c_char_p]
+        L.lq_mlp_load.argtypes = [C.c_char_p, C.c_int, C.POINTER(vp)]
+        L.lq_query_radiance_multi.argtypes = [C.POINTER(vp), i32, vp, vp, vp, vp, vp, C.c_int,
+                                              C.c_uint32, vp]
+        for name in ("lq_mlp_create", "lq_mlp_get_params", "lq_mlp_set_params", "lq_mlp_train",
+                     "lq_mlp_grad", "lq_mlp_forward", "lq_mlp_build_trust", "lq_mlp_trust_map",
+                     "lq_mlp_infer", "lq_mlp_save", "lq_mlp_load", "lq_query_radiance_multi"):
+            getattr(L, name).restype = C.c_int
+        _mlp_ready = True
+    return L
+
+
+class Surrogate:
+    """The learned surrogate (Fourier features + 4 x 64 MLP) on one GPU."""
+
+    def __init__(self, seed: int = 31, device: int = 0, path: str | None = None):
+        L = _mlp_lib()
+        self.handle = C.c_void_p()
+        self.device = device
+        if path is not None:
+            check(L.lq_mlp_load(os.fsencode(path), device, C.byref(self.handle)))
+        else:
+            cfg = MlpConfig(10, 64, 4)
+            check(L.lq_mlp_create(C.byref(cfg), seed, device, C.byref(self.handle)))
+        self.n_params = int(L.lq_mlp_num_params())
+
+    def free(self):
+        if self.handle:
+            _mlp_lib().lq_mlp_free(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        check(_mlp_lib().lq_mlp_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, theta) -> None:
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        assert theta.shape == (self.n_params,)
+        check(_mlp_lib().lq_mlp_set_params(self.handle, theta.ctypes.data))
+
+    def train(self, origins, dirs, rgb, steps: int, total_steps: int | None = None,
+              batch: int = 65536, lr0: float = 5e-4, lr1: float = 5e-6, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, log: bool = True, stream=None):
+        cfg = TrainConfig(steps, total_steps or steps, batch, lr0, lr1, beta1, beta2, eps)
+        losses = np.zeros(max(steps, 1), np.float32) if log else None
+        check(_mlp_lib().lq_mlp_train(self.handle, _ptr(origins), _ptr(dirs), _ptr(rgb),
+                                      origins.shape[0], C.byref(cfg),
+                                      losses.ctypes.data if log else None, _stream(stream)))
+        return losses[:steps] if log else None
+
+    def grad(self, origins, dirs, rgb, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=origins.device)
+        loss = C.c_float()
+        check(_mlp_lib().lq_mlp_grad(self.handle, _ptr(origins), _ptr(dirs), _ptr(rgb),
+                                     origins.shape[0], _ptr(g), C.byref(loss), _stream(stream)))
+        return float(loss.value), g
+
+    def forward(self, origins, dirs, rgb=None, stream=None):
+        import torch
+        n = origins.shape[0]
+        if rgb is None:
+            rgb = torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+        check(_mlp_lib().lq_mlp_forward(self.handle, _ptr(origins), _ptr(dirs), n, _ptr(rgb),
+                                        _stream(stream)))
+        return rgb
+
+    def build_trust(self, origins, dirs, rgb_ref, max_rel_err: float = 0.01, stream=None):
+        check(_mlp_lib().lq_mlp_build_trust(self.handle, _ptr(origins), _ptr(dirs), _ptr(rgb_ref),
+                                            origins.shape[0], max_rel_err, _stream(stream)))
+
+    def trust_map(self) -> np.ndarray | None:
+        nb = C.c_int32()
+        check(_mlp_lib().lq_mlp_trust_map(self.handle, None, C.byref(nb)))
+        if nb.value == 0:
+            return None
+        out = np.zeros(nb.value, np.uint8)
+        check(_mlp_lib().lq_mlp_trust_map(self.handle, out.ctypes.data, C.byref(nb)))
+        return out
+
+    def infer(self, origins, dirs, fallback: "Octree | None", rgb=None, want_used: bool = True,
+              stream=None):
+        import torch
+        n = origins.shape[0]
+        if rgb is None:
+            rgb = torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+        used = torch.empty((n,), dtype=torch.uint8, device=origins.device) if want_used else None
+        check(_mlp_lib().lq_mlp_infer(self.handle, fallback.handle if fallback else None,
+                                      _ptr(origins), _ptr(dirs), n, _ptr(rgb), _ptr(used),
+                                      _stream(stream)))
+        return rgb, used
+
+    def save(self, path: str) -> None:
+        check(_mlp_lib().lq_mlp_save(self.handle, os.fsencode(path)))
+
+
+def query_multi(trees, offsets, origins, dirs, model: str = "linear", flags: int = 0,
+                rgb=None, alpha=None, stream=None):
+    """One launch over several luminaires: rays [offsets[k], offsets[k+1])
+    query trees[k] (Octree objects)."""
+    import torch
+    L = _mlp_lib()
+    n = origins.shape[0]
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    assert offs.shape == (len(trees) + 1,) and offs[-1] == n
+    handles = (C.c_void_p * len(trees))(*[t.handle.value for t in trees])
+    if rgb is None:
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+    if alpha is None:
+        alpha = torch.empty((n,), dtype=torch.float32, device=origins.device)
+    check(L.lq_query_radiance_multi(handles, len(trees), offs.ctypes.data, _ptr(origins), _ptr(dirs),
+                                    _ptr(rgb), _ptr(alpha), MODEL[model], flags, _stream(stream)))
+    return rgb, alpha

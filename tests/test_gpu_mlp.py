@@ -1,0 +1,212 @@
+"""GPU surrogate (forward, backward, Adam, training, trust map, fallback)
+against the FP64 oracle, and the multi-luminaire query."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import core, mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import torch
+    import paper_2207_05009_amd as lq
+    assert torch.cuda.is_available()
+    lq.lib()
+    return lq
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _rays(n, seed):
+    return inputs.rays.room_to_proxy(n, seed)
+
+
+def _theta(seed, scale=1.0):
+    th = omlp.he_uniform(seed) * scale
+    th[-3:] = 0.5
+    return th.astype(np.float32)
+
+
+def test_forward_matches_oracle(lq):
+    import torch
+    o, d = _rays(4096, 1)
+    sur = lq.Surrogate(seed=1)
+    th = _theta(2)
+    sur.set_params(th)
+    _say("surrogate forward")
+    g = sur.forward(_dev(o), _dev(d))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    # same bfloat16 rounding of weights and GEMM inputs as the kernel
+    ref, hit = omlp.predict(th.astype(np.float64), o, d, round_bf16=omlp.bf16)
+    # compare the network output y = log(L + 0.01): a one-ulp bfloat16
+    # difference early in the network moves y by ~1e-2 at most
+    y_g = np.log(g[hit] + omlp.EPS_OUT)
+    y_r = np.log(ref[hit] + omlp.EPS_OUT)
+    dy = np.abs(y_g - y_r)
+    _say(f"|dy| median {np.median(dy):.2e} p99 {np.quantile(dy, 0.99):.2e} max {dy.max():.2e}")
+    assert dy.max() < 3e-2 and np.median(dy) < 2e-3
+    # against the exact (unrounded) network: the stated bfloat16 error
+    exact, _ = omlp.predict(th.astype(np.float64), o, d)
+    rel_x = np.abs(g - exact) / np.maximum(np.abs(exact), 1e-2)
+    _say(f"bf16 network vs fp64 network: median {np.median(rel_x):.2e} max {rel_x.max():.2e}")
+    assert np.all(g[~hit] == 0)
+
+
+def test_gradient_matches_oracle(lq):
+    o, d = _rays(2048, 3)
+    tgt = np.exp(np.random.default_rng(4).uniform(-4, 5, size=(2048, 3))).astype(np.float32)
+    sur = lq.Surrogate(seed=1)
+    th = _theta(5, 0.7)
+    sur.set_params(th)
+    _say("surrogate gradient")
+    loss, g = sur.grad(_dev(o), _dev(d), _dev(tgt))
+    g = g.cpu().numpy().astype(np.float64)
+    x6, hit = omlp.sphere_param(o, d)
+    F = omlp.features(x6)
+    rl, rg = omlp.loss_and_grad(th.astype(np.float64), F, tgt.astype(np.float64), hit,
+                                round_bf16=omlp.bf16)
+    assert loss == pytest.approx(rl, rel=2e-2)
+    cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
+    rel_l2 = float(np.linalg.norm(g - rg) / np.linalg.norm(rg))
+    _say(f"gradient cosine {cos:.6f} rel-L2 {rel_l2:.3e}")
+    assert cos > 0.999 and rel_l2 < 3e-2
+    # layer by layer
+    off = 0
+    for i, o_ in omlp.LAYERS:
+        sl = slice(off, off + i * o_ + o_)
+        c = g[sl] @ rg[sl] / (np.linalg.norm(g[sl]) * np.linalg.norm(rg[sl]))
+        assert c > 0.998, (i, o_, c)
+        off += i * o_ + o_
+
+
+def test_adam_steps_match_oracle(lq):
+    o, d = _rays(1024, 6)
+    tgt = np.exp(np.random.default_rng(7).uniform(-3, 4, size=(1024, 3))).astype(np.float32)
+    sur = lq.Surrogate(seed=1)
+    th0 = _theta(8, 0.7)
+    sur.set_params(th0)
+    _say("three Adam steps")
+    sur.train(_dev(o), _dev(d), _dev(tgt), steps=3, total_steps=10, batch=1024, lr0=1e-3, lr1=1e-4)
+    th_gpu = sur.get_params().astype(np.float64)
+    x6, hit = omlp.sphere_param(o, d)
+    F = omlp.features(x6)
+    th = th0.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for k in range(3):
+        _, gr = omlp.loss_and_grad(th, F, tgt.astype(np.float64), hit, round_bf16=omlp.bf16)
+        th, m, v = omlp.adam_step(th, gr, m, v, k + 1, omlp.lr_at(k, 10, 1e-3, 1e-4))
+    du_gpu, du_ref = th_gpu - th0, th - th0
+    cos = du_gpu @ du_ref / (np.linalg.norm(du_gpu) * np.linalg.norm(du_ref))
+    _say(f"update cosine {cos:.5f}")
+    assert cos > 0.99
+    # Adam moves every parameter by about lr per step
+    assert np.median(np.abs(du_gpu)) == pytest.approx(np.median(np.abs(du_ref)), rel=0.1)
+
+
+def _training_set(lq, tree_oct, n, seed):
+    import torch
+    o, d = _rays(n, seed)
+    ot, dt = _dev(o), _dev(d)
+    rgb, _ = tree_oct.query(ot, dt)
+    torch.cuda.synchronize()
+    return ot, dt, rgb
+
+
+def test_training_reduces_loss_and_resume_is_bit_identical(lq, c0_tree, tmp_path):
+    import torch
+    oct_ = lq.Octree(c0_tree, "f32")
+    o, d, rgb = _training_set(lq, oct_, 1 << 18, 30)
+    _say("training 400 steps")
+    a = lq.Surrogate(seed=31)
+    la = a.train(o, d, rgb, steps=400, total_steps=800, batch=8192)
+    assert np.all(np.isfinite(la))
+    assert la[-50:].mean() < 0.5 * la[:10].mean(), (la[:10].mean(), la[-50:].mean())
+    # resume: 400 + (save, load) + 400 == 800 in one go
+    p = str(tmp_path / "s.lqmp")
+    a.save(p)
+    b = lq.Surrogate(path=p)
+    lb = b.train(o, d, rgb, steps=400, total_steps=800, batch=8192)
+    c = lq.Surrogate(seed=31)
+    lc = c.train(o, d, rgb, steps=800, total_steps=800, batch=8192)
+    assert np.array_equal(b.get_params(), c.get_params())
+    assert np.array_equal(np.concatenate([la, lb]), lc)
+    torch.cuda.synchronize()
+
+
+def test_trust_map_and_fallback(lq, c0_tree):
+    import torch
+    oct_ = lq.Octree(c0_tree, "f32")
+    o, d, rgb = _training_set(lq, oct_, 1 << 17, 40)
+    sur = lq.Surrogate(seed=3)
+    sur.train(o, d, rgb, steps=100, total_steps=100, batch=8192)
+    qo, qd = _rays(50000, 41)
+    qo, qd = _dev(qo), _dev(qd)
+    ref, _ = oct_.query(qo, qd)
+    plain = sur.forward(qo, qd)
+    # an impossible error bound: every ray falls back to the octree
+    _say("trust map, strict")
+    sur.build_trust(o, d, rgb, max_rel_err=1e-12)
+    tm = sur.trust_map()
+    assert tm is not None and tm.sum() == 0
+    out, used = sur.infer(qo, qd, oct_)
+    torch.cuda.synchronize()
+    hit = torch.from_numpy(omlp.sphere_param(qo.cpu().numpy(), qd.cpu().numpy())[1]).cuda()
+    assert torch.equal(used.bool(), hit)
+    assert torch.equal(out[hit], ref[hit])
+    assert bool((out[~hit] == 0).all())
+    # a loose bound: the bins with enough samples are trusted, those rays keep
+    # the surrogate's value
+    _say("trust map, loose")
+    sur.build_trust(o, d, rgb, max_rel_err=1e9)
+    tm = sur.trust_map()
+    assert tm.sum() > 0
+    out, used = sur.infer(qo, qd, oct_)
+    torch.cuda.synchronize()
+    u = used.bool()
+    assert torch.equal(out[~u], plain[~u])
+    assert torch.equal(out[u], ref[u])
+    assert float(u.float().mean()) < 0.5
+
+
+def test_multi_tree_query_matches_single(lq):
+    import torch
+    trees = [inputs.random_tree(dep, 0.3, seed=70 + dep, sh_degree=3) for dep in (2, 3, 4, 5)]
+    octs = [lq.Octree(t, "f16") for t in trees]
+    counts = [1000, 37, 5000, 2048]
+    rays = [_rays(c, 80 + k) for k, c in enumerate(counts)]
+    o = np.concatenate([r[0] for r in rays])
+    d = np.concatenate([r[1] for r in rays])
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    _say("multi-tree query")
+    for model in ("linear", "exp"):
+        rgb, alpha = lq.query_multi(octs, offs, _dev(o), _dev(d), model=model)
+        torch.cuda.synchronize()
+        for k, oc in enumerate(octs):
+            s = slice(offs[k], offs[k + 1])
+            r1, a1 = oc.query(_dev(o[s]), _dev(d[s]), model=model)
+            torch.cuda.synchronize()
+            assert torch.equal(rgb[s], r1) and torch.equal(alpha[s], a1), (model, k)
+    # and one of them against the oracle
+    k = 2
+    s = slice(offs[k], offs[k + 1])
+    orc = core.query(trees[k], o[s], d[s], model=0, storage="f16")
+    rgb, _ = lq.query_multi(octs, offs, _dev(o), _dev(d))
+    err = np.abs(rgb.cpu().numpy()[s] - orc["L"]) / np.maximum(np.abs(orc["L"]), 1e-6 * 2048)
+    amb = orc["alt_valid"].astype(bool)
+    assert err[~amb].max() < 1e-4
