@@ -39,7 +39,7 @@ def log(msg):
 def kernel_sources_hash():
     """Hash of the sources the query kernel is built from."""
     h = hashlib.sha1()
-    for name in ("octree_query.hip", "march.h", "lq_internal.h"):
+    for name in ("octree_kernels.h", "octree_query_f32.hip", "march.h", "lq_internal.h"):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:12]
@@ -116,6 +116,66 @@ def cpu_baseline(tree, o, d, budget_s):
                       f"with its OpenMP loop over rays, {t_total:.1f} s"}
 
 
+def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
+    """Learned surrogate: trained on (ray, radiance) pairs that the float32
+    octree renders for incoherent room rays, trust map from held-out pairs
+    at 1% relative error, then inference with octree fallback on the
+    16,777,216 room rays."""
+    import torch
+    import inputs
+    t0 = time.perf_counter()
+    o, d = inputs.rays.room_to_proxy(args.surrogate_pairs, 30)
+    ho, hd = inputs.rays.room_to_proxy(5_000_000, 32)
+    o, d, ho, hd = [torch.from_numpy(x).cuda() for x in (o, d, ho, hd)]
+    rgb, _ = oct32.query(o, d)
+    hrgb, _ = oct32.query(ho, hd)
+    qref, _ = oct32.query(qo, qd)
+    torch.cuda.synchronize()
+    log(f"surrogate data: {time.perf_counter() - t0:.1f} s")
+    sur = lumiq.Surrogate(seed=31)
+    lr0 = 5e-3
+    t0 = time.perf_counter()
+    losses = sur.train(o, d, rgb, steps=args.surrogate_steps, total_steps=args.surrogate_steps,
+                       batch=65536, lr0=lr0, lr1=lr0 / 100)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sur.build_trust(ho, hd, hrgb, max_rel_err=0.01)
+    del o, d, rgb, ho, hd, hrgb
+    n = qo.shape[0]
+    out = torch.empty_like(qref)
+    ms_fwd, _ = time_launches(lambda: sur.forward(qo, qd, rgb=out), 10, 2)
+    pred = out.clone()
+    used = torch.empty((n,), dtype=torch.uint8, device="cuda")
+
+    def hybrid():
+        lumiq.check(lumiq._mlp_lib().lq_mlp_infer(sur.handle, oct32.handle, lumiq._ptr(qo),
+                                                  lumiq._ptr(qd), n, lumiq._ptr(out),
+                                                  lumiq._ptr(used), lumiq._stream(None)))
+
+    ms_hyb, _ = time_launches(hybrid, 10, 2)
+    ms_oct, _ = time_launches(lambda: oct32.query(qo, qd, rgb=qref_buf), 10, 2)
+    torch.cuda.synchronize()
+
+    def rel_l2(a, b):
+        return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+    res = {
+        "train_steps": args.surrogate_steps, "train_pairs": args.surrogate_pairs, "batch": 65536,
+        "lr": [lr0, lr0 / 100], "train_s": round(t_train, 2),
+        "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-200:].mean()),
+        "surrogate_only": {"rays_per_s": n / (ms_fwd * 1e-3), "ms": ms_fwd,
+                           "rel_l2_vs_octree_f32": rel_l2(pred, qref)},
+        "surrogate_with_fallback": {"rays_per_s": n / (ms_hyb * 1e-3), "ms": ms_hyb,
+                                    "rel_l2_vs_octree_f32": rel_l2(out, qref),
+                                    "fallback_fraction": float(used.float().mean())},
+        "octree_f32_same_rays": {"rays_per_s": n / (ms_oct * 1e-3), "ms": ms_oct},
+        "flop_per_ray": 41344,
+        "mfma_frac_surrogate_only": 41344 * n / (ms_fwd * 1e-3) / 2.5e15,
+    }
+    log(f"surrogate: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +184,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=20000,
+                    help="optimiser steps of the surrogate (0: skip the surrogate variant)")
+    ap.add_argument("--surrogate-pairs", type=int, default=50_000_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -208,6 +271,8 @@ def main():
             log(f"room {storage}: {vms:.3f} ms/step")
             if storage != "f32":
                 oc.free()
+        if args.surrogate_steps > 0:
+            variants["surrogate"] = surrogate_variant(args, lumiq, tree, oct32, ro_t, rd_t, rrgb)
         del ro_t, rd_t, rrgb, ralpha
 
     cpu = None

@@ -168,7 +168,7 @@ LQ_HD inline float sel3(const float (&v)[3], int a) { return a == 0 ? v[0] : (a 
 LQ_HD inline float tapprox(const Ray &r, int a, float P) { return (P - sel3(r.o, a)) * sel3(r.inv, a); }
 
 // sign((Pa - oa)/da - (Pb - ob)/db), exact, for da, db != 0
-LQ_HD __noinline__ int cross_cmp_exact(float Pa, float oa, float daf, float Pb, float ob, float dbf) {
+static LQ_HD __noinline__ int cross_cmp_exact(float Pa, float oa, float daf, float Pb, float ob, float dbf) {
     double A1, A0, B1, B0;
     two_sum((double)Pa, -(double)oa, A1, A0);
     two_sum((double)Pb, -(double)ob, B1, B0);

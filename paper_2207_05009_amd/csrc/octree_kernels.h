@@ -1,0 +1,251 @@
+// octree_kernels.h -- the emission-query kernels and their launchers,
+// instantiated per storage type by octree_query_{f32,f16,bf16}.hip.
+//
+// Persistent waves: the grid holds as many 256-lane blocks as fit on the
+// chip at once.  Every lane marches one ray at a time (Marcher in march.h),
+// one octree node per step.  When fewer than kRefillBelow lanes of a wave
+// still hold a ray, the idle lanes are refilled from a ray counter with one
+// atomic per wave: a 64-bit ballot of the idle lanes, one atomicAdd of its
+// popcount by the lowest idle lane, and each idle lane takes
+// base + (number of idle lanes below it).  Rays of very different lengths
+// then do not leave most of a wave idle until its longest ray is done,
+// while the atomic's latency and the per-ray set-up are paid for many lanes
+// at once.
+//
+// XCD-aware work split: the batch is cut into kXcds contiguous ranges with a
+// counter each.  Workgroups are dispatched to the accelerator dies round
+// robin, so a wave of block b starts on range b % kXcds: the rays one die's
+// L2 sees are neighbours in the batch (for a camera, a band of image rows),
+// not every kXcds-th chunk.  A wave whose range is used up continues on the
+// next ranges, so the tail stays balanced.
+#include <mutex>
+#include <unordered_map>
+
+#pragma once
+
+#include <algorithm>
+
+#include "march.h"
+
+namespace lq {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRefillBelow = 48;     // refill when fewer lanes of a wave are busy
+constexpr int kStepsPerCheck = 4;    // steps between refill checks
+constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
+constexpr unsigned kAllRanges = (1u << kXcds) - 1u;
+
+__device__ inline uint64_t lanemask_lt() {
+    const unsigned lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <class M>
+__device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool trace) {
+    RayOut r;
+    m.result(r);
+    if (a.rgb) {
+        a.rgb[3 * i] = r.rgb[0];
+        a.rgb[3 * i + 1] = r.rgb[1];
+        a.rgb[3 * i + 2] = r.rgb[2];
+    }
+    if (a.alpha) a.alpha[i] = r.alpha;
+    if (trace) {
+        a.count[i] = r.count;
+        a.hash[i] = r.hash;
+        a.term_idx[i] = r.term_idx;
+        a.n_comp[i] = r.n_comp;
+        if (a.n_steps) a.n_steps[i] = r.n_steps;
+    }
+}
+
+__device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; }
+
+// the persistent loop shared by the single- and multi-tree kernels;
+// tree_of(ray) returns the DevTree a ray queries
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, class TreeOf>
+__device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeOf tree_of) {
+    __shared__ int32_t s_path[10 * kBlock];   // per-lane node path, [level][lane]
+    int32_t *path = s_path + threadIdx.x;
+    Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
+    int64_t ray = -1;            // ray held by this lane, -1 when idle
+    uint32_t *ids = nullptr;
+    int cur = blockIdx.x % kXcds;   // range this wave draws from (wave-uniform)
+    unsigned used_up = 0;           // ranges known to be exhausted (wave-uniform)
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
+    for (;;) {
+        bool want = ray < 0 && used_up != kAllRanges;
+        uint64_t need = __ballot(want);
+        const int busy = __popcll(__ballot(ray >= 0));
+        if (need && busy < kRefillBelow) {
+            for (int tries = 0; need && tries < kXcds; ++tries) {
+                const int cnt = __popcll(need);
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                unsigned long long base = 0;
+                if ((int)__lane_id() == leader) base = atomicAdd(queue + cur, (unsigned long long)cnt);
+                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+                base = ((unsigned long long)hi << 32) | lo;
+                const int64_t start = range_begin(cur, n);
+                const int64_t len = range_begin(cur + 1, n) - start;
+                if (want) {
+                    const int64_t slot = (int64_t)base + __popcll(need & lanemask_lt());
+                    if (slot < len) {
+                        const int64_t idx = a.index ? a.index[start + slot] : start + slot;
+                        ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)idx * a.max_ids : nullptr;
+                        if (m.init(tree_of(idx), a.o + 3 * idx, a.d + 3 * idx)) {
+                            ray = idx;
+                            want = false;
+                        } else {
+                            write_ray(a, idx, m, TRACE);   // no positive-length overlap: done
+                        }
+                    }
+                }
+                if ((int64_t)base + cnt >= len) {   // this range is used up: move on
+                    used_up |= 1u << cur;
+                    for (int j = 1; j <= kXcds; ++j) {
+                        const int c = (cur + j) % kXcds;
+                        if (!(used_up & (1u << c))) { cur = c; break; }
+                    }
+                }
+                want = want && used_up != kAllRanges;
+                need = __ballot(want);
+            }
+        }
+        if (__all(ray < 0 && used_up == kAllRanges)) break;
+        for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
+            if (m.step(tree_of(ray), a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock)) {
+                write_ray(a, ray, m, TRACE);
+                ray = -1;
+            }
+        }
+    }
+}
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+__global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
+                                                  unsigned long long *queue) {
+    persistent_query<ST, DEG, ACC64, TRACE, SKIP>(a, queue, [&](int64_t) -> const DevTree & { return t; });
+}
+
+// several trees: rays [offsets[k], offsets[k+1]) query trees[k]
+template <int ST, int DEG, bool ACC64, bool SKIP>
+__global__ __launch_bounds__(kBlock) void k_query_multi(const DevTree *trees, const int64_t *offsets,
+                                                        int n_trees, const QueryArgs a,
+                                                        unsigned long long *queue) {
+    auto tree_of = [&](int64_t ray) -> const DevTree & {
+        int lo = 0, hi = n_trees;            // offsets[lo] <= ray < offsets[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (offsets[mid] <= ray) lo = mid;
+            else hi = mid;
+        }
+        return trees[lo];
+    };
+    persistent_query<ST, DEG, ACC64, false, SKIP>(a, queue, tree_of);
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
+
+// resident blocks of a kernel on the current device (cached)
+template <class Kern>
+int resident_blocks(Kern kern) {
+    static std::mutex mu;
+    static std::unordered_map<int, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 1;
+    (void)hipGetLastError();
+    int nb = per_cu * cus;
+    cache[dev] = nb;
+    return nb;
+}
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+hipError_t launch_one(const DevTree &t, const QueryArgs &a, hipStream_t s) {
+    auto kern = k_query<ST, DEG, ACC64, TRACE, SKIP>;
+    const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
+    const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
+    unsigned long long *queue = nullptr;
+    hipError_t e = hipMallocAsync((void **)&queue, kXcds * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kXcds), 0, s, queue);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, t, a, queue);
+    e = hipGetLastError();
+    hipError_t f = hipFreeAsync(queue, s);
+    return e != hipSuccess ? e : f;
+}
+
+template <int ST, int DEG>
+hipError_t launch_deg(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s) {
+    // traces record every data leaf, so they march the full table; so do
+    // queries that composite every leaf
+    const bool acc64 = (a.flags & LQ_FP64_ACCUM) != 0;
+    const bool full = trace || (a.flags & LQ_NO_SIGMA_SKIP) != 0;
+    if (trace) return acc64 ? launch_one<ST, DEG, true, true, false>(t, a, s)
+                            : launch_one<ST, DEG, false, true, false>(t, a, s);
+    if (full) return acc64 ? launch_one<ST, DEG, true, false, false>(t, a, s)
+                           : launch_one<ST, DEG, false, false, false>(t, a, s);
+    return acc64 ? launch_one<ST, DEG, true, false, true>(t, a, s)
+                 : launch_one<ST, DEG, false, false, true>(t, a, s);
+}
+
+template <int ST>
+hipError_t launch_st(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s) {
+    switch (t.sh_degree) {
+        case 0: return launch_deg<ST, 0>(t, a, trace, s);
+        case 1: return launch_deg<ST, 1>(t, a, trace, s);
+        case 2: return launch_deg<ST, 2>(t, a, trace, s);
+        case 3: return launch_deg<ST, 3>(t, a, trace, s);
+        case 4: return launch_deg<ST, 4>(t, a, trace, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int ST, int DEG, bool ACC64, bool SKIP>
+hipError_t launch_multi_one(const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                            hipStream_t s) {
+    auto kern = k_query_multi<ST, DEG, ACC64, SKIP>;
+    const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
+    const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
+    unsigned long long *queue = nullptr;
+    hipError_t e = hipMallocAsync((void **)&queue, kXcds * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kXcds), 0, s, queue);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, trees, offsets, n_trees, a, queue);
+    e = hipGetLastError();
+    hipError_t f = hipFreeAsync(queue, s);
+    return e != hipSuccess ? e : f;
+}
+
+template <int ST, int DEG>
+hipError_t launch_multi_deg(const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                            hipStream_t s) {
+    const bool acc64 = (a.flags & LQ_FP64_ACCUM) != 0;
+    const bool full = (a.flags & LQ_NO_SIGMA_SKIP) != 0;
+    if (full) return acc64 ? launch_multi_one<ST, DEG, true, false>(trees, offsets, n_trees, a, s)
+                           : launch_multi_one<ST, DEG, false, false>(trees, offsets, n_trees, a, s);
+    return acc64 ? launch_multi_one<ST, DEG, true, true>(trees, offsets, n_trees, a, s)
+                 : launch_multi_one<ST, DEG, false, true>(trees, offsets, n_trees, a, s);
+}
+
+template <int ST>
+hipError_t launch_multi_st(int deg, const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                           hipStream_t s) {
+    switch (deg) {
+        case 2: return launch_multi_deg<ST, 2>(trees, offsets, n_trees, a, s);
+        case 3: return launch_multi_deg<ST, 3>(trees, offsets, n_trees, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+}  // namespace lq

@@ -1,0 +1,15 @@
+// octree_query_bf16.hip -- bf16 storage instantiations of the query kernels.
+#include "octree_kernels.h"
+
+namespace lq {
+
+hipError_t launch_query_bf16(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s) {
+    return launch_st<LQ_BF16>(t, a, trace, s);
+}
+
+hipError_t launch_query_multi_bf16(int sh_degree, const DevTree *trees, const int64_t *offsets, int n_trees,
+                                   const QueryArgs &a, hipStream_t s) {
+    return launch_multi_st<LQ_BF16>(sh_degree, trees, offsets, n_trees, a, s);
+}
+
+}  // namespace lq
