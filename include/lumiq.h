@@ -220,8 +220,8 @@ lq_status lq_mlp_forward(const lq_mlp *mlp, const float *origins, const float *d
 
 /*
  * Trust map: held-out (ray, reference radiance) pairs are binned by the
- * octahedral cells (16 x 16) of the entry direction and of the ray
- * direction; a bin is trusted when it holds at least 4 pairs and its
+ * octahedral cells (32 x 32) of the entry direction and of the ray
+ * direction (1,048,576 bins); a bin is trusted when it holds at least 4 pairs and its
  * squared error sum is within max_rel_err^2 of its squared reference sum
  * (plus (1e-3)^2 per pair).  Synchronises the stream.
  */
@@ -231,10 +231,15 @@ lq_status lq_mlp_build_trust(lq_mlp *mlp, const float *origins, const float *dir
 lq_status lq_mlp_trust_map(const lq_mlp *mlp, uint8_t *host_map, int32_t *n_bins);
 
 /*
- * Surrogate with octree fallback: rays in untrusted bins are compacted on
- * the device and answered by lq_query_radiance on `fallback` (linear model,
- * default flags); used_fallback[n] (device, nullable) marks them.  Without
- * a trust map or a fallback tree this is lq_mlp_forward.
+ * Surrogate with octree fallback.  A classification pass splits the batch on
+ * the device: rays whose line misses the bounding sphere get radiance 0,
+ * rays in trusted bins go to a surrogate list, the rest to an octree list.
+ * The surrogate then answers only its list and lq_query_radiance on
+ * `fallback` (linear model, default flags) only the other;
+ * used_fallback[n] (device, nullable) marks the rays the octree answered.
+ * No host synchronisation; the lists live in stream-ordered scratch
+ * (16 n + 16 bytes).  Without a trust map or a fallback tree this is
+ * lq_mlp_forward.
  */
 lq_status lq_mlp_infer(const lq_mlp *mlp, const lq_octree *fallback, const float *origins,
                        const float *dirs, int64_t n, float *rgb, uint8_t *used_fallback,

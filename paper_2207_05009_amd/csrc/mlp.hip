@@ -1,5 +1,8 @@
 // mlp.hip -- training and inference of the learned surrogate on gfx950.
 //
+// Inference (k_infer): the whole network in registers, 16 rays per MFMA
+// tile, no LDS traffic; see the comment above the kernel.
+//
 // Training step (one launch + one reduction launch):
 //   k_train_step: a workgroup of 4 waves stages the bfloat16 weight image in
 //   LDS and processes tiles of 64 samples.  Per tile, each wave takes 16
@@ -53,9 +56,6 @@ constexpr int kOffAct = kOffDY + kTile * kSD * 2;         // [64] float
 constexpr int kOffLoss = kOffAct + kTile * 4;             // [kWaves] float
 constexpr int kTrainLds = kOffLoss + kWaves * 4;
 
-// inference-kernel LDS carve: weights + per wave [16][kSF] + 2 x [16][kSH]
-constexpr int kInfWave = 16 * kSF * 2 + 2 * 16 * kSH * 2;
-constexpr int kInfLds = kOffF + kWaves * kInfWave;
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -406,56 +406,209 @@ __global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
 }
 
 // ------------------------------------------------------------ inference
-// Forward pass for 16 rays per wave iteration.  mode 0: radiance only;
-// mode 1: radiance, trust lookup and compaction of untrusted rays; mode 2:
-// accumulate trust statistics against reference radiance.
-__global__ __launch_bounds__(256) void k_infer(const float *o, const float *d, int64_t n, const uint16_t *wimg,
-                                               const float *bias, int mode, const uint8_t *trust, float *rgb,
-                                               uint8_t *used_fb, int64_t *fb_list, unsigned long long *fb_count,
-                                               const float *ref, double *terr, double *tref, unsigned *tcnt) {
-    extern __shared__ __align__(16) char smem[];
-    uint16_t *sW = reinterpret_cast<uint16_t *>(smem + kOffW);
-    float *sB = reinterpret_cast<float *>(smem + kOffB);
-    stage_weights(wimg, bias, sW, sB);
+// Every weight of the network lives in registers (168 VGPRs per lane): a wave
+// loads its share of the bfloat16 image once and then runs tiles of 16 rays
+// through MFMA 16x16x32 (bf16 in, f32 accumulate) without touching LDS.
+// Lane l = 16 g + r (g = lane group, r = sample of the tile).  The weights are
+// the A operand, so output block fb of a layer leaves lane l holding features
+// 16 fb + 4 g + i (i < 4) of sample r; a 32-wide K block kb of the next layer
+// takes, in lane group g, the four rows of block 2 kb followed by the four of
+// block 2 kb + 1 — the weights are loaded in that same K order, so no value
+// moves between lanes.  The first layer's K order is chosen for the features
+// (slot_feature below): lane group g evaluates 10 + 5 consecutive
+// frequencies of two input variables by exact sincospi at the first
+// frequency of each run of five, then angle doubling.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// variable whose 10 frequencies lane group g evaluates, the variable of its
+// run of 5 and the first frequency of that run
+__host__ __device__ constexpr int run_a(int g) { return g == 0 ? 0 : g == 1 ? 2 : g == 2 ? 3 : 5; }
+__host__ __device__ constexpr int run_b(int g) { return g < 2 ? 1 : 4; }
+__host__ __device__ constexpr int run_b0(int g) { return (g & 1) ? 5 : 0; }
+
+// feature (index of the Fourier encoding, 0..127) that slot j (0..31) of lane
+// group g holds: j < 20 sin/cos of the 10-run, 20 <= j < 30 the 5-run,
+// j = 30, 31 the raw variables 2g, 2g + 1 (group 3: the two zero pads)
+__host__ __device__ constexpr int slot_feature(int g, int j) {
+    return j < 20   ? (1 + 2 * kFreq) * run_a(g) + 1 + j
+           : j < 30 ? (1 + 2 * kFreq) * run_b(g) + 1 + 2 * run_b0(g) + (j - 20)
+           : g == 3 ? kFeatUsed + (j - 30)
+                    : (1 + 2 * kFreq) * (2 * g + (j - 30));
+}
+constexpr bool slots_are_a_permutation() {
+    bool seen[kFeat] = {};
+    for (int g = 0; g < 4; ++g)
+        for (int j = 0; j < 32; ++j) {
+            const int c = slot_feature(g, j);
+            if (c < 0 || c >= kFeat || seen[c]) return false;
+            seen[c] = true;
+        }
+    return true;
+}
+static_assert(slots_are_a_permutation(), "the feature slots must cover the encoding once");
+
+__device__ inline float pick6(const float (&x)[6], int i) {
+    float r = x[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) r = i == k ? x[k] : r;
+    return r;
+}
+
+// sin, cos of pi 2^k x for k = 0..4 into f[0..10) (x already scaled by the
+// run's first frequency): exact sincospi, then sin 2a = 2 sin a cos a and
+// cos 2a = (cos a - sin a)(cos a + sin a).  Four doublings amplify the
+// initial error 16-fold: below 1e-6, far under the bfloat16 feature rounding.
+__device__ inline void sincos_run5(float x, float *f) {
+    float sn, cs;
+    sincospif(x, &sn, &cs);
+    f[0] = sn;
+    f[1] = cs;
+#pragma unroll
+    for (int k = 1; k < 5; ++k) {
+        const float s2 = 2.0f * sn * cs;
+        const float c2 = (cs - sn) * (cs + sn);
+        sn = s2;
+        cs = c2;
+        f[2 * k] = sn;
+        f[2 * k + 1] = cs;
+    }
+}
+
+__device__ inline bf16x8 load_bf8(const uint16_t *p0, const uint16_t *p1) {
+    // four consecutive elements from p0, four from p1
+    const u16x8 v = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ inline bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
+    bf16x8 h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = (__bf16)fmaxf(lo[i], 0.0f);
+        h[4 + i] = (__bf16)fmaxf(hi[i], 0.0f);
+    }
+    return h;
+}
+
+__device__ inline void load_ray(const float *o, const float *d, int64_t ray, bool valid, float *oo, float *dd) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        oo[c] = valid ? o[3 * ray + c] : 0.0f;
+        dd[c] = valid ? d[3 * ray + c] : 0.0f;
+    }
+}
+
+__device__ inline int64_t ray_of(const int64_t *index, int64_t pos) { return index ? index[pos] : pos; }
+
+// mode 0: radiance; mode 2: accumulate trust statistics against the
+// reference radiance.  With an index list the kernel answers rays
+// index[0 .. *n_dev) (the count read on the device), else rays 0 .. n.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_infer(
+    const float *o, const float *d, int64_t n, const int64_t *index, const unsigned long long *n_dev,
+    const uint16_t *wimg, const float *bias, int mode, float *rgb, const float *ref, double *terr,
+    double *tref, unsigned *tcnt) {
+    __shared__ __align__(16) float sB[kBiasPad];
+    for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int lane = __lane_id();
-    const int r16 = lane & 15, q4 = lane >> 4;
-    char *mine = smem + kOffF + wave * kInfWave;
-    uint16_t *sF = reinterpret_cast<uint16_t *>(mine);
-    uint16_t *sHa = reinterpret_cast<uint16_t *>(mine + 16 * kSF * 2);
-    uint16_t *sHb = reinterpret_cast<uint16_t *>(mine + 16 * kSF * 2 + 16 * kSH * 2);
+    const int r16 = lane & 15, g = lane >> 4;
+
+    bf16x8 w1[4][4], wh[3][4][2], wo[2];
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const uint16_t *row = wimg + kI1 + (fb * 16 + r16) * kFeat;
+            u16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = row[slot_feature(g, kb * 8 + e)];
+            w1[fb][kb] = __builtin_bit_cast(bf16x8, v);
+        }
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const uint16_t *row = wimg + kI2 + l * kHidden * kHidden + (fb * 16 + r16) * kHidden + 4 * g;
+                wh[l][fb][kb] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
+            }
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        const uint16_t *row = wimg + kI5 + r16 * kHidden + 4 * g;
+        wo[kb] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
+    }
+
+    if (n_dev) n = (int64_t)*n_dev;
     const int64_t nblk = (n + 15) / 16;
-    for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < nblk; blk += (int64_t)gridDim.x * kWaves) {
-        const int64_t ray = blk * 16 + r16;
-        const bool valid = ray < n;
-        wave_sync();
-        const bool act = wave_features(o, d, valid ? ray : 0, valid, sF, r16);
-        wave_sync();
-        fwd_layer<kFeat, 4>(sF, kSF, sW + kLW1, kSF, sB, sHa, kSH, 0);
-        wave_sync();
-        fwd_layer<kHidden, 4>(sHa, kSH, sW + kLW2, kSH, sB + 64, sHb, kSH, 0);
-        wave_sync();
-        fwd_layer<kHidden, 4>(sHb, kSH, sW + kLW3, kSH, sB + 128, sHa, kSH, 0);
-        wave_sync();
-        fwd_layer<kHidden, 4>(sHa, kSH, sW + kLW4, kSH, sB + 192, sHb, kSH, 0);
-        wave_sync();
-        const f32x4 y = out_layer(sHb, kSH, sW + kLW5, sB + 256, 0);
-        bool fb = false;
-        if (q4 == 0 && valid) {
+    const int64_t wstride = (int64_t)gridDim.x * kWaves;
+    int64_t blk = (int64_t)blockIdx.x * kWaves + wave;
+    // the next tile's rays are loaded while the current one computes
+    bool nvalid = blk * 16 + r16 < n;
+    int64_t nray = nvalid ? ray_of(index, blk * 16 + r16) : 0;
+    float no[3], nd[3];
+    load_ray(o, d, nray, nvalid, no, nd);
+    for (; blk < nblk; blk += wstride) {
+        const int64_t ray = nray;
+        const bool valid = nvalid;
+        float oo[3] = {no[0], no[1], no[2]}, dd[3] = {nd[0], nd[1], nd[2]};
+        const int64_t nxt = blk + wstride;
+        nvalid = nxt < nblk && nxt * 16 + r16 < n;
+        nray = nvalid ? ray_of(index, nxt * 16 + r16) : 0;
+        load_ray(o, d, nray, nvalid, no, nd);
+
+        float x6[6] = {0, 0, 0, 0, 0, 0};
+        const bool act = valid && sphere_x6(oo, dd, x6);
+        float f[32];
+        const float va = pick6(x6, run_a(g)), vb = pick6(x6, run_b(g));
+        sincos_run5(va, f);
+        sincos_run5(va * 32.0f, f + 10);
+        sincos_run5(run_b0(g) ? vb * 32.0f : vb, f + 20);
+        f[30] = g < 3 ? pick6(x6, 2 * g) : 0.0f;
+        f[31] = g < 3 ? pick6(x6, 2 * g + 1) : 0.0f;
+        bf16x8 x[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[kb][e] = (__bf16)(act ? f[kb * 8 + e] : 0.0f);
+
+        f32x4 acc[4];
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) acc[fb] = *reinterpret_cast<const f32x4 *>(sB + fb * 16 + 4 * g);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(w1[fb][kb], x[kb], acc[fb]);
+        bf16x8 h[2] = {relu_pack(acc[0], acc[1]), relu_pack(acc[2], acc[3])};
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+                acc[fb] = *reinterpret_cast<const f32x4 *>(sB + (l + 1) * kHidden + fb * 16 + 4 * g);
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(wh[l][fb][kb], h[kb], acc[fb]);
+            h[0] = relu_pack(acc[0], acc[1]);
+            h[1] = relu_pack(acc[2], acc[3]);
+        }
+        f32x4 y = *reinterpret_cast<const f32x4 *>(sB + 4 * kHidden + 4 * g);
+        y = mfma32(wo[0], h[0], y);
+        y = mfma32(wo[1], h[1], y);
+
+        if (g == 0 && valid) {
             float L[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) L[c] = act ? fmaxf(expf(y[c]) - kEpsOut, 0.0f) : 0.0f;
-            int bin = 0;
-            if (act && mode != 0) {
-                float x6[6];
-                float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
-                float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
-                sphere_x6(oo, dd, x6);
-                bin = trust_bin(x6);
-            }
             if (mode == 2) {
                 if (act) {
+                    const int bin = trust_bin(x6);
                     double e2 = 0.0, r2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -468,28 +621,73 @@ __global__ __launch_bounds__(256) void k_infer(const float *o, const float *d, i
                     atomicAdd(tcnt + bin, 1u);
                 }
             } else {
-                fb = mode == 1 && act && !trust[bin];
-                if (!fb) {
-                    rgb[3 * ray] = L[0];
-                    rgb[3 * ray + 1] = L[1];
-                    rgb[3 * ray + 2] = L[2];
-                }
-                if (used_fb) used_fb[ray] = fb ? 1 : 0;
+                rgb[3 * ray] = L[0];
+                rgb[3 * ray + 1] = L[1];
+                rgb[3 * ray + 2] = L[2];
             }
         }
-        if (mode == 1) {
-            const uint64_t mask = __ballot(fb);
-            if (mask) {
-                const int leader = __ffsll((unsigned long long)mask) - 1;
-                unsigned long long b = 0;
-                if (lane == leader) b = atomicAdd(fb_count, (unsigned long long)__popcll(mask));
-                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, leader);
-                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), leader);
-                b = ((unsigned long long)hi << 32) | lo;
-                const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
-                if (fb) fb_list[b + __popcll(below)] = ray;
-            }
+    }
+}
+
+// Split a batch for the hybrid query: rays whose line misses the bounding
+// sphere get radiance 0 here; the others go to the surrogate list if their
+// trust bin is trusted, else to the octree list.  A block classifies
+// kClassRays rays (16 per thread, strided by the block size so that loads
+// coalesce), places them with wave ballots and LDS counters, and reserves
+// its slots in each global list with one atomic per list.
+constexpr int kClassPer = 16;
+constexpr int kClassRays = 256 * kClassPer;
+
+__global__ __launch_bounds__(256) void k_classify(const float *o, const float *d, int64_t n, const uint8_t *trust,
+                                                  float *rgb, uint8_t *used_fb, int64_t *mlp_list,
+                                                  unsigned long long *mlp_cnt, int64_t *oct_list,
+                                                  unsigned long long *oct_cnt) {
+    __shared__ unsigned s_cnt[2];
+    __shared__ unsigned long long s_base[2];
+    if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = __lane_id();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kClassRays;
+    uint32_t slot[kClassPer];   // list (bit 31: octree) and position in the block's share, or ~0u: none
+#pragma unroll
+    for (int k = 0; k < kClassPer; ++k) {
+        const int64_t ray = base + k * 256 + threadIdx.x;
+        int cls = -1;   // -1 nothing to do, 0 surrogate, 1 octree, 2 miss
+        if (ray < n) {
+            float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
+            float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
+            float x6[6];
+            cls = sphere_x6(oo, dd, x6) ? (trust[trust_bin(x6)] ? 0 : 1) : 2;
         }
+        slot[k] = ~0u;
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const uint64_t mask = __ballot(cls == l);
+            if (!mask) continue;
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            unsigned wb = 0;
+            if (lane == leader) wb = atomicAdd(&s_cnt[l], (unsigned)__popcll(mask));
+            wb = __builtin_amdgcn_readlane(wb, leader);
+            if (cls == l) slot[k] = ((unsigned)l << 31) | (wb + (unsigned)__popcll(mask & below));
+        }
+        if (cls == 2) {
+            rgb[3 * ray] = 0.0f;
+            rgb[3 * ray + 1] = 0.0f;
+            rgb[3 * ray + 2] = 0.0f;
+        }
+        if (used_fb && cls >= 0) used_fb[ray] = cls == 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_base[0] = atomicAdd(mlp_cnt, (unsigned long long)s_cnt[0]);
+    if (threadIdx.x == 1) s_base[1] = atomicAdd(oct_cnt, (unsigned long long)s_cnt[1]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kClassPer; ++k) {
+        if (slot[k] == ~0u) continue;
+        const int64_t ray = base + k * 256 + threadIdx.x;
+        const unsigned l = slot[k] >> 31, pos = slot[k] & 0x7FFFFFFFu;
+        (l ? oct_list : mlp_list)[s_base[l] + pos] = ray;
     }
 }
 
@@ -607,9 +805,7 @@ static lq_status alloc_mlp(int device, lq_mlp **out) {
         return mfail(LQ_ERR_OOM, "device allocation for the surrogate failed");
     }
     if (hipFuncSetAttribute((const void *)k_train_step, hipFuncAttributeMaxDynamicSharedMemorySize, kTrainLds) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, kInfLds) !=
-            hipSuccess) {
+        hipSuccess) {
         (void)hipGetLastError();
         free_mlp(p);
         return mfail(LQ_ERR_UNSUPPORTED, "the device cannot give the kernels their LDS");
@@ -794,10 +990,16 @@ lq_status lq_mlp_train(lq_mlp *p, const float *o, const float *d, const float *r
 
 namespace lq {
 
+// one persistent wave per resident slot: the inference kernel holds the
+// network in registers, so its occupancy is what fits in the register file
 static int infer_grid(int device) {
-    int cus = 1;
+    int cus = 1, per_cu = 1;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    return (cus > 0 ? cus : 1) * 2;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_infer, 256, 0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return (cus > 0 ? cus : 1) * per_cu;
 }
 
 }  // namespace lq
@@ -814,10 +1016,9 @@ lq_status lq_mlp_forward(const lq_mlp *p, const float *o, const float *d, int64_
     if ((st = check_dev_ptr(o, n * 12, p->device, "origins")) != LQ_OK) return st;
     if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
     if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), kInfLds, (hipStream_t)stream, o, d, n,
-                       p->wimg, p->bias, 0, (const uint8_t *)nullptr, rgb, (uint8_t *)nullptr, (int64_t *)nullptr,
-                       (unsigned long long *)nullptr, (const float *)nullptr, (double *)nullptr, (double *)nullptr,
-                       (unsigned *)nullptr);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), 0, (hipStream_t)stream, o, d, n,
+                       (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wimg, p->bias, 0, rgb,
+                       (const float *)nullptr, (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
     e = hipGetLastError();
     return e == hipSuccess ? LQ_OK : mhip(e, "surrogate forward");
 }
@@ -840,9 +1041,9 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
     double *tref = terr + kTrustBins;
     unsigned *tcnt = reinterpret_cast<unsigned *>(tref + kTrustBins);
     hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), kInfLds, s, o, d, n, p->wimg, p->bias, 2,
-                       (const uint8_t *)nullptr, (float *)nullptr, (uint8_t *)nullptr, (int64_t *)nullptr,
-                       (unsigned long long *)nullptr, rgb_ref, terr, tref, tcnt);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), 0, s, o, d, n, (const int64_t *)nullptr,
+                       (const unsigned long long *)nullptr, p->wimg, p->bias, 2, (float *)nullptr, rgb_ref, terr,
+                       tref, tcnt);
     hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tref, tcnt,
                        max_rel_err, 1e-3f, 4u, p->trust);
     e = hipGetLastError();
@@ -879,18 +1080,23 @@ lq_status lq_mlp_infer(const lq_mlp *p, const lq_octree *fallback, const float *
     if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
     if (used_fallback && (st = check_dev_ptr(used_fallback, n, p->device, "used_fallback")) != LQ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    // two counters, then the surrogate list and the octree list (n each)
     unsigned char *scratch = nullptr;
-    const size_t bytes = 8 + (size_t)n * 8;
+    const size_t bytes = 16 + (size_t)n * 16;
     if ((e = hipMallocAsync((void **)&scratch, bytes, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(scratch);
-    int64_t *list = reinterpret_cast<int64_t *>(scratch + 8);
-    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, s, scratch, (size_t)8);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), kInfLds, s, o, d, n, p->wimg, p->bias, 1,
-                       p->trust, rgb, used_fallback, list, cnt, (const float *)nullptr, (double *)nullptr,
-                       (double *)nullptr, (unsigned *)nullptr);
+    int64_t *mlp_list = reinterpret_cast<int64_t *>(scratch + 16);
+    int64_t *oct_list = mlp_list + n;
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, s, scratch, (size_t)16);
+    const int64_t cblocks = (n + kClassRays - 1) / kClassRays;
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)cblocks), dim3(256), 0, s, o, d, n, p->trust, rgb, used_fallback,
+                       mlp_list, cnt, oct_list, cnt + 1);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), 0, s, o, d, n, mlp_list,
+                       (const unsigned long long *)cnt, p->wimg, p->bias, 0, rgb, (const float *)nullptr,
+                       (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
     e = hipGetLastError();
     if (e == hipSuccess) {
-        lq_status q = query_indexed(fallback, o, d, n, list, cnt, rgb, s);
+        lq_status q = query_indexed(fallback, o, d, n, oct_list, cnt + 1, rgb, s);
         if (q != LQ_OK) {
             (void)hipFreeAsync(scratch, s);
             return q;
@@ -912,7 +1118,7 @@ lq_status lq_mlp_save(const lq_mlp *p, const char *path) {
     if (e != hipSuccess) return mhip(e, "reading the surrogate");
     FILE *f = fopen(path, "wb");
     if (!f) return mfail(LQ_ERR_IO, std::string("cannot write ") + path);
-    const uint32_t hdr[4] = {0x504D514Cu /* "LQMP" */, 1u, (uint32_t)kParams, p->has_trust ? 1u : 0u};
+    const uint32_t hdr[4] = {0x504D514Cu /* "LQMP" */, 2u, (uint32_t)kParams, p->has_trust ? 1u : 0u};
     const int64_t meta[2] = {p->step, (int64_t)p->seed};
     bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(meta, sizeof(meta), 1, f) == 1 &&
               fwrite(buf.data(), 4, buf.size(), f) == buf.size() &&
@@ -930,7 +1136,7 @@ lq_status lq_mlp_load(const char *path, int device, lq_mlp **out) {
     int64_t meta[2];
     std::vector<float> buf((size_t)3 * kParams);
     std::vector<uint8_t> trust(kTrustBins);
-    bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x504D514Cu && hdr[1] == 1u &&
+    bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x504D514Cu && hdr[1] == 2u &&
               hdr[2] == (uint32_t)kParams && fread(meta, sizeof(meta), 1, f) == 1 &&
               fread(buf.data(), 4, buf.size(), f) == buf.size() &&
               fread(trust.data(), 1, trust.size(), f) == trust.size();

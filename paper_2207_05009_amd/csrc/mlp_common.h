@@ -48,9 +48,9 @@ constexpr int kI5 = kI4 + kHidden * kHidden;
 constexpr int kImage = kI5 + kOutPad * kHidden;                  // 21504
 constexpr int kBiasPad = 4 * kHidden + kOutPad;                  // 272 floats
 
-// trust map: octahedral 16x16 cells for the entry direction and for the ray
-// direction
-constexpr int kOctRes = 16;
+// trust map: octahedral 32x32 cells for the entry direction and for the ray
+// direction (1,048,576 bins)
+constexpr int kOctRes = 32;
 constexpr int kTrustBins = kOctRes * kOctRes * kOctRes * kOctRes;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
