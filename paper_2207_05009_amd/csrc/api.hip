@@ -15,6 +15,7 @@ struct lq_octree {
     lq::DevTree t;
     int32_t *d_child;
     int32_t *d_child_skip;
+    int32_t *d_top;   // grids of child and child_skip, or null (depth <= kTopLevel)
     void *d_rows;
     int64_t bytes;
 };
@@ -145,6 +146,33 @@ static lq_status validate_desc(const lq_octree_desc *d, std::vector<int32_t> *bf
     return LQ_OK;
 }
 
+// Dense top grid of a child table (see DevTree::top): the descent from the
+// root along every cell of level kTopLevel; cells are indexed z, y, x.
+static std::vector<int32_t> top_grid(const int32_t *table, int depth) {
+    std::vector<int32_t> g;
+    if (depth <= kTopLevel) return g;
+    const int R = 1 << kTopLevel;
+    g.resize(kTopCells);
+    for (int z = 0; z < R; ++z)
+        for (int y = 0; y < R; ++y)
+            for (int x = 0; x < R; ++x) {
+                int32_t node = 0, e = 0;
+                for (int level = 0; level < kTopLevel; ++level) {
+                    const int b = kTopLevel - 1 - level;
+                    const int oct = ((x >> b) & 1) | (((y >> b) & 1) << 1) | (((z >> b) & 1) << 2);
+                    const int32_t c = table[(size_t)node * 8 + oct];
+                    if (c <= 0) {   // leaves sit at max depth > kTopLevel: c is empty
+                        e = -(level + 1);
+                        break;
+                    }
+                    node = c;
+                    e = c;
+                }
+                g[((size_t)z * R + y) * R + x] = e;
+            }
+    return g;
+}
+
 // Child table without the leaves for which keep_leaf() is false and without
 // the nodes that are left empty; the root stays node 0, order breadth-first.
 template <class Keep>
@@ -244,33 +272,43 @@ lq_status lq_load_octree_desc(const lq_octree_desc *desc, int storage, int devic
     const size_t child_bytes = (size_t)desc->n_nodes * 32;
     const size_t skip_bytes = skip.size() * 4;
     const size_t row_total = rows.size() ? rows.size() : 64;
+    std::vector<int32_t> tops = top_grid(desc->child, desc->max_depth);
+    const std::vector<int32_t> top_skip = top_grid(skip.data(), desc->max_depth);
+    tops.insert(tops.end(), top_skip.begin(), top_skip.end());
+    const size_t top_bytes = tops.size() * 4;
     t->d_child = nullptr;
     t->d_child_skip = nullptr;
+    t->d_top = nullptr;
     t->d_rows = nullptr;
-    if (hipMalloc((void **)&t->d_child, child_bytes) != hipSuccess ||
-        hipMalloc((void **)&t->d_child_skip, skip_bytes) != hipSuccess ||
-        hipMalloc(&t->d_rows, row_total) != hipSuccess) {
-        (void)hipGetLastError();
+    auto release = [&]() {
         (void)hipFree(t->d_child);
         (void)hipFree(t->d_child_skip);
+        (void)hipFree(t->d_top);
         (void)hipFree(t->d_rows);
         delete t;
+    };
+    if (hipMalloc((void **)&t->d_child, child_bytes) != hipSuccess ||
+        hipMalloc((void **)&t->d_child_skip, skip_bytes) != hipSuccess ||
+        (top_bytes && hipMalloc((void **)&t->d_top, top_bytes) != hipSuccess) ||
+        hipMalloc(&t->d_rows, row_total) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
         return fail(LQ_ERR_OOM, "device allocation of the tree tables failed");
     }
     e = hipMemcpy(t->d_child, desc->child, child_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(t->d_child_skip, skip.data(), skip_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && top_bytes) e = hipMemcpy(t->d_top, tops.data(), top_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess && rows.size()) e = hipMemcpy(t->d_rows, rows.data(), rows.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(t->d_child);
-        (void)hipFree(t->d_child_skip);
-        (void)hipFree(t->d_rows);
-        delete t;
+        release();
         return hip_fail(e, "uploading the tree");
     }
-    t->bytes = (int64_t)(child_bytes + skip_bytes + row_total);
+    t->bytes = (int64_t)(child_bytes + skip_bytes + top_bytes + row_total);
     DevTree &dt = t->t;
     dt.child = t->d_child;
     dt.child_skip = t->d_child_skip;
+    dt.top = top_bytes ? t->d_top : nullptr;
+    dt.top_skip = top_bytes ? t->d_top + kTopCells : nullptr;
     dt.rows = t->d_rows;
     dt.depth = desc->max_depth;
     dt.sh_degree = desc->sh_degree;
@@ -342,6 +380,7 @@ void lq_free_octree(lq_octree *t) {
     (void)hipSetDevice(t->device);
     (void)hipFree(t->d_child);
     (void)hipFree(t->d_child_skip);
+    (void)hipFree(t->d_top);
     (void)hipFree(t->d_rows);
     (void)hipSetDevice(cur);
     delete t;

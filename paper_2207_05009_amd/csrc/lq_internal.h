@@ -21,9 +21,19 @@ namespace lq {
 //         coefficients of R, G, B (K each), zero padded so that a row is a
 //         power-of-two number of bytes >= 64 (one row never straddles a
 //         128-byte line when it is <= 128 bytes).
+// Level of the dense top grid: for each cell of level kTopLevel the grid
+// holds the node covering it (> 0) or, where the tree ends above that level
+// in an empty node, minus the level of that node's cell.  One read replaces
+// the first kTopLevel steps of a descent.  Trees of depth <= kTopLevel have
+// no grid.
+constexpr int kTopLevel = 4;
+constexpr int kTopCells = 1 << (3 * kTopLevel);
+
 struct DevTree {
     const int32_t *child;
     const int32_t *child_skip;
+    const int32_t *top;        // [kTopCells] grid of `child`, or null
+    const int32_t *top_skip;   // [kTopCells] grid of `child_skip`, or null
     const void *rows;
     int32_t depth, sh_degree, K, storage;
     int32_t n_nodes, n_leaves, row_elems, pad;

@@ -22,8 +22,11 @@
 // the current event (the plane crossing, or the origin, that starts the
 // current segment).  Each step descends by the bits of q -- from the
 // deepest common ancestor of the previous and the new cell, whose path is
-// kept per lane -- takes the exit of the node found (ties between axes are
-// exact), and re-locates q on the other axes inside the node's extent.
+// kept per lane, or, when that ancestor lies above the top grid's level,
+// from the grid entry of q -- takes the exit of the node found (ties between
+// axes are exact), and re-locates q on the other axes inside the node's
+// extent.  The leaf row is fetched before the exit is computed, so its
+// latency overlaps that work.
 //
 // Everything here is __host__ __device__ so that the same code can be
 // compiled for the host when debugging the traversal.
@@ -207,6 +210,14 @@ LQ_HD inline int cmp_event(const Ray &r, int b, float P, const Event &e) {
 }
 
 LQ_HD inline float plane_of(int k, float h) { return fmaf((float)k, h, -1.0f); }
+
+// true when the filter certifies t_a(P) > t_b(Q) from the approximations
+// ta, tb (the same bound as cross_cmp); false means later or undecided
+LQ_HD inline bool later(float ta, float tb) {
+    return ta - tb > fmaf(kFilterRel, fabsf(ta) + fabsf(tb), kFilterAbs);
+}
+
+LQ_HD inline int lo_sel(const int (&lo)[3], int a) { return a == 0 ? lo[0] : (a == 1 ? lo[1] : lo[2]); }
 
 // Cell index along axis b (d_b != 0) of the point just after event e, known
 // to lie in [lo, hi).
@@ -406,8 +417,11 @@ struct Marcher {
     }
 
     // Visit one node; returns true when the march is over.
+    // top: the dense top grid of the table marched (DevTree::top or
+    // top_skip, possibly a copy in LDS), or null.  path[l] is kept only for
+    // the levels the grid does not cover.
     LQ_HD bool step(const DevTree &t, int model, uint32_t flags, uint32_t *ids, int32_t max_ids,
-                    int32_t *path, int path_stride) {
+                    int32_t *path, int path_stride, const int32_t *top = nullptr) {
         const int D = t.depth;
         const int N = 1 << D;
         const float h = 2.0f / (float)N;
@@ -423,9 +437,22 @@ struct Marcher {
             level = D - 1 - hb;
             if (level > path_top) level = path_top;
             if (level < 0) level = 0;
+        }
+        bool descend = true;
+        if (top && level < kTopLevel) {
+            const int gs = D - kTopLevel;
+            const int e = top[((q[2] >> gs) << (2 * kTopLevel)) | ((q[1] >> gs) << kTopLevel) | (q[0] >> gs)];
+            if (e > 0) {
+                node = e;
+                level = kTopLevel;
+            } else {   // empty node whose cell is at level -e
+                level = -e;
+                descend = false;
+            }
+        } else if (path_top >= 0) {
             node = path[level * path_stride];
         }
-        for (;;) {
+        while (descend) {
             path[level * path_stride] = node;
             int sh = D - 1 - level;
             int oct = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
@@ -444,48 +471,121 @@ struct Marcher {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) lo[ax] = (q[ax] >> sshift) << sshift;
 
-        // exit crossing of the node (exact; ties collected in xmask)
-        int xa = -1;
-        float xP = 0.0f, xt = 0.0f;
-        unsigned xmask = 0;
+        // fetch the leaf row first: its latency overlaps the exit and
+        // next-cell computation below, which do not depend on it
+        const bool is_leaf = c < 0;
+        const int leaf = is_leaf ? -c - 1 : 0;
+        const uint4 *rowp = reinterpret_cast<const uint4 *>(static_cast<const char *>(t.rows) + (size_t)leaf * RB);
+        uint32_t w[NCH * 4];
+        if (is_leaf) {
+            const uint4 c0 = rowp[0];
+            w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
+            if (SKIP) {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            float dx = r.d[ax];
-            if (dx == 0.0f) continue;
-            int k = dx > 0.0f ? lo[ax] + Sz : lo[ax];
-            float P = plane_of(k, h);
-            float tt = tapprox(r, ax, P);
-            int cmpv = xa < 0 ? -1 : cross_cmp(r, ax, P, tt, xa, xP, xt);
-            if (cmpv < 0) {
-                xa = ax; xP = P; xt = tt;
-                xmask = 1u << ax;
-            } else if (cmpv == 0) {
-                xmask |= 1u << ax;
+                for (int ch = 1; ch < NCH; ++ch) {
+                    const uint4 cc = rowp[ch];
+                    w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
+                }
             }
         }
 
-        if (c < 0) {
-            const int leaf = -c - 1;
+        // Exit crossing of the node and the neighbouring cell.  Fast path:
+        // the float32 plane parameters, every decision certified by the
+        // error filter -- the exit axis by its margin over the other axes,
+        // each re-located coordinate by the margins of the two planes that
+        // bound its cell.  When a margin is too thin (ties, grazing), the
+        // exact path below decides everything again.
+        int xa = 0;
+        float xP = 0.0f, xt = 0.0f;
+        unsigned xmask = 0;
+        int nq[3] = {q[0], q[1], q[2]};
+        bool leave = false;
+        bool fast = r.filter_ok;
+        {
+            float tc[3], Pc[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                Pc[ax] = plane_of(r.d[ax] > 0.0f ? lo[ax] + Sz : lo[ax], h);
+                tc[ax] = r.d[ax] != 0.0f ? (Pc[ax] - r.o[ax]) * r.inv[ax] : INFINITY;
+            }
+            xa = tc[1] < tc[0] ? 1 : 0;
+            xa = tc[2] < (xa ? tc[1] : tc[0]) ? 2 : xa;
+            xP = xa == 0 ? Pc[0] : (xa == 1 ? Pc[1] : Pc[2]);
+            xt = xa == 0 ? tc[0] : (xa == 1 ? tc[1] : tc[2]);
+            xmask = 1u << xa;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                if (ax != xa && r.d[ax] != 0.0f) fast = fast && later(tc[ax], xt);
+            const int nx = (xa == 0 ? r.d[0] : (xa == 1 ? r.d[1] : r.d[2])) > 0.0f ? lo_sel(lo, xa) + Sz
+                                                                                    : lo_sel(lo, xa) - 1;
+            leave = nx < 0 || nx >= N;
+            nq[0] = xa == 0 ? nx : nq[0];
+            nq[1] = xa == 1 ? nx : nq[1];
+            nq[2] = xa == 2 ? nx : nq[2];
+            if (!leave && Sz > 1) {
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const float db = r.d[ax];
+                    if (ax == xa || db == 0.0f) continue;
+                    const int hi = lo[ax] + Sz;
+                    const float pp = fmaf(xt, db, r.o[ax]);
+                    float g = (pp + 1.0f) * (0.5f * (float)N);
+                    g = fminf(fmaxf(g, (float)lo[ax]), (float)(hi - 1));
+                    const int k = (int)g;
+                    const float tk = (plane_of(k, h) - r.o[ax]) * r.inv[ax];
+                    const float tk1 = (plane_of(k + 1, h) - r.o[ax]) * r.inv[ax];
+                    // the point just after the exit lies in [plane k, plane k+1)
+                    const bool ok = db > 0.0f ? (k == lo[ax] || later(xt, tk)) && (k + 1 == hi || later(tk1, xt))
+                                              : (k + 1 == hi || later(xt, tk1)) && (k == lo[ax] || later(tk, xt));
+                    fast = fast && ok;
+                    nq[ax] = k;
+                }
+            }
+        }
+        if (!fast) {
+            xa = -1;
+            xmask = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                float dx = r.d[ax];
+                if (dx == 0.0f) continue;
+                int k = dx > 0.0f ? lo[ax] + Sz : lo[ax];
+                float P = plane_of(k, h);
+                float tt = tapprox(r, ax, P);
+                int cmpv = xa < 0 ? -1 : cross_cmp(r, ax, P, tt, xa, xP, xt);
+                if (cmpv < 0) {
+                    xa = ax; xP = P; xt = tt;
+                    xmask = 1u << ax;
+                } else if (cmpv == 0) {
+                    xmask |= 1u << ax;
+                }
+            }
+            leave = false;
+            nq[0] = q[0]; nq[1] = q[1]; nq[2] = q[2];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                if (!(xmask & (1u << ax))) continue;
+                nq[ax] = r.d[ax] > 0.0f ? lo[ax] + Sz : lo[ax] - 1;
+                leave = leave || nq[ax] < 0 || nq[ax] >= N;
+            }
+            if (!leave && Sz > 1) {
+                const Event e{xa, xP, xt};
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    if ((xmask & (1u << ax)) || r.d[ax] == 0.0f) continue;
+                    nq[ax] = locate(r, ax, lo[ax], lo[ax] + Sz, e, h, N);
+                }
+            }
+        }
+        const Event nev{xa, xP, xt};
+
+        if (is_leaf) {
             if (TRACE) {
                 uint32_t id = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
                 if ((int32_t)count < max_ids) ids[count] = id;
                 hash = (hash ^ (uint64_t)id) * kFnvPrime;
             }
             ++count;
-            const uint4 *rowp = reinterpret_cast<const uint4 *>(
-                static_cast<const char *>(t.rows) + (size_t)leaf * RB);
-            uint32_t w[NCH * 4];
-            {
-                uint4 c0 = rowp[0];
-                w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
-            }
-            if (SKIP) {
-#pragma unroll
-                for (int ch = 1; ch < NCH; ++ch) {
-                    uint4 cc = rowp[ch];
-                    w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
-                }
-            }
             const float sig = S::get(w, 0);
             if (SKIP || (flags & LQ_NO_SIGMA_SKIP) || sig >= t.sigma_min) {
 #pragma unroll
@@ -520,25 +620,8 @@ struct Marcher {
                 }
             }
         }
-
-        // step to the neighbouring node
-        bool leave = false;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (!(xmask & (1u << ax))) continue;
-            int nq = r.d[ax] > 0.0f ? lo[ax] + Sz : lo[ax] - 1;
-            leave = leave || nq < 0 || nq >= N;
-            q[ax] = nq;
-        }
         if (leave) return true;
-        const Event nev{xa, xP, xt};
-        if (Sz > 1) {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                if ((xmask & (1u << ax)) || r.d[ax] == 0.0f) continue;
-                q[ax] = locate(r, ax, lo[ax], lo[ax] + Sz, nev, h, N);
-            }
-        }
+        q[0] = nq[0]; q[1] = nq[1]; q[2] = nq[2];
         ev = nev;
         return false;
     }
@@ -560,10 +643,10 @@ struct Marcher {
 template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP = false>
 LQ_HD inline void march_ray(const DevTree &t, const float *o3, const float *d3, int model,
                             uint32_t flags, RayOut &out, uint32_t *ids, int32_t max_ids,
-                            int32_t *path, int path_stride) {
+                            int32_t *path, int path_stride, const int32_t *top = nullptr) {
     Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
     if (m.init(t, o3, d3))
-        while (!m.step(t, model, flags, ids, max_ids, path, path_stride)) {
+        while (!m.step(t, model, flags, ids, max_ids, path, path_stride, top)) {
         }
     m.result(out);
 }

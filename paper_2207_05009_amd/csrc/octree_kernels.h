@@ -63,11 +63,28 @@ __device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool
 __device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; }
 
 // the persistent loop shared by the single- and multi-tree kernels;
-// tree_of(ray) returns the DevTree a ray queries
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, class TreeOf>
+// tree_of(ray) returns the DevTree a ray queries.  With TOP_LDS (one tree)
+// the block copies the tree's top grid into LDS; otherwise each ray reads
+// its tree's grid from global memory.
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, class TreeOf>
 __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeOf tree_of) {
     __shared__ int32_t s_path[10 * kBlock];   // per-lane node path, [level][lane]
     int32_t *path = s_path + threadIdx.x;
+    const int32_t *top_lds = nullptr;
+    if constexpr (TOP_LDS) {
+        __shared__ int32_t s_top[kTopCells];
+        const DevTree &t0 = tree_of(0);
+        const int32_t *src = SKIP ? t0.top_skip : t0.top;
+        if (src) {
+            for (int i = threadIdx.x; i < kTopCells; i += kBlock) s_top[i] = src[i];
+            top_lds = s_top;
+        }
+        __syncthreads();
+    }
+    auto top_of = [&](const DevTree &t) -> const int32_t * {
+        if constexpr (TOP_LDS) return top_lds;
+        return SKIP ? t.top_skip : t.top;
+    };
     Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
     int64_t ray = -1;            // ray held by this lane, -1 when idle
     uint32_t *ids = nullptr;
@@ -115,7 +132,8 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         }
         if (__all(ray < 0 && used_up == kAllRanges)) break;
         for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
-            if (m.step(tree_of(ray), a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock)) {
+            const DevTree &tr = tree_of(ray);
+            if (m.step(tr, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock, top_of(tr))) {
                 write_ray(a, ray, m, TRACE);
                 ray = -1;
             }
@@ -126,7 +144,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
 template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
                                                   unsigned long long *queue) {
-    persistent_query<ST, DEG, ACC64, TRACE, SKIP>(a, queue, [&](int64_t) -> const DevTree & { return t; });
+    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true>(a, queue, [&](int64_t) -> const DevTree & { return t; });
 }
 
 // several trees: rays [offsets[k], offsets[k+1]) query trees[k]
@@ -143,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_query_multi(const DevTree *trees, co
         }
         return trees[lo];
     };
-    persistent_query<ST, DEG, ACC64, false, SKIP>(a, queue, tree_of);
+    persistent_query<ST, DEG, ACC64, false, SKIP, false>(a, queue, tree_of);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
