@@ -3,11 +3,11 @@
 //
 // Persistent waves: the grid holds as many 256-lane blocks as fit on the
 // chip at once.  Every lane marches one ray at a time (Marcher in march.h),
-// one octree node per step.  When fewer than kRefillBelow lanes of a wave
-// still hold a ray, the idle lanes are refilled from a ray counter with one
-// atomic per wave: a 64-bit ballot of the idle lanes, one atomicAdd of its
-// popcount by the lowest idle lane, and each idle lane takes
-// base + (number of idle lanes below it).  Rays of very different lengths
+// one octree node per step.  Every kStepsPerCheck steps the wave counts its
+// busy lanes; when fewer than kRefillBelow still hold a ray, the idle lanes
+// are refilled from a ray counter with one atomic per wave: a 64-bit ballot
+// of the idle lanes, one atomicAdd of its popcount by the lowest idle lane,
+// and each idle lane takes base + (number of idle lanes below it).  Rays of very different lengths
 // then do not leave most of a wave idle until its longest ray is done,
 // while the atomic's latency and the per-ray set-up are paid for many lanes
 // at once.
@@ -31,10 +31,11 @@ namespace lq {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRefillBelow = 48;     // refill when fewer lanes of a wave are busy
-constexpr int kStepsPerCheck = 4;    // steps between refill checks
+constexpr int kRefillBelow = 40;     // refill when fewer lanes of a wave are busy
+constexpr int kStepsPerCheck = 8;    // steps between refill checks
 constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
-constexpr unsigned kAllRanges = (1u << kXcds) - 1u;
+static_assert(kXcds >= 1 && kXcds <= 31, "one bit per range in a 32-bit mask");
+constexpr unsigned kAllRanges = (1u << kXcds) - 1u;   // every range used up
 
 __device__ inline uint64_t lanemask_lt() {
     const unsigned lane = __lane_id();
