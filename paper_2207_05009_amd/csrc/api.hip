@@ -71,33 +71,6 @@ uint16_t f32_to_bf16_rne(float x) {
 
 int row_bytes(int storage, int K);   // octree_query.hip
 
-// ------------------------------------------------------------ SH constants
-// Real SH without the Condon-Shortley phase:
-//   Y_lm = s_m K_l^|m| P_l^|m|(cos theta) trig(m phi),  s_0 = 1, s_m = sqrt(2),
-//   K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
-// P_l^|m|(cos theta) sin^|m| ... trig folds into a polynomial in (x, y, z);
-// a_lm is the rational factor between the two, so c_lm = s_m K_l^|m| a_lm
-// multiplies the polynomial evaluated in the kernel (same k = l^2 + l + m order).
-static void sh_constants(float *c) {
-    static const double a[25] = {
-        1.0,                                      // l = 0
-        1.0, 1.0, 1.0,                            // l = 1: y, z, x
-        6.0, 3.0, 0.5, 3.0, 3.0,                  // l = 2: xy, yz, 3z^2-1, xz, x^2-y^2
-        15.0, 30.0, 1.5, 0.5, 1.5, 15.0, 15.0,    // l = 3
-        420.0, 105.0, 15.0, 2.5, 0.125, 2.5, 7.5, 105.0, 105.0,   // l = 4
-    };
-    for (int l = 0; l <= 4; ++l) {
-        for (int m = -l; m <= l; ++m) {
-            int am = m < 0 ? -m : m;
-            double f = 1.0;
-            for (int i = l - am + 1; i <= l + am; ++i) f *= (double)i;   // (l+m)!/(l-m)!
-            double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) / f);
-            double s = am == 0 ? 1.0 : sqrt(2.0);
-            c[l * l + l + m] = (float)(s * K * a[l * l + l + m]);
-        }
-    }
-}
-
 // ------------------------------------------------------------ validation
 // On success, *bfs (if given) receives the nodes in breadth-first order.
 static lq_status validate_desc(const lq_octree_desc *d, std::vector<int32_t> *bfs = nullptr) {
@@ -320,7 +293,6 @@ lq_status lq_load_octree_desc(const lq_octree_desc *desc, int storage, int devic
     dt.l_max = desc->l_max;
     dt.sigma_min = desc->sigma_min;
     dt.alpha_max = desc->alpha_max;
-    sh_constants(dt.ycoef);
     *out = t;
     return LQ_OK;
 }

@@ -38,7 +38,6 @@ struct DevTree {
     int32_t depth, sh_degree, K, storage;
     int32_t n_nodes, n_leaves, row_elems, pad;
     float l_max, sigma_min, alpha_max, pad2;
-    float ycoef[25];   // SH normalisation constants, c_lm of Y_lm = c_lm * poly_lm(x,y,z)
 };
 
 struct QueryArgs {

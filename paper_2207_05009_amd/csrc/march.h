@@ -25,8 +25,7 @@
 // kept per lane, or, when that ancestor lies above the top grid's level,
 // from the grid entry of q -- takes the exit of the node found (ties between
 // axes are exact), and re-locates q on the other axes inside the node's
-// extent.  The leaf row is fetched before the exit is computed, so its
-// latency overlaps that work.
+// extent.
 //
 // Everything here is __host__ __device__ so that the same code can be
 // compiled for the host when debugging the traversal.
@@ -77,10 +76,49 @@ LQ_HD constexpr int row_bytes_for(int elem_bytes, int K) {
 }
 
 // ------------------------------------------------------------ SH basis
-// Y_lm(x, y, z) = c_lm * poly_lm; the host computes c_lm from the
-// normalisation formula (api.hip), the polynomials are below.
+// Y_lm(x, y, z) = c_lm * poly_lm for the real orthonormal basis without the
+// Condon-Shortley phase, k = l^2 + l + m.  With K_l^m = sqrt((2l+1)/(4 pi) *
+// (l-|m|)!/(l+|m|)!), Y_lm = s_m K_l^|m| P_l^|m|(z) {cos, sin}(|m| phi),
+// s_0 = 1, s_m = sqrt(2); a_lm below is the rational factor between
+// P_l^|m|(z) {cos, sin}(|m| phi) and the polynomial written in sh_basis, so
+// c_lm = s_m K_l^|m| a_lm.  The table is evaluated at compile time.
+constexpr double cx_sqrt(double x) {   // Newton's method, to a fixed point
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 200; ++i) {
+        const double nr = 0.5 * (r + x / r);
+        if (nr == r) break;
+        r = nr;
+    }
+    return r;
+}
+struct ShTable {
+    float c[25];
+};
+constexpr ShTable make_sh_table() {
+    const double a[25] = {
+        1.0,                                      // l = 0
+        1.0, 1.0, 1.0,                            // l = 1: y, z, x
+        6.0, 3.0, 0.5, 3.0, 3.0,                  // l = 2: xy, yz, 3z^2-1, xz, x^2-y^2
+        15.0, 30.0, 1.5, 0.5, 1.5, 15.0, 15.0,    // l = 3
+        420.0, 105.0, 15.0, 2.5, 0.125, 2.5, 7.5, 105.0, 105.0,   // l = 4
+    };
+    ShTable t{};
+    for (int l = 0; l <= 4; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const int am = m < 0 ? -m : m;
+            double f = 1.0;
+            for (int i = l - am + 1; i <= l + am; ++i) f *= (double)i;   // (l+|m|)!/(l-|m|)!
+            const double K = cx_sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846) / f);
+            const double sm = am == 0 ? 1.0 : cx_sqrt(2.0);
+            t.c[l * l + l + m] = (float)(sm * K * a[l * l + l + m]);
+        }
+    return t;
+}
+constexpr ShTable kSh = make_sh_table();
+
 template <int DEG>
-LQ_HD inline void sh_basis(float x, float y, float z, const float *c, float *Y) {
+LQ_HD inline void sh_basis(float x, float y, float z, float *Y) {
+    constexpr const float *c = kSh.c;
     Y[0] = c[0];
     if constexpr (DEG >= 1) {
         Y[1] = c[1] * y;
@@ -408,11 +446,8 @@ struct Marcher {
         }
 
         // ---- emission direction omega = -d/|d| and its SH values
-        float c[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) c[k] = t.ycoef[k];
         float inv_len = 1.0f / dlen;
-        sh_basis<DEG>(-r.d[0] * inv_len, -r.d[1] * inv_len, -r.d[2] * inv_len, c, Y);
+        sh_basis<DEG>(-r.d[0] * inv_len, -r.d[1] * inv_len, -r.d[2] * inv_len, Y);
         return true;
     }
 
@@ -470,24 +505,6 @@ struct Marcher {
         int lo[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) lo[ax] = (q[ax] >> sshift) << sshift;
-
-        // fetch the leaf row first: its latency overlaps the exit and
-        // next-cell computation below, which do not depend on it
-        const bool is_leaf = c < 0;
-        const int leaf = is_leaf ? -c - 1 : 0;
-        const uint4 *rowp = reinterpret_cast<const uint4 *>(static_cast<const char *>(t.rows) + (size_t)leaf * RB);
-        uint32_t w[NCH * 4];
-        if (is_leaf) {
-            const uint4 c0 = rowp[0];
-            w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
-            if (SKIP) {
-#pragma unroll
-                for (int ch = 1; ch < NCH; ++ch) {
-                    const uint4 cc = rowp[ch];
-                    w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
-                }
-            }
-        }
 
         // Exit crossing of the node and the neighbouring cell.  Fast path:
         // the float32 plane parameters, every decision certified by the
@@ -578,6 +595,24 @@ struct Marcher {
             }
         }
         const Event nev{xa, xP, xt};
+        // the leaf row (fetched after the exit computation: holding it
+        // across that code costs more in registers than its latency)
+        const bool is_leaf = c < 0;
+        const int leaf = is_leaf ? -c - 1 : 0;
+        const uint4 *rowp = reinterpret_cast<const uint4 *>(static_cast<const char *>(t.rows) + (size_t)leaf * RB);
+        uint32_t w[NCH * 4];
+        if (is_leaf) {
+            const uint4 c0 = rowp[0];
+            w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
+            if (SKIP) {
+#pragma unroll
+                for (int ch = 1; ch < NCH; ++ch) {
+                    const uint4 cc = rowp[ch];
+                    w[4 * ch] = cc.x; w[4 * ch + 1] = cc.y; w[4 * ch + 2] = cc.z; w[4 * ch + 3] = cc.w;
+                }
+            }
+        }
+
 
         if (is_leaf) {
             if (TRACE) {
