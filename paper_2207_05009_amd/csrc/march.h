@@ -348,7 +348,8 @@ struct Marcher {
     float dlen;
     float Y[K];
     Event ev;
-    int q[3], pq[3];
+    int q[3];
+    uint32_t qdiff;       // OR of the bitwise differences between the current and the previous cell
     int path_top, steps_left;
     Acc L0, L1, L2, T;
     uint32_t count, ncomp, nsteps;
@@ -369,7 +370,7 @@ struct Marcher {
         hash = kFnvOffset;
         path_top = -1;
         q[0] = q[1] = q[2] = 0;
-        pq[0] = pq[1] = pq[2] = 0;
+        qdiff = 0;
         ev = Event{-1, 0.0f, 0.0f};
 
         const int D = t.depth;
@@ -467,8 +468,7 @@ struct Marcher {
         if (path_top >= 0) {
             // the old and new cells share the path down to the level above
             // their highest differing coordinate bit
-            uint32_t diff = (uint32_t)((q[0] ^ pq[0]) | (q[1] ^ pq[1]) | (q[2] ^ pq[2]));
-            int hb = 31 - __builtin_clz(diff | 1u);
+            int hb = 31 - __builtin_clz(qdiff | 1u);
             level = D - 1 - hb;
             if (level > path_top) level = path_top;
             if (level < 0) level = 0;
@@ -498,7 +498,6 @@ struct Marcher {
         }
         if (c > 0) c = 0;   // malformed table guard: never descend below max depth
         path_top = level - 1;
-        pq[0] = q[0]; pq[1] = q[1]; pq[2] = q[2];
         ++nsteps;
         const int sshift = D - level;
         const int Sz = 1 << sshift;
@@ -507,11 +506,12 @@ struct Marcher {
         for (int ax = 0; ax < 3; ++ax) lo[ax] = (q[ax] >> sshift) << sshift;
 
         // Exit crossing of the node and the neighbouring cell.  Fast path:
-        // the float32 plane parameters, every decision certified by the
-        // error filter -- the exit axis by its margin over the other axes,
-        // each re-located coordinate by the margins of the two planes that
-        // bound its cell.  When a margin is too thin (ties, grazing), the
-        // exact path below decides everything again.
+        // the float32 plane parameters, every decision certified -- the exit
+        // axis by the error filter on its margin over the other axes, each
+        // re-located coordinate by the distance of its float32 cell
+        // coordinate from the nearest cell boundary.  When a margin is too
+        // thin (ties, grazing), the exact path below decides everything
+        // again.
         int xa = 0;
         float xP = 0.0f, xt = 0.0f;
         unsigned xmask = 0;
@@ -544,17 +544,19 @@ struct Marcher {
                 for (int ax = 0; ax < 3; ++ax) {
                     const float db = r.d[ax];
                     if (ax == xa || db == 0.0f) continue;
-                    const int hi = lo[ax] + Sz;
+                    // cell coordinate of the exit point in units of cells: g
+                    // and its error bound eg (xt is within 3.0000002u|t| of
+                    // the exact exit parameter; the fma and the add round
+                    // once each; 8u covers it all with margin).  A g at least
+                    // eg away from an integer certifies its cell.
                     const float pp = fmaf(xt, db, r.o[ax]);
-                    float g = (pp + 1.0f) * (0.5f * (float)N);
-                    g = fminf(fmaxf(g, (float)lo[ax]), (float)(hi - 1));
-                    const int k = (int)g;
-                    const float tk = (plane_of(k, h) - r.o[ax]) * r.inv[ax];
-                    const float tk1 = (plane_of(k + 1, h) - r.o[ax]) * r.inv[ax];
-                    // the point just after the exit lies in [plane k, plane k+1)
-                    const bool ok = db > 0.0f ? (k == lo[ax] || later(xt, tk)) && (k + 1 == hi || later(tk1, xt))
-                                              : (k + 1 == hi || later(xt, tk1)) && (k == lo[ax] || later(tk, xt));
-                    fast = fast && ok;
+                    const float half_n = 0.5f * (float)N;
+                    const float g = (pp + 1.0f) * half_n;
+                    const float eg = (fabsf(xt * db) + fabsf(pp) + 1.0f) * (half_n * 0x1p-21f);
+                    const float fl = floorf(g);
+                    const float fr = g - fl;
+                    const int k = (int)fl;
+                    fast = fast && fr > eg && fr < 1.0f - eg && k >= lo[ax] && k < lo[ax] + Sz;
                     nq[ax] = k;
                 }
             }
@@ -656,6 +658,7 @@ struct Marcher {
             }
         }
         if (leave) return true;
+        qdiff = (uint32_t)((q[0] ^ nq[0]) | (q[1] ^ nq[1]) | (q[2] ^ nq[2]));
         q[0] = nq[0]; q[1] = nq[1]; q[2] = nq[2];
         ev = nev;
         return false;
