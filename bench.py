@@ -242,7 +242,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": nbytes, "per_ray": counts,
-                "kernel": "k_query<F32, SH deg 2, FP32 accumulation>",
+                "kernel": "k_query_plain<F32, SH deg 2, sigma_min-pruned table, linear>",
                 "kernel_sources": kernel_sources_hash()}
 
     variants = {}

@@ -335,7 +335,9 @@ struct RayOut {
 // the new cell.  With SKIP the march uses the child table without the
 // leaves below sigma_min (DevTree::child_skip): every leaf it meets is
 // composited, so its whole row is fetched at once.
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP = false>
+// MODEL: LQ_LINEAR or LQ_EXP fixed at compile time, or -1 to take the model
+// passed to step().
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP = false, int MODEL = -1>
 struct Marcher {
     using S = Storage<ST>;
     using Acc = typename std::conditional<ACC64, double, float>::type;
@@ -644,7 +646,7 @@ struct Marcher {
                 const Acc delta = (Acc)dt * (Acc)dlen;
                 const Acc sd = (Acc)sig * delta;
                 Acc wgt;
-                if (model == LQ_EXP) wgt = -T * expm1(sd * Acc(-1));
+                if ((MODEL >= 0 ? MODEL : model) == LQ_EXP) wgt = -T * expm1(sd * Acc(-1));
                 else wgt = sd < T ? sd : T;
                 L0 += wgt * (Acc)phi0;
                 L1 += wgt * (Acc)phi1;

@@ -67,7 +67,7 @@ __device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; 
 // tree_of(ray) returns the DevTree a ray queries.  With TOP_LDS (one tree)
 // the block copies the tree's top grid into LDS; otherwise each ray reads
 // its tree's grid from global memory.
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, class TreeOf>
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, int MODEL, class TreeOf>
 __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeOf tree_of) {
     __shared__ int32_t s_path[10 * kBlock];   // per-lane node path, [level][lane]
     int32_t *path = s_path + threadIdx.x;
@@ -86,7 +86,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         if constexpr (TOP_LDS) return top_lds;
         return SKIP ? t.top_skip : t.top;
     };
-    Marcher<ST, DEG, ACC64, TRACE, SKIP> m;
+    Marcher<ST, DEG, ACC64, TRACE, SKIP, MODEL> m;
     int64_t ray = -1;            // ray held by this lane, -1 when idle
     uint32_t *ids = nullptr;
     int cur = blockIdx.x % kXcds;   // range this wave draws from (wave-uniform)
@@ -142,10 +142,31 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
     }
 }
 
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+// MODEL >= 0 fixes the transmittance model at compile time (the plain
+// queries), -1 takes it from the arguments.
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL>
 __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
                                                   unsigned long long *queue) {
-    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true>(a, queue, [&](int64_t) -> const DevTree & { return t; });
+    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true, MODEL>(a, queue,
+                                                              [&](int64_t) -> const DevTree & { return t; });
+}
+
+// The plain query (float32 accumulation, no trace) with a register budget
+// for five waves per SIMD: it waits on dependent loads, and a fifth wave
+// hides more of that than the few values the budget moves out of registers
+// (spilled only on the path of rays that miss the box) cost.  The
+// validation variants keep the default budget, which they need.
+template <int ST, int DEG, bool SKIP, int MODEL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_query_plain(
+    const DevTree t, const QueryArgs a, unsigned long long *queue) {
+    persistent_query<ST, DEG, false, false, SKIP, true, MODEL>(a, queue,
+                                                              [&](int64_t) -> const DevTree & { return t; });
+}
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL>
+constexpr auto query_kernel() {
+    if constexpr (!ACC64 && !TRACE) return k_query_plain<ST, DEG, SKIP, MODEL>;
+    else return k_query<ST, DEG, ACC64, TRACE, SKIP, MODEL>;
 }
 
 // several trees: rays [offsets[k], offsets[k+1]) query trees[k]
@@ -162,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_query_multi(const DevTree *trees, co
         }
         return trees[lo];
     };
-    persistent_query<ST, DEG, ACC64, false, SKIP, false>(a, queue, tree_of);
+    persistent_query<ST, DEG, ACC64, false, SKIP, false, -1>(a, queue, tree_of);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
@@ -188,9 +209,9 @@ int resident_blocks(Kern kern) {
     return nb;
 }
 
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP>
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL = -1>
 hipError_t launch_one(const DevTree &t, const QueryArgs &a, hipStream_t s) {
-    auto kern = k_query<ST, DEG, ACC64, TRACE, SKIP>;
+    auto kern = query_kernel<ST, DEG, ACC64, TRACE, SKIP, MODEL>();
     const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
     const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
     unsigned long long *queue = nullptr;
@@ -213,8 +234,9 @@ hipError_t launch_deg(const DevTree &t, const QueryArgs &a, bool trace, hipStrea
                             : launch_one<ST, DEG, false, true, false>(t, a, s);
     if (full) return acc64 ? launch_one<ST, DEG, true, false, false>(t, a, s)
                            : launch_one<ST, DEG, false, false, false>(t, a, s);
-    return acc64 ? launch_one<ST, DEG, true, false, true>(t, a, s)
-                 : launch_one<ST, DEG, false, false, true>(t, a, s);
+    if (acc64) return launch_one<ST, DEG, true, false, true>(t, a, s);
+    return a.model == LQ_EXP ? launch_one<ST, DEG, false, false, true, LQ_EXP>(t, a, s)
+                             : launch_one<ST, DEG, false, false, true, LQ_LINEAR>(t, a, s);
 }
 
 template <int ST>
