@@ -31,8 +31,8 @@ namespace lq {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRefillBelow = 40;     // refill when fewer lanes of a wave are busy
-constexpr int kStepsPerCheck = 8;    // steps between refill checks
+constexpr int kRefillBelow = 32;     // refill when fewer lanes of a wave are busy
+constexpr int kStepsPerCheck = 16;   // steps between refill checks
 constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
 static_assert(kXcds >= 1 && kXcds <= 31, "one bit per range in a 32-bit mask");
 constexpr unsigned kAllRanges = (1u << kXcds) - 1u;   // every range used up
