@@ -96,24 +96,31 @@ def traffic_from_profiles(kernel_tag):
 
 def cpu_baseline(tree, o, d, budget_s):
     """The FP64 oracle on the host cores, on a seeded sample of the rays,
-    chunk by chunk until the time budget is spent."""
+    chunk by chunk until the time budget is spent; then the same oracle on
+    one thread for a fifth of the budget."""
     import numpy as np
     from oracle import core
     threads = max(1, min(16, os.cpu_count() or 1))
     P = core.PreparedTree(tree, "f32")
     rng = np.random.default_rng(123)
     order = rng.permutation(len(o))
-    done, t_total = 0, 0.0
-    chunk = 131072
-    while done < len(o) and t_total < budget_s:
-        idx = np.sort(order[done: done + chunk])
-        t0 = time.perf_counter()
-        core.query(tree, o[idx], d[idx], model=core.LINEAR, prepared=P, n_threads=threads)
-        t_total += time.perf_counter() - t0
-        done += len(idx)
+
+    def run(n_threads, budget, chunk):
+        done, t_total = 0, 0.0
+        while done < len(o) and t_total < budget:
+            idx = np.sort(order[done: done + chunk])
+            t0 = time.perf_counter()
+            core.query(tree, o[idx], d[idx], model=core.LINEAR, prepared=P, n_threads=n_threads)
+            t_total += time.perf_counter() - t0
+            done += len(idx)
+        return done, t_total
+
+    done, t_total = run(threads, budget_s, 131072)
+    done1, t1 = run(1, budget_s / 5.0, 8192)
     return {"value": done / t_total, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} of the {len(o)} camera rays (seeded random subset), FP64 oracle "
-                      f"with its OpenMP loop over rays, {t_total:.1f} s"}
+                      f"with its OpenMP loop over rays, {t_total:.1f} s",
+            "one_thread": {"value": done1 / t1, "unit": "rays/s", "sample": f"{done1} rays, {t1:.1f} s"}}
 
 
 def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
@@ -176,6 +183,42 @@ def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
     return res
 
 
+def uneven_variant(lumiq):
+    """The uneven multi-luminaire batch (16 trees of depth 6 to 10, SH degree
+    3, float16, log-uniform ray counts): one persistent launch over all rays
+    against one launch per luminaire; load balance = sum of the isolated
+    launch times / the one launch's time."""
+    import torch
+    from inputs import uneven
+    t0 = time.perf_counter()
+    trees = uneven.trees()
+    o, d, offs = uneven.batch_rays()
+    log(f"uneven batch: {len(trees)} trees ready in {time.perf_counter() - t0:.0f} s, {len(o)} rays")
+    octs = [lumiq.Octree(t, "f16") for t in trees]
+    ot, dt = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    n = len(o)
+    rgb = torch.empty((n, 3), device="cuda")
+    alpha = torch.empty((n,), device="cuda")
+    ms_one, _ = time_launches(lambda: lumiq.query_multi(octs, offs, ot, dt, rgb=rgb, alpha=alpha), 10, 3)
+    iso = []
+    for k, oc in enumerate(octs):
+        a, b = int(offs[k]), int(offs[k + 1])
+        ok, dk, rk, ak = ot[a:b], dt[a:b], rgb[a:b], alpha[a:b]
+        ms_k, _ = time_launches(lambda: oc.query(ok, dk, rgb=rk, alpha=ak), 10, 2)
+        iso.append(ms_k)
+    res = {
+        "trees": [{"depth": t.depth, "leaves": int(t.n_leaves), "rays": int(offs[k + 1] - offs[k]),
+                   "ms_isolated": round(iso[k], 4)} for k, t in enumerate(trees)],
+        "rays": n, "storage": "f16", "sh_degree": 3,
+        "ms_one_launch": ms_one, "rays_per_s": n / (ms_one * 1e-3),
+        "ms_sum_isolated": sum(iso), "load_balance": sum(iso) / ms_one,
+    }
+    log(f"uneven batch: one launch {ms_one:.3f} ms, isolated sum {sum(iso):.3f} ms")
+    for oc in octs:
+        oc.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +230,8 @@ def main():
     ap.add_argument("--surrogate-steps", type=int, default=20000,
                     help="optimiser steps of the surrogate (0: skip the surrogate variant)")
     ap.add_argument("--surrogate-pairs", type=int, default=50_000_000)
+    ap.add_argument("--uneven", action="store_true",
+                    help="also run the uneven 16-luminaire batch (generates depth-10 trees: minutes of CPU)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -274,6 +319,9 @@ def main():
         if args.surrogate_steps > 0:
             variants["surrogate"] = surrogate_variant(args, lumiq, tree, oct32, ro_t, rd_t, rrgb)
         del ro_t, rd_t, rrgb, ralpha
+
+    if args.uneven:
+        variants["uneven_batch"] = uneven_variant(lumiq)
 
     cpu = None
     if not args.no_cpu:

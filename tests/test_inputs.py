@@ -80,3 +80,16 @@ def test_treefile_roundtrip(tmp_path, c0_tree):
     assert np.array_equal(t.child, c0_tree.child)
     assert np.array_equal(t.sigma, c0_tree.sigma) and np.array_equal(t.sh, c0_tree.sh)
     assert t.depth == c0_tree.depth and t.l_max == c0_tree.l_max
+
+
+def test_uneven_batch_recipe():
+    """The uneven multi-luminaire batch: 16 trees of depth 6..10 with at least
+    one of depth 10, SH degree 3; ray counts log-uniform in [2^10, 2^23]."""
+    from inputs import uneven
+    sp = uneven.specs()
+    assert len(sp) == 16 and max(s.depth for s in sp) == 10
+    assert all(6 <= s.depth <= 10 and s.sh_degree == 3 for s in sp)
+    assert [s.seed for s in sp] == list(range(40, 56))
+    c = uneven.ray_counts()
+    assert len(c) == 16 and all(2 ** 10 <= x <= 2 ** 23 for x in c)
+    assert c == uneven.ray_counts()   # deterministic
