@@ -1,7 +1,7 @@
 // mlp.hip -- training and inference of the learned surrogate on gfx950.
 //
-// Inference (k_infer): the whole network in registers, 16 rays per MFMA
-// tile, no LDS traffic; see the comment above the kernel.
+// Inference (k_infer): weights staged in LDS in MFMA lane order, 16 rays per
+// MFMA tile, activations in registers; see the comment above the kernel.
 //
 // Training step (one launch + one reduction launch):
 //   k_train_step: a workgroup of 4 waves stages the bfloat16 weight image in
@@ -406,15 +406,17 @@ __global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
 }
 
 // ------------------------------------------------------------ inference
-// Every weight of the network lives in registers (168 VGPRs per lane): a wave
-// loads its share of the bfloat16 image once and then runs tiles of 16 rays
-// through MFMA 16x16x32 (bf16 in, f32 accumulate) without touching LDS.
-// Lane l = 16 g + r (g = lane group, r = sample of the tile).  The weights are
-// the A operand, so output block fb of a layer leaves lane l holding features
-// 16 fb + 4 g + i (i < 4) of sample r; a 32-wide K block kb of the next layer
-// takes, in lane group g, the four rows of block 2 kb followed by the four of
-// block 2 kb + 1 — the weights are loaded in that same K order, so no value
-// moves between lanes.  The first layer's K order is chosen for the features
+// The weights live in LDS as MFMA operands in lane order ([block][lane],
+// 16 bytes per lane: one conflict-free ds_read_b128 per MFMA), read on every
+// use so that the compiler does not hoist them into registers (three waves
+// per SIMD instead of one).  Tiles of 16 rays go through MFMA 16x16x32 (bf16
+// in, f32 accumulate) with the activations in registers.  Lane l = 16 g + r
+// (g = lane group, r = sample of the tile).  The weights are the A operand,
+// so output block fb of a layer leaves lane l holding features 16 fb + 4 g + i
+// (i < 4) of sample r; a 32-wide K block kb of the next layer takes, in lane
+// group g, the four rows of block 2 kb followed by the four of block 2 kb + 1
+// -- the weights are staged in that same K order, so no value moves between
+// lanes.  The first layer's K order is chosen for the features
 // (slot_feature below): lane group g evaluates 10 + 5 consecutive
 // frequencies of two input variables by exact sincospi at the first
 // frequency of each run of five, then angle doubling.
@@ -508,7 +510,7 @@ __device__ inline int64_t ray_of(const int64_t *index, int64_t pos) { return ind
 // mode 0: radiance; mode 2: accumulate trust statistics against the
 // reference radiance.  With an index list the kernel answers rays
 // index[0 .. *n_dev) (the count read on the device), else rays 0 .. n.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_infer(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_infer(
     const float *o, const float *d, int64_t n, const int64_t *index, const unsigned long long *n_dev,
     const uint16_t *wimg, const float *bias, int mode, float *rgb, const float *ref, double *terr,
     double *tref, unsigned *tcnt) {
@@ -519,31 +521,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int lane = __lane_id();
     const int r16 = lane & 15, g = lane >> 4;
 
-    bf16x8 w1[4][4], wh[3][4][2], wo[2];
-#pragma unroll
-    for (int fb = 0; fb < 4; ++fb)
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const uint16_t *row = wimg + kI1 + (fb * 16 + r16) * kFeat;
-            u16x8 v;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = row[slot_feature(g, kb * 8 + e)];
-            w1[fb][kb] = __builtin_bit_cast(bf16x8, v);
+    // hidden and output layers: lane-ordered bf16x8 operands in LDS,
+    // [l][fb][kb][lane] (l = 3: the output layer, fb = 0 only)
+    __shared__ __align__(16) bf16x8 sWh[(3 * 4 * 2 + 2) * 64];
+    for (int i = threadIdx.x; i < (3 * 4 * 2 + 2) * 64; i += blockDim.x) {
+        const int ln = i & 63, blk = i >> 6;
+        const int rr = ln & 15, gg = ln >> 4;
+        const uint16_t *row;
+        int kb;
+        if (blk < 24) {
+            const int l = blk / 8, fb = (blk / 2) % 4;
+            kb = blk % 2;
+            row = wimg + kI2 + l * kHidden * kHidden + (fb * 16 + rr) * kHidden + 4 * gg;
+        } else {
+            kb = blk - 24;
+            row = wimg + kI5 + rr * kHidden + 4 * gg;
         }
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int fb = 0; fb < 4; ++fb)
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb) {
-                const uint16_t *row = wimg + kI2 + l * kHidden * kHidden + (fb * 16 + r16) * kHidden + 4 * g;
-                wh[l][fb][kb] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
-            }
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-        const uint16_t *row = wimg + kI5 + r16 * kHidden + 4 * g;
-        wo[kb] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
+        sWh[i] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
     }
+    // first layer: [fb][kb][lane], K in the feature-slot order
+    __shared__ __align__(16) bf16x8 sW1[4 * 4 * 64];
+    for (int i = threadIdx.x; i < 4 * 4 * 64; i += blockDim.x) {
+        const int ln = i & 63, blk = i >> 6;
+        const int rr = ln & 15, gg = ln >> 4;
+        const int fb = blk / 4, kb = blk % 4;
+        const uint16_t *row = wimg + kI1 + (fb * 16 + rr) * kFeat;
+        u16x8 v;
+        for (int e = 0; e < 8; ++e) v[e] = row[slot_feature(gg, kb * 8 + e)];
+        sW1[i] = __builtin_bit_cast(bf16x8, v);
+    }
+    __syncthreads();
 
     if (n_dev) n = (int64_t)*n_dev;
     const int64_t nblk = (n + 15) / 16;
@@ -584,7 +591,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-            for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(w1[fb][kb], x[kb], acc[fb]);
+            for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(((volatile bf16x8 *)sW1)[(fb * 4 + kb) * 64 + lane], x[kb], acc[fb]);
         bf16x8 h[2] = {relu_pack(acc[0], acc[1]), relu_pack(acc[2], acc[3])};
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -594,13 +601,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-                for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(wh[l][fb][kb], h[kb], acc[fb]);
+                for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(((volatile bf16x8 *)sWh)[((l * 4 + fb) * 2 + kb) * 64 + lane], h[kb], acc[fb]);
             h[0] = relu_pack(acc[0], acc[1]);
             h[1] = relu_pack(acc[2], acc[3]);
         }
         f32x4 y = *reinterpret_cast<const f32x4 *>(sB + 4 * kHidden + 4 * g);
-        y = mfma32(wo[0], h[0], y);
-        y = mfma32(wo[1], h[1], y);
+        y = mfma32(((volatile bf16x8 *)sWh)[24 * 64 + lane], h[0], y);
+        y = mfma32(((volatile bf16x8 *)sWh)[25 * 64 + lane], h[1], y);
 
         if (g == 0 && valid) {
             float L[3];
@@ -990,8 +997,8 @@ lq_status lq_mlp_train(lq_mlp *p, const float *o, const float *d, const float *r
 
 namespace lq {
 
-// one persistent wave per resident slot: the inference kernel holds the
-// network in registers, so its occupancy is what fits in the register file
+// one persistent block per resident slot (the occupancy the kernel's
+// register and LDS budget allows)
 static int infer_grid(int device) {
     int cus = 1, per_cu = 1;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
