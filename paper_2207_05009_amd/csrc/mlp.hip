@@ -407,9 +407,10 @@ __global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
 
 // ------------------------------------------------------------ inference
 // The weights live in LDS as MFMA operands in lane order ([block][lane],
-// 16 bytes per lane: one conflict-free ds_read_b128 per MFMA), read on every
-// use so that the compiler does not hoist them into registers (three waves
-// per SIMD instead of one).  Tiles of 16 rays go through MFMA 16x16x32 (bf16
+// 16 bytes per lane: one conflict-free ds_read_b128 per MFMA), shared by the
+// eight waves of a block and read again for every tile (a fence per tile
+// keeps the compiler from hoisting them into registers, which would leave
+// room for one wave per SIMD instead of four).  Tiles of 16 rays go through MFMA 16x16x32 (bf16
 // in, f32 accumulate) with the activations in registers.  Lane l = 16 g + r
 // (g = lane group, r = sample of the tile).  The weights are the A operand,
 // so output block fb of a layer leaves lane l holding features 16 fb + 4 g + i
@@ -454,11 +455,10 @@ constexpr bool slots_are_a_permutation() {
 }
 static_assert(slots_are_a_permutation(), "the feature slots must cover the encoding once");
 
-__device__ inline float pick6(const float (&x)[6], int i) {
-    float r = x[0];
-#pragma unroll
-    for (int k = 1; k < 6; ++k) r = i == k ? x[k] : r;
-    return r;
+// x[i] for a lane-dependent i, by selects on the six values (an indexed
+// read of a private array would put the array in memory)
+__device__ inline float pick6(float a0, float a1, float a2, float a3, float a4, float a5, int i) {
+    return i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : i == 3 ? a3 : i == 4 ? a4 : a5;
 }
 
 // sin, cos of pi 2^k x for k = 0..4 into f[0..10) (x already scaled by the
@@ -487,14 +487,20 @@ __device__ inline bf16x8 load_bf8(const uint16_t *p0, const uint16_t *p1) {
     return __builtin_bit_cast(bf16x8, v);
 }
 
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// bfloat16 of relu(x) for eight values: round first, then clear the negative
+// ones as signed 16-bit integers (a bfloat16 with its sign bit set is negative
+// as an int16), which equals rounding relu(x) and takes one packed max per pair
 __device__ inline bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
     bf16x8 h;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        h[i] = (__bf16)fmaxf(lo[i], 0.0f);
-        h[4 + i] = (__bf16)fmaxf(hi[i], 0.0f);
+        h[i] = (__bf16)lo[i];
+        h[4 + i] = (__bf16)hi[i];
     }
-    return h;
+    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(s16x8, h), zero));
 }
 
 __device__ inline void load_ray(const float *o, const float *d, int64_t ray, bool valid, float *oo, float *dd) {
@@ -510,7 +516,10 @@ __device__ inline int64_t ray_of(const int64_t *index, int64_t pos) { return ind
 // mode 0: radiance; mode 2: accumulate trust statistics against the
 // reference radiance.  With an index list the kernel answers rays
 // index[0 .. *n_dev) (the count read on the device), else rays 0 .. n.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_infer(
+constexpr int kInfBlock = 512;               // inference block: eight waves share one copy of the weights
+constexpr int kInfWaves = kInfBlock / 64;
+
+__global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_infer(
     const float *o, const float *d, int64_t n, const int64_t *index, const unsigned long long *n_dev,
     const uint16_t *wimg, const float *bias, int mode, float *rgb, const float *ref, double *terr,
     double *tref, unsigned *tcnt) {
@@ -554,14 +563,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 
     if (n_dev) n = (int64_t)*n_dev;
     const int64_t nblk = (n + 15) / 16;
-    const int64_t wstride = (int64_t)gridDim.x * kWaves;
-    int64_t blk = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t wstride = (int64_t)gridDim.x * kInfWaves;
+    int64_t blk = (int64_t)blockIdx.x * kInfWaves + wave;
     // the next tile's rays are loaded while the current one computes
     bool nvalid = blk * 16 + r16 < n;
     int64_t nray = nvalid ? ray_of(index, blk * 16 + r16) : 0;
     float no[3], nd[3];
     load_ray(o, d, nray, nvalid, no, nd);
     for (; blk < nblk; blk += wstride) {
+        // a fence per tile keeps the weight reads inside the loop (hoisted,
+        // the operands would need the register file of a single wave)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int64_t ray = nray;
         const bool valid = nvalid;
         float oo[3] = {no[0], no[1], no[2]}, dd[3] = {nd[0], nd[1], nd[2]};
@@ -572,18 +584,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 
         float x6[6] = {0, 0, 0, 0, 0, 0};
         const bool act = valid && sphere_x6(oo, dd, x6);
+        const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
         float f[32];
-        const float va = pick6(x6, run_a(g)), vb = pick6(x6, run_b(g));
+        const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));
+        const float vb = pick6(e0, e1, e2, e3, e4, e5, run_b(g));
         sincos_run5(va, f);
         sincos_run5(va * 32.0f, f + 10);
         sincos_run5(run_b0(g) ? vb * 32.0f : vb, f + 20);
-        f[30] = g < 3 ? pick6(x6, 2 * g) : 0.0f;
-        f[31] = g < 3 ? pick6(x6, 2 * g + 1) : 0.0f;
+        f[30] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g) : 0.0f;
+        f[31] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g + 1) : 0.0f;
         bf16x8 x[4];
+        const bf16x8 zero8 = {};
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
+        for (int kb = 0; kb < 4; ++kb) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) x[kb][e] = (__bf16)(act ? f[kb * 8 + e] : 0.0f);
+            for (int e = 0; e < 8; ++e) x[kb][e] = (__bf16)f[kb * 8 + e];
+            x[kb] = act ? x[kb] : zero8;   // rays that miss the sphere: zero features
+        }
 
         f32x4 acc[4];
 #pragma unroll
@@ -591,7 +608,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-            for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(((volatile bf16x8 *)sW1)[(fb * 4 + kb) * 64 + lane], x[kb], acc[fb]);
+            for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(sW1[(fb * 4 + kb) * 64 + lane], x[kb], acc[fb]);
         bf16x8 h[2] = {relu_pack(acc[0], acc[1]), relu_pack(acc[2], acc[3])};
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -601,13 +618,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-                for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(((volatile bf16x8 *)sWh)[((l * 4 + fb) * 2 + kb) * 64 + lane], h[kb], acc[fb]);
+                for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(sWh[((l * 4 + fb) * 2 + kb) * 64 + lane], h[kb], acc[fb]);
             h[0] = relu_pack(acc[0], acc[1]);
             h[1] = relu_pack(acc[2], acc[3]);
         }
         f32x4 y = *reinterpret_cast<const f32x4 *>(sB + 4 * kHidden + 4 * g);
-        y = mfma32(((volatile bf16x8 *)sWh)[24 * 64 + lane], h[0], y);
-        y = mfma32(((volatile bf16x8 *)sWh)[25 * 64 + lane], h[1], y);
+        y = mfma32(sWh[24 * 64 + lane], h[0], y);
+        y = mfma32(sWh[25 * 64 + lane], h[1], y);
 
         if (g == 0 && valid) {
             float L[3];
@@ -615,7 +632,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             for (int c = 0; c < 3; ++c) L[c] = act ? fmaxf(expf(y[c]) - kEpsOut, 0.0f) : 0.0f;
             if (mode == 2) {
                 if (act) {
-                    const int bin = trust_bin(x6);
+                    const float p6[6] = {e0, e1, e2, e3, e4, e5};
+                    const int bin = trust_bin(p6);
                     double e2 = 0.0, r2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -1002,7 +1020,7 @@ namespace lq {
 static int infer_grid(int device) {
     int cus = 1, per_cu = 1;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_infer, 256, 0) != hipSuccess || per_cu < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_infer, kInfBlock, 0) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 1;
     }
@@ -1023,7 +1041,7 @@ lq_status lq_mlp_forward(const lq_mlp *p, const float *o, const float *d, int64_
     if ((st = check_dev_ptr(o, n * 12, p->device, "origins")) != LQ_OK) return st;
     if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
     if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), 0, (hipStream_t)stream, o, d, n,
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, (hipStream_t)stream, o, d, n,
                        (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wimg, p->bias, 0, rgb,
                        (const float *)nullptr, (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
     e = hipGetLastError();
@@ -1048,7 +1066,7 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
     double *tref = terr + kTrustBins;
     unsigned *tcnt = reinterpret_cast<unsigned *>(tref + kTrustBins);
     hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), 0, s, o, d, n, (const int64_t *)nullptr,
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, (const int64_t *)nullptr,
                        (const unsigned long long *)nullptr, p->wimg, p->bias, 2, (float *)nullptr, rgb_ref, terr,
                        tref, tcnt);
     hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tref, tcnt,
@@ -1098,7 +1116,7 @@ lq_status lq_mlp_infer(const lq_mlp *p, const lq_octree *fallback, const float *
     const int64_t cblocks = (n + kClassRays - 1) / kClassRays;
     hipLaunchKernelGGL(k_classify, dim3((unsigned)cblocks), dim3(256), 0, s, o, d, n, p->trust, rgb, used_fallback,
                        mlp_list, cnt, oct_list, cnt + 1);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(256), 0, s, o, d, n, mlp_list,
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, mlp_list,
                        (const unsigned long long *)cnt, p->wimg, p->bias, 0, rgb, (const float *)nullptr,
                        (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
     e = hipGetLastError();
