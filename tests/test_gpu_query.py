@@ -254,3 +254,45 @@ def test_abi_rejects_bad_pointers(lq, c0_tree):
                              C.c_void_p(rgb.data_ptr()), None, 0, 1 << 9, None)
     assert st == -1
     assert L.lq_query_radiance(oct_.handle, None, None, 0, None, None, 0, 0, None) == 0
+
+
+@pytest.fixture(scope="module")
+def full_rays():
+    cam = inputs.rays.pinhole(2048, 2048)
+    room = inputs.rays.room_to_proxy(1 << 24, 20)
+    return {"camera": cam, "room": room}
+
+
+@pytest.mark.parametrize("workload", ["camera", "room"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_full_size_error_against_oracle(lq, c1_tree, full_rays, workload, storage):
+    """Every benchmarked configuration at full size, in the launch the
+    benchmark times: a seeded sample of rays must match the oracle on the
+    stored (dequantised) tree to 1e-4; the error against the float32 tree --
+    the storage error -- is stated."""
+    import torch
+    o, d = full_rays[workload]
+    _say(f"full-size {workload} batch, {len(o)} rays, storage {storage}")
+    oct_ = lq.Octree(c1_tree, storage)
+    rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(11).choice(len(o), 20000, replace=False))
+    g_rgb = rgb.cpu().numpy()[idx].astype(np.float64)
+    g_alpha = alpha.cpu().numpy()[idx].astype(np.float64)
+    oct_.free()
+    orc = core.query(c1_tree, o[idx], d[idx], model=0, storage=storage)
+    amb = orc["alt_valid"].astype(bool)
+    err = parity.rel_err(g_rgb, orc["L"], c1_tree.l_max).max(1)
+    alt_err = parity.rel_err(g_rgb, orc["alt_L"], c1_tree.l_max).max(1)
+    err = np.where(amb, np.minimum(err, alt_err), err)
+    aerr = np.abs(g_alpha - orc["alpha"])
+    aerr = np.where(amb, np.minimum(aerr, np.abs(g_alpha - orc["alt_alpha"])), aerr)
+    _say(f"{workload} {storage} vs oracle on the stored tree: max {err.max():.2e} "
+         f"p99 {np.quantile(err, 0.99):.2e} max |dalpha| {aerr.max():.2e} ({int(amb.sum())} ambiguous)")
+    assert err.max() <= parity.RTOL and aerr.max() <= parity.RTOL
+    if storage != "f32":
+        orc32 = core.query(c1_tree, o[idx], d[idx], model=0)
+        e32 = parity.rel_err(g_rgb, orc32["L"], c1_tree.l_max).max(1)
+        rl2 = float(np.linalg.norm(g_rgb - orc32["L"]) / np.linalg.norm(orc32["L"]))
+        _say(f"{workload} {storage} storage error vs the float32 tree: median {np.median(e32):.2e} "
+             f"p99 {np.quantile(e32, 0.99):.2e} max {e32.max():.2e} rel-L2 {rl2:.2e}")
