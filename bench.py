@@ -191,7 +191,7 @@ def uneven_variant(lumiq):
     import torch
     from inputs import uneven
     t0 = time.perf_counter()
-    trees = uneven.trees()
+    trees = uneven.trees(progress=log)
     o, d, offs = uneven.batch_rays()
     log(f"uneven batch: {len(trees)} trees ready in {time.perf_counter() - t0:.0f} s, {len(o)} rays")
     octs = [lumiq.Octree(t, "f16") for t in trees]

@@ -64,17 +64,20 @@ __device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool
 __device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; }
 
 // the persistent loop shared by the single- and multi-tree kernels;
-// tree_of(ray) returns the DevTree a ray queries.  With TOP_LDS (one tree)
+// tree_index(ray) finds the tree a ray queries (once, when a lane takes the
+// ray) and tree_at(k) returns tree k.  With TOP_LDS (one tree)
 // the block copies the tree's top grid into LDS; otherwise each ray reads
 // its tree's grid from global memory.
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, int MODEL, class TreeOf>
-__device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeOf tree_of) {
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, int MODEL, class TreeIndex,
+          class TreeAt>
+__device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeIndex tree_index,
+                                        TreeAt tree_at) {
     __shared__ int32_t s_path[10 * kBlock];   // per-lane node path, [level][lane]
     int32_t *path = s_path + threadIdx.x;
     const int32_t *top_lds = nullptr;
     if constexpr (TOP_LDS) {
         __shared__ int32_t s_top[kTopCells];
-        const DevTree &t0 = tree_of(0);
+        const DevTree &t0 = tree_at(0);
         const int32_t *src = SKIP ? t0.top_skip : t0.top;
         if (src) {
             for (int i = threadIdx.x; i < kTopCells; i += kBlock) s_top[i] = src[i];
@@ -88,6 +91,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
     };
     Marcher<ST, DEG, ACC64, TRACE, SKIP, MODEL> m;
     int64_t ray = -1;            // ray held by this lane, -1 when idle
+    int tk = 0;                  // tree of that ray
     uint32_t *ids = nullptr;
     int cur = blockIdx.x % kXcds;   // range this wave draws from (wave-uniform)
     unsigned used_up = 0;           // ranges known to be exhausted (wave-uniform)
@@ -112,7 +116,8 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
                     if (slot < len) {
                         const int64_t idx = a.index ? a.index[start + slot] : start + slot;
                         ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)idx * a.max_ids : nullptr;
-                        if (m.init(tree_of(idx), a.o + 3 * idx, a.d + 3 * idx)) {
+                        tk = tree_index(idx);
+                        if (m.init(tree_at(tk), a.o + 3 * idx, a.d + 3 * idx)) {
                             ray = idx;
                             want = false;
                         } else {
@@ -133,7 +138,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         }
         if (__all(ray < 0 && used_up == kAllRanges)) break;
         for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
-            const DevTree &tr = tree_of(ray);
+            const DevTree &tr = tree_at(tk);
             if (m.step(tr, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock, top_of(tr))) {
                 write_ray(a, ray, m, TRACE);
                 ray = -1;
@@ -147,8 +152,8 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
 template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL>
 __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
                                                   unsigned long long *queue) {
-    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true, MODEL>(a, queue,
-                                                              [&](int64_t) -> const DevTree & { return t; });
+    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true, MODEL>(
+        a, queue, [](int64_t) { return 0; }, [&](int) -> const DevTree & { return t; });
 }
 
 // The plain query (float32 accumulation, no trace) with a register budget
@@ -159,8 +164,8 @@ __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryAr
 template <int ST, int DEG, bool SKIP, int MODEL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_query_plain(
     const DevTree t, const QueryArgs a, unsigned long long *queue) {
-    persistent_query<ST, DEG, false, false, SKIP, true, MODEL>(a, queue,
-                                                              [&](int64_t) -> const DevTree & { return t; });
+    persistent_query<ST, DEG, false, false, SKIP, true, MODEL>(
+        a, queue, [](int64_t) { return 0; }, [&](int) -> const DevTree & { return t; });
 }
 
 template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL>
@@ -169,21 +174,38 @@ constexpr auto query_kernel() {
     else return k_query<ST, DEG, ACC64, TRACE, SKIP, MODEL>;
 }
 
-// several trees: rays [offsets[k], offsets[k+1]) query trees[k]
-template <int ST, int DEG, bool ACC64, bool SKIP>
-__global__ __launch_bounds__(kBlock) void k_query_multi(const DevTree *trees, const int64_t *offsets,
-                                                        int n_trees, const QueryArgs a,
-                                                        unsigned long long *queue) {
-    auto tree_of = [&](int64_t ray) -> const DevTree & {
+// several trees: rays [offsets[k], offsets[k+1]) query trees[k]; the tree of
+// a ray is found by binary search when a lane takes it.  The float32 kernels
+// are specialised on the model like the plain ones, but keep the default
+// register budget: a lane's tree fields come from memory and need registers
+// (with the five-wave budget they spill, 10.7 vs 7.9 ms on the uneven batch).
+template <int ST, int DEG, bool ACC64, bool SKIP, int MODEL>
+__device__ inline void multi_query(const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
+                                   unsigned long long *queue) {
+    auto tree_index = [&](int64_t ray) {
         int lo = 0, hi = n_trees;            // offsets[lo] <= ray < offsets[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (offsets[mid] <= ray) lo = mid;
             else hi = mid;
         }
-        return trees[lo];
+        return lo;
     };
-    persistent_query<ST, DEG, ACC64, false, SKIP, false, -1>(a, queue, tree_of);
+    persistent_query<ST, DEG, ACC64, false, SKIP, false, MODEL>(
+        a, queue, tree_index, [&](int k) -> const DevTree & { return trees[k]; });
+}
+
+template <int ST, int DEG, bool ACC64, bool SKIP>
+__global__ __launch_bounds__(kBlock) void k_query_multi(const DevTree *trees, const int64_t *offsets,
+                                                        int n_trees, const QueryArgs a,
+                                                        unsigned long long *queue) {
+    multi_query<ST, DEG, ACC64, SKIP, -1>(trees, offsets, n_trees, a, queue);
+}
+
+template <int ST, int DEG, bool SKIP, int MODEL>
+__global__ __launch_bounds__(kBlock) void k_query_multi_plain(
+    const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs a, unsigned long long *queue) {
+    multi_query<ST, DEG, false, SKIP, MODEL>(trees, offsets, n_trees, a, queue);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
@@ -251,10 +273,13 @@ hipError_t launch_st(const DevTree &t, const QueryArgs &a, bool trace, hipStream
     return hipErrorInvalidValue;
 }
 
-template <int ST, int DEG, bool ACC64, bool SKIP>
+template <int ST, int DEG, bool ACC64, bool SKIP, int MODEL = -1>
 hipError_t launch_multi_one(const DevTree *trees, const int64_t *offsets, int n_trees, const QueryArgs &a,
                             hipStream_t s) {
-    auto kern = k_query_multi<ST, DEG, ACC64, SKIP>;
+    auto kern = [] {
+        if constexpr (!ACC64 && MODEL >= 0) return k_query_multi_plain<ST, DEG, SKIP, MODEL>;
+        else return k_query_multi<ST, DEG, ACC64, SKIP>;
+    }();
     const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
     const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
     unsigned long long *queue = nullptr;
@@ -274,8 +299,9 @@ hipError_t launch_multi_deg(const DevTree *trees, const int64_t *offsets, int n_
     const bool full = (a.flags & LQ_NO_SIGMA_SKIP) != 0;
     if (full) return acc64 ? launch_multi_one<ST, DEG, true, false>(trees, offsets, n_trees, a, s)
                            : launch_multi_one<ST, DEG, false, false>(trees, offsets, n_trees, a, s);
-    return acc64 ? launch_multi_one<ST, DEG, true, true>(trees, offsets, n_trees, a, s)
-                 : launch_multi_one<ST, DEG, false, true>(trees, offsets, n_trees, a, s);
+    if (acc64) return launch_multi_one<ST, DEG, true, true>(trees, offsets, n_trees, a, s);
+    return a.model == LQ_EXP ? launch_multi_one<ST, DEG, false, true, LQ_EXP>(trees, offsets, n_trees, a, s)
+                             : launch_multi_one<ST, DEG, false, true, LQ_LINEAR>(trees, offsets, n_trees, a, s);
 }
 
 template <int ST>
