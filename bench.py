@@ -117,10 +117,20 @@ def cpu_baseline(tree, o, d, budget_s):
 
     done, t_total = run(threads, budget_s, 131072)
     done1, t1 = run(1, budget_s / 5.0, 8192)
+    # the surrogate's FP64 oracle (numpy forward pass) on room rays, for context
+    import inputs
+    from oracle import mlp as omlp
+    ro, rd = inputs.rays.room_to_proxy(65536, 21)
+    theta = omlp.he_uniform(31)
+    t0 = time.perf_counter()
+    omlp.predict(theta, ro, rd)
+    t_mlp = time.perf_counter() - t0
     return {"value": done / t_total, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} of the {len(o)} camera rays (seeded random subset), FP64 oracle "
                       f"with its OpenMP loop over rays, {t_total:.1f} s",
-            "one_thread": {"value": done1 / t1, "unit": "rays/s", "sample": f"{done1} rays, {t1:.1f} s"}}
+            "one_thread": {"value": done1 / t1, "unit": "rays/s", "sample": f"{done1} rays, {t1:.1f} s"},
+            "surrogate_oracle": {"value": len(ro) / t_mlp, "unit": "rays/s",
+                                 "sample": f"{len(ro)} room rays, numpy FP64 forward, {t_mlp:.2f} s"}}
 
 
 def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):

@@ -351,18 +351,50 @@ __device__ inline int bias_index(int p) {
 }
 
 // sum the partial rows in a fixed order; optional Adam update
-__global__ void k_reduce_adam(const float *part, int rows, float *theta, float *m, float *v, uint16_t *wimg,
-                              float *bias, const float *loss_part, float *loss_out, float *grad_out,
-                              int update, float lr, float b1, float b2, float eps, float c1, float c2) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
-        float s = 0.0f;
-        for (int r = 0; r < rows; ++r) s += loss_part[r];
-        *loss_out = s;
-    }
-    if (p >= kParams) return;
+// Sum of the partial gradient rows and the Adam update.  A block takes
+// kRedParams consecutive parameters; its four waves sum fixed quarters of the
+// rows (eight interleaved accumulators each, to keep eight loads in flight)
+// and wave 0 adds the quarters in a fixed order: the result does not depend
+// on scheduling, so a resumed run repeats an uninterrupted one bit for bit.
+// Block 0 also sums the per-workgroup losses with a fixed LDS tree.
+constexpr int kRedParams = 64;
+
+__global__ __launch_bounds__(256) void k_reduce_adam(const float *part, int rows, float *theta, float *m, float *v,
+                                                     uint16_t *wimg, float *bias, const float *loss_part,
+                                                     float *loss_out, float *grad_out, int update, float lr,
+                                                     float b1, float b2, float eps, float c1, float c2) {
+    __shared__ float s_part[4][kRedParams];
+    __shared__ float s_loss[256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * kRedParams + lane;
     float g = 0.0f;
-    for (int r = 0; r < rows; ++r) g += part[(size_t)r * kParams + p];
+    if (p < kParams) {
+        const int r0 = rows * w / 4, r1 = rows * (w + 1) / 4;
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        int r = r0;
+        for (; r + 8 <= r1; r += 8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += part[(size_t)(r + j) * kParams + p];
+        }
+        for (; r < r1; ++r) acc[0] += part[(size_t)r * kParams + p];
+        g = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    }
+    s_part[w][lane] = g;
+    if (blockIdx.x == 0) {
+        float l = 0.0f;
+        for (int r = threadIdx.x; r < rows; r += 256) l += loss_part[r];
+        s_loss[threadIdx.x] = l;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (int st = 128; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) s_loss[threadIdx.x] += s_loss[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *loss_out = s_loss[0];
+    }
+    if (w != 0 || p >= kParams) return;
+    g = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
     if (grad_out) grad_out[p] = g;
     if (!update) return;
     const float mm = b1 * m[p] + (1.0f - b1) * g;
@@ -952,7 +984,7 @@ lq_status lq_mlp_grad(lq_mlp *p, const float *o, const float *d, const float *rg
     int rows = 0;
     e = launch_step(p, o, d, rgb, n, 0, n, rows, s);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, p->part, rows, p->theta,
+        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, p->part, rows, p->theta,
                            p->m, p->v, p->wimg, p->bias, p->loss_part, loss_dev, grad, 0, 0.0f, 0.0f, 0.0f, 0.0f,
                            0.0f, 0.0f);
         e = hipGetLastError();
@@ -997,7 +1029,7 @@ lq_status lq_mlp_train(lq_mlp *p, const float *o, const float *d, const float *r
         const double t = (double)(gstep + 1);
         const float c1 = (float)(1.0 / (1.0 - pow((double)cfg->beta1, t)));
         const float c2 = (float)(1.0 / (1.0 - pow((double)cfg->beta2, t)));
-        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, p->part, rows, p->theta,
+        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, p->part, rows, p->theta,
                            p->m, p->v, p->wimg, p->bias, p->loss_part, loss_dev + k, (float *)nullptr, 1, lr,
                            cfg->beta1, cfg->beta2, cfg->eps, c1, c2);
         e = hipGetLastError();
