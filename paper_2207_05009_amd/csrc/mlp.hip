@@ -451,8 +451,8 @@ __global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
 // -- the weights are staged in that same K order, so no value moves between
 // lanes.  The first layer's K order is chosen for the features
 // (slot_feature below): lane group g evaluates 10 + 5 consecutive
-// frequencies of two input variables by exact sincospi at the first
-// frequency of each run of five, then angle doubling.
+// frequencies of two input variables: the hardware sine and cosine at the
+// first frequency of each run of five, then angle doubling.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
@@ -494,12 +494,15 @@ __device__ inline float pick6(float a0, float a1, float a2, float a3, float a4, 
 }
 
 // sin, cos of pi 2^k x for k = 0..4 into f[0..10) (x already scaled by the
-// run's first frequency): exact sincospi, then sin 2a = 2 sin a cos a and
+// run's first frequency, |x| <= 32): the hardware sine and cosine of the
+// argument reduced exactly to [-1/2, 1/2] turn (within 1.3e-7 of the exact
+// values over this range), then sin 2a = 2 sin a cos a and
 // cos 2a = (cos a - sin a)(cos a + sin a).  Four doublings amplify the
-// initial error 16-fold: below 1e-6, far under the bfloat16 feature rounding.
+// initial error 16-fold: about 2e-6, far under the bfloat16 feature rounding.
 __device__ inline void sincos_run5(float x, float *f) {
-    float sn, cs;
-    sincospif(x, &sn, &cs);
+    const float h = 0.5f * x;          // turns
+    const float r = h - rintf(h);      // exact for |h| < 2^23
+    float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
     f[0] = sn;
     f[1] = cs;
 #pragma unroll
