@@ -151,7 +151,8 @@ lq_status lq_query_trace(const lq_octree *tree, const float *origins, const floa
  * trees[k], all in one persistent launch.  ray_offsets is a HOST array of
  * n_trees + 1 non-decreasing values starting at 0; origins/dirs/rgb/alpha
  * are device arrays of ray_offsets[n_trees] rays.  Every tree must live on
- * the same device.  Same per-ray semantics as lq_query_radiance.
+ * the same device and share its storage and SH degree, which must be 2 or 3
+ * (else LQ_ERR_UNSUPPORTED).  Same per-ray semantics as lq_query_radiance.
  */
 lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees,
                                   const int64_t *ray_offsets, const float *origins,
