@@ -88,11 +88,69 @@ __device__ void stage_weights(const uint16_t *wimg, const float *bias, uint16_t 
     for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
 }
 
-// features of the 16 samples of a wave: lane l does sample l % 16, feature
-// columns 32 (l / 16) .. + 31.  Returns whether the lane's sample is active.
+// variable whose 10 frequencies lane group g evaluates, the variable of its
+// run of 5 and the first frequency of that run
+__host__ __device__ constexpr int run_a(int g) { return g == 0 ? 0 : g == 1 ? 2 : g == 2 ? 3 : 5; }
+__host__ __device__ constexpr int run_b(int g) { return g < 2 ? 1 : 4; }
+__host__ __device__ constexpr int run_b0(int g) { return (g & 1) ? 5 : 0; }
+
+// feature (index of the Fourier encoding, 0..127) that slot j (0..31) of lane
+// group g holds: j < 20 sin/cos of the 10-run, 20 <= j < 30 the 5-run,
+// j = 30, 31 the raw variables 2g, 2g + 1 (group 3: the two zero pads)
+__host__ __device__ constexpr int slot_feature(int g, int j) {
+    return j < 20   ? (1 + 2 * kFreq) * run_a(g) + 1 + j
+           : j < 30 ? (1 + 2 * kFreq) * run_b(g) + 1 + 2 * run_b0(g) + (j - 20)
+           : g == 3 ? kFeatUsed + (j - 30)
+                    : (1 + 2 * kFreq) * (2 * g + (j - 30));
+}
+constexpr bool slots_are_a_permutation() {
+    bool seen[kFeat] = {};
+    for (int g = 0; g < 4; ++g)
+        for (int j = 0; j < 32; ++j) {
+            const int c = slot_feature(g, j);
+            if (c < 0 || c >= kFeat || seen[c]) return false;
+            seen[c] = true;
+        }
+    return true;
+}
+static_assert(slots_are_a_permutation(), "the feature slots must cover the encoding once");
+
+// x[i] for a lane-dependent i, by selects on the six values (an indexed
+// read of a private array would put the array in memory)
+__device__ inline float pick6(float a0, float a1, float a2, float a3, float a4, float a5, int i) {
+    return i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : i == 3 ? a3 : i == 4 ? a4 : a5;
+}
+
+// sin, cos of pi 2^k x for k = 0..4 into f[0..10) (x already scaled by the
+// run's first frequency, |x| <= 32): the hardware sine and cosine of the
+// argument reduced exactly to [-1/2, 1/2] turn (within 1.3e-7 of the exact
+// values over this range), then sin 2a = 2 sin a cos a and
+// cos 2a = (cos a - sin a)(cos a + sin a).  Four doublings amplify the
+// initial error 16-fold: about 2e-6, far under the bfloat16 feature rounding.
+__device__ inline void sincos_run5(float x, float *f) {
+    const float h = 0.5f * x;          // turns
+    const float r = h - rintf(h);      // exact for |h| < 2^23
+    float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+    f[0] = sn;
+    f[1] = cs;
+#pragma unroll
+    for (int k = 1; k < 5; ++k) {
+        const float s2 = 2.0f * sn * cs;
+        const float c2 = (cs - sn) * (cs + sn);
+        sn = s2;
+        cs = c2;
+        f[2 * k] = sn;
+        f[2 * k + 1] = cs;
+    }
+}
+
+// features of the 16 samples of a wave: lane l does sample l % 16 and the
+// 32 feature slots of its lane group (slot_feature), written to their
+// columns of the sample's LDS row.  Returns whether the lane's sample is
+// active (its line meets the bounding sphere).
 __device__ bool wave_features(const float *o, const float *d, int64_t ray, bool valid, uint16_t *sF,
                               int row) {
-    const int lane = __lane_id();
+    const int g = __lane_id() >> 4;
     float x6[6] = {0, 0, 0, 0, 0, 0};
     bool act = false;
     if (valid) {
@@ -100,10 +158,18 @@ __device__ bool wave_features(const float *o, const float *d, int64_t ray, bool 
         float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
         act = sphere_x6(oo, dd, x6);
     }
-    const int c0 = (lane >> 4) * 32;
-    uint16_t *dst = sF + row * kSF + c0;
-#pragma unroll 4
-    for (int c = 0; c < 32; ++c) dst[c] = f2bf(act ? feature(x6, c0 + c) : 0.0f);
+    const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
+    float f[32];
+    const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));
+    const float vb = pick6(e0, e1, e2, e3, e4, e5, run_b(g));
+    sincos_run5(va, f);
+    sincos_run5(va * 32.0f, f + 10);
+    sincos_run5(run_b0(g) ? vb * 32.0f : vb, f + 20);
+    f[30] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g) : 0.0f;
+    f[31] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g + 1) : 0.0f;
+    uint16_t *dst = sF + row * kSF;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) dst[slot_feature(g, j)] = f2bf(act ? f[j] : 0.0f);
     return act;
 }
 
@@ -458,62 +524,6 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// variable whose 10 frequencies lane group g evaluates, the variable of its
-// run of 5 and the first frequency of that run
-__host__ __device__ constexpr int run_a(int g) { return g == 0 ? 0 : g == 1 ? 2 : g == 2 ? 3 : 5; }
-__host__ __device__ constexpr int run_b(int g) { return g < 2 ? 1 : 4; }
-__host__ __device__ constexpr int run_b0(int g) { return (g & 1) ? 5 : 0; }
-
-// feature (index of the Fourier encoding, 0..127) that slot j (0..31) of lane
-// group g holds: j < 20 sin/cos of the 10-run, 20 <= j < 30 the 5-run,
-// j = 30, 31 the raw variables 2g, 2g + 1 (group 3: the two zero pads)
-__host__ __device__ constexpr int slot_feature(int g, int j) {
-    return j < 20   ? (1 + 2 * kFreq) * run_a(g) + 1 + j
-           : j < 30 ? (1 + 2 * kFreq) * run_b(g) + 1 + 2 * run_b0(g) + (j - 20)
-           : g == 3 ? kFeatUsed + (j - 30)
-                    : (1 + 2 * kFreq) * (2 * g + (j - 30));
-}
-constexpr bool slots_are_a_permutation() {
-    bool seen[kFeat] = {};
-    for (int g = 0; g < 4; ++g)
-        for (int j = 0; j < 32; ++j) {
-            const int c = slot_feature(g, j);
-            if (c < 0 || c >= kFeat || seen[c]) return false;
-            seen[c] = true;
-        }
-    return true;
-}
-static_assert(slots_are_a_permutation(), "the feature slots must cover the encoding once");
-
-// x[i] for a lane-dependent i, by selects on the six values (an indexed
-// read of a private array would put the array in memory)
-__device__ inline float pick6(float a0, float a1, float a2, float a3, float a4, float a5, int i) {
-    return i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : i == 3 ? a3 : i == 4 ? a4 : a5;
-}
-
-// sin, cos of pi 2^k x for k = 0..4 into f[0..10) (x already scaled by the
-// run's first frequency, |x| <= 32): the hardware sine and cosine of the
-// argument reduced exactly to [-1/2, 1/2] turn (within 1.3e-7 of the exact
-// values over this range), then sin 2a = 2 sin a cos a and
-// cos 2a = (cos a - sin a)(cos a + sin a).  Four doublings amplify the
-// initial error 16-fold: about 2e-6, far under the bfloat16 feature rounding.
-__device__ inline void sincos_run5(float x, float *f) {
-    const float h = 0.5f * x;          // turns
-    const float r = h - rintf(h);      // exact for |h| < 2^23
-    float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
-    f[0] = sn;
-    f[1] = cs;
-#pragma unroll
-    for (int k = 1; k < 5; ++k) {
-        const float s2 = 2.0f * sn * cs;
-        const float c2 = (cs - sn) * (cs + sn);
-        sn = s2;
-        cs = c2;
-        f[2 * k] = sn;
-        f[2 * k + 1] = cs;
-    }
 }
 
 __device__ inline bf16x8 load_bf8(const uint16_t *p0, const uint16_t *p1) {

@@ -91,18 +91,6 @@ __device__ inline bool sphere_x6(const float *o, const float *d, float *x6) {
     return true;
 }
 
-// feature c (0..127) of the encoded input
-__device__ inline float feature(const float *x6, int c) {
-    if (c >= kFeatUsed) return 0.0f;
-    const int v = c / (1 + 2 * kFreq);
-    const int j = c - v * (1 + 2 * kFreq);
-    const float x = x6[v];
-    if (j == 0) return x;
-    const int k = (j - 1) >> 1;
-    const float a = ldexpf(x, k);            // sin(2^k pi x) = sinpi(2^k x)
-    return (j - 1) & 1 ? cospif(a) : sinpif(a);
-}
-
 // octahedral cell (0..kOctRes^2-1) of a unit vector
 __device__ inline int oct_cell(float x, float y, float z) {
     const float s = fabsf(x) + fabsf(y) + fabsf(z);
