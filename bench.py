@@ -193,12 +193,16 @@ def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
     return res
 
 
+UNEVEN_SURROGATE_STEPS = 5000
+
+
 def uneven_variant(lumiq):
     """The uneven multi-luminaire batch (16 trees of depth 6 to 10, SH degree
     3, float16, log-uniform ray counts): one persistent launch over all rays
     against one launch per luminaire; load balance = sum of the isolated
     launch times / the one launch's time."""
     import torch
+    import inputs
     from inputs import uneven
     t0 = time.perf_counter()
     trees = uneven.trees(progress=log)
@@ -224,6 +228,47 @@ def uneven_variant(lumiq):
         "ms_sum_isolated": sum(iso), "load_balance": sum(iso) / ms_one,
     }
     log(f"uneven batch: one launch {ms_one:.3f} ms, isolated sum {sum(iso):.3f} ms")
+
+    # per-luminaire surrogates (the training recipe of the single luminaire
+    # with fewer steps) on the luminaires with at least 2^20 rays, compared
+    # with the octree on the same rays
+    surr = []
+    for k, oc in enumerate(octs):
+        a, b = int(offs[k]), int(offs[k + 1])
+        if b - a < (1 << 20):
+            continue
+        to_, td_ = inputs.rays.room_to_proxy(8_000_000, 100 + k)
+        ho_, hd_ = inputs.rays.room_to_proxy(8_000_000, 200 + k)
+        to_, td_, ho_, hd_ = [torch.from_numpy(x).cuda() for x in (to_, td_, ho_, hd_)]
+        trgb, _ = oc.query(to_, td_)
+        hrgb, _ = oc.query(ho_, hd_)
+        sur = lumiq.Surrogate(seed=31 + k)
+        t0 = time.perf_counter()
+        sur.train(to_, td_, trgb, steps=UNEVEN_SURROGATE_STEPS, total_steps=UNEVEN_SURROGATE_STEPS,
+                  batch=65536, lr0=5e-3, lr1=5e-5)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        sur.build_trust(ho_, hd_, hrgb, max_rel_err=0.01)
+        del to_, td_, trgb, ho_, hd_, hrgb
+        ok, dk, nk = ot[a:b], dt[a:b], b - a
+        ref = torch.empty((nk, 3), device="cuda")
+        out = torch.empty((nk, 3), device="cuda")
+        used = torch.empty((nk,), dtype=torch.uint8, device="cuda")
+        ms_oct, _ = time_launches(lambda: oc.query(ok, dk, rgb=ref), 10, 2)
+
+        def hybrid():
+            lumiq.check(lumiq._mlp_lib().lq_mlp_infer(sur.handle, oc.handle, lumiq._ptr(ok), lumiq._ptr(dk), nk,
+                                                      lumiq._ptr(out), lumiq._ptr(used), lumiq._stream(None)))
+
+        ms_h, _ = time_launches(hybrid, 10, 2)
+        rel = float(torch.linalg.norm((out - ref).double()) / torch.linalg.norm(ref.double()))
+        surr.append({"tree": k, "depth": trees[k].depth, "rays": nk, "train_s": round(t_train, 2),
+                     "octree_ms": ms_oct, "hybrid_ms": ms_h, "speedup": ms_oct / ms_h,
+                     "rel_l2_vs_octree": rel, "fallback_fraction": float(used.float().mean())})
+        log(f"uneven batch: luminaire {k} surrogate {surr[-1]}")
+        sur.free()
+    res["surrogates"] = {"train_steps": UNEVEN_SURROGATE_STEPS, "train_pairs": 8_000_000,
+                         "heldout_pairs": 8_000_000, "per_luminaire": surr}
     for oc in octs:
         oc.free()
     return res
