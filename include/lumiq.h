@@ -72,7 +72,8 @@ typedef struct lq_mlp lq_mlp;         /* opaque, library-owned */
  *     Node 0 is the root cube [-1,1]^3; octant index = bx | by<<1 | bz<<2 where
  *     b_a is 1 for the upper half along axis a.  Data leaves sit at max_depth
  *     (cells of edge 2^(1-max_depth)); the table must be a tree (every node
- *     reached once, leaves only below nodes of depth max_depth-1).
+ *     reached once, leaves only below nodes of depth max_depth-1) of fewer
+ *     than 2^29 nodes.
  *   sigma[n_leaves], sh[n_leaves][3][(sh_degree+1)^2] float32: density and
  *     real SH coefficients (orthonormal basis without the Condon-Shortley
  *     phase, index k = l^2 + l + m) per colour channel; emission is

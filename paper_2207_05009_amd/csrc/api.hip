@@ -78,6 +78,8 @@ static lq_status validate_desc(const lq_octree_desc *d, std::vector<int32_t> *bf
     if (d->max_depth < 1 || d->max_depth > 10) return fail(LQ_ERR_FORMAT, "max_depth must be in [1, 10]");
     if (d->sh_degree < 0 || d->sh_degree > 4) return fail(LQ_ERR_FORMAT, "sh_degree must be in [0, 4]");
     if (d->n_nodes < 1) return fail(LQ_ERR_FORMAT, "n_nodes must be >= 1 (the root)");
+    // the kernels address child slots with 32-bit offsets (node * 8 + octant)
+    if (d->n_nodes >= (1 << 29)) return fail(LQ_ERR_UNSUPPORTED, "n_nodes must be below 2^29");
     if (d->n_leaves < 0) return fail(LQ_ERR_FORMAT, "n_leaves must be >= 0");
     if (!d->child) return fail(LQ_ERR_INVALID_ARG, "child table is NULL");
     if (d->n_leaves > 0 && (!d->sigma || !d->sh)) return fail(LQ_ERR_INVALID_ARG, "sigma/sh is NULL");

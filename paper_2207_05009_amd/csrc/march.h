@@ -493,7 +493,7 @@ struct Marcher {
             path[level * path_stride] = node;
             int sh = D - 1 - level;
             int oct = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
-            c = child[(size_t)node * 8 + oct];
+            c = child[(uint32_t)node * 8u + (uint32_t)oct];   // n_nodes < 2^29 (checked at load)
             ++level;
             if (c <= 0 || level >= D) break;
             node = c;
