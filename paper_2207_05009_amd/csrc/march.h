@@ -444,7 +444,17 @@ struct Marcher {
             } else if (ax == ev.ax) {
                 q[ax] = dx > 0.0f ? 0 : N - 1;
             } else {
-                q[ax] = locate(r, ax, 0, N, ev, h, N);
+                // the cell coordinate of the entry point, certified like the
+                // re-location in step(); else the exact search
+                const float pp = fmaf(ev.t, dx, ox);
+                const float half_n = 0.5f * (float)N;
+                const float g = (pp + 1.0f) * half_n;
+                const float eg = (fabsf(ev.t * dx) + fabsf(pp) + 1.0f) * (half_n * 0x1p-21f);
+                const float fl = floorf(g);
+                const float fr = g - fl;
+                const int k = (int)fl;
+                q[ax] = r.filter_ok && fr > eg && fr < 1.0f - eg && k >= 0 && k < N ? k
+                                                                                  : locate(r, ax, 0, N, ev, h, N);
             }
         }
 
