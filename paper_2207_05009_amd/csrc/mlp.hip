@@ -4,15 +4,18 @@
 // MFMA tile, activations in registers; see the comment above the kernel.
 //
 // Training step (one launch + one reduction launch):
-//   k_train_step: a workgroup of 4 waves stages the bfloat16 weight image in
-//   LDS and processes tiles of 64 samples.  Per tile, each wave takes 16
-//   samples through the sphere parameterisation, the Fourier features, the
-//   forward GEMMs (MFMA 16x16x16 bf16, weights as the A operand so that a
-//   layer's output blocks are the next layer's B operand), the loss of Eq. 8
-//   and the backward data GEMMs; activations and output gradients stay in
-//   LDS.  Then the 84 16x16 blocks of the weight gradients (K = the tile's
-//   samples) are split over the 4 waves and accumulate in registers across
-//   the workgroup's tiles.  Each workgroup writes one partial gradient row.
+//   k_train_step: a workgroup of 4 waves stages the bfloat16 weights in LDS in
+//   MFMA lane order (forward and transposed) and processes tiles of 64
+//   samples.  Per tile, each wave takes 16 samples through the sphere
+//   parameterisation and the Fourier features, then the forward GEMMs and the
+//   backward data GEMMs (MFMA 16x16x32 bf16, weights as the A operand, so one
+//   layer's output registers are the next layer's B operand), with the loss
+//   of Eq. 8 in between.  Features, activations and output gradients are also
+//   written to LDS, one row per feature, and after a barrier the 84 16x16
+//   blocks of the weight gradients (K = the tile's 64 samples) are split over
+//   the 4 waves and accumulate in registers across the workgroup's tiles;
+//   bias gradients are row sums.  Each workgroup writes one partial gradient
+//   row.
 //   k_reduce_adam: sums the rows in a fixed order (deterministic), applies
 //   Adam to the float32 master weights and refreshes the bfloat16 image.
 #include <math.h>
@@ -33,59 +36,33 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kTile = 64;                   // samples per tile (16 per wave)
-constexpr int kSF = kFeat + 4;              // padded LDS row strides (bf16 elements)
-constexpr int kSH = kHidden + 4;
-constexpr int kSD = kOutPad + 4;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// LDS image of the weights: layer l rows of padded stride
-constexpr int kLW1 = 0;
-constexpr int kLW2 = kLW1 + kHidden * kSF;
-constexpr int kLW3 = kLW2 + kHidden * kSH;
-constexpr int kLW4 = kLW3 + kHidden * kSH;
-constexpr int kLW5 = kLW4 + kHidden * kSH;
-constexpr int kLWEnd = kLW5 + kOutPad * kSH;    // bf16 elements
-
-// training-kernel LDS carve (bytes)
-constexpr int kOffW = 0;
-constexpr int kOffB = kOffW + kLWEnd * 2;
-constexpr int kOffF = kOffB + kBiasPad * 4;
-constexpr int kOffH = kOffF + kTile * kSF * 2;            // 4 x [64][kSH]
-constexpr int kOffDZ = kOffH + 4 * kTile * kSH * 2;       // 4 x [64][kSH]
-constexpr int kOffDY = kOffDZ + 4 * kTile * kSH * 2;      // [64][kSD]
-constexpr int kOffAct = kOffDY + kTile * kSD * 2;         // [64] float
-constexpr int kOffLoss = kOffAct + kTile * 4;             // [kWaves] float
-constexpr int kTrainLds = kOffLoss + kWaves * 4;
-
-
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ inline bf16x4 ld4(const uint16_t *p) { return *reinterpret_cast<const bf16x4 *>(p); }
-
-__device__ inline bf16x4 ld4_strided(const uint16_t *p, int stride) {
-    bf16x4 v;
-    v[0] = (short)p[0];
-    v[1] = (short)p[stride];
-    v[2] = (short)p[2 * stride];
-    v[3] = (short)p[3 * stride];
-    return v;
+__device__ inline bf16x8 load_bf8(const uint16_t *p0, const uint16_t *p1) {
+    // four consecutive elements from p0, four from p1
+    const u16x8 v = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3]};
+    return __builtin_bit_cast(bf16x8, v);
 }
 
-// stage the bfloat16 weight image and the biases in LDS
-__device__ void stage_weights(const uint16_t *wimg, const float *bias, uint16_t *sW, float *sB) {
-    for (int i = threadIdx.x; i < kImage; i += blockDim.x) {
-        int dst;
-        if (i < kI2) dst = kLW1 + (i / kFeat) * kSF + i % kFeat;
-        else if (i < kI3) dst = kLW2 + ((i - kI2) / kHidden) * kSH + (i - kI2) % kHidden;
-        else if (i < kI4) dst = kLW3 + ((i - kI3) / kHidden) * kSH + (i - kI3) % kHidden;
-        else if (i < kI5) dst = kLW4 + ((i - kI4) / kHidden) * kSH + (i - kI4) % kHidden;
-        else dst = kLW5 + ((i - kI5) / kHidden) * kSH + (i - kI5) % kHidden;
-        sW[dst] = wimg[i];
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// bfloat16 of relu(x) for eight values: round first, then clear the negative
+// ones as signed 16-bit integers (a bfloat16 with its sign bit set is negative
+// as an int16), which equals rounding relu(x) and takes one packed max per pair
+__device__ inline bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
+    bf16x8 h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = (__bf16)lo[i];
+        h[4 + i] = (__bf16)hi[i];
     }
-    for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
+    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(s16x8, h), zero));
 }
 
 // variable whose 10 frequencies lane group g evaluates, the variable of its
@@ -144,217 +121,295 @@ __device__ inline void sincos_run5(float x, float *f) {
     }
 }
 
-// features of the 16 samples of a wave: lane l does sample l % 16 and the
-// 32 feature slots of its lane group (slot_feature), written to their
-// columns of the sample's LDS row.  Returns whether the lane's sample is
-// active (its line meets the bounding sphere).
-__device__ bool wave_features(const float *o, const float *d, int64_t ray, bool valid, uint16_t *sF,
-                              int row) {
-    const int g = __lane_id() >> 4;
-    float x6[6] = {0, 0, 0, 0, 0, 0};
-    bool act = false;
-    if (valid) {
-        float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
-        float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
-        act = sphere_x6(oo, dd, x6);
-    }
-    const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
-    float f[32];
-    const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));
-    const float vb = pick6(e0, e1, e2, e3, e4, e5, run_b(g));
-    sincos_run5(va, f);
-    sincos_run5(va * 32.0f, f + 10);
-    sincos_run5(run_b0(g) ? vb * 32.0f : vb, f + 20);
-    f[30] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g) : 0.0f;
-    f[31] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g + 1) : 0.0f;
-    uint16_t *dst = sF + row * kSF;
-#pragma unroll
-    for (int j = 0; j < 32; ++j) dst[slot_feature(g, j)] = f2bf(act ? f[j] : 0.0f);
-    return act;
+// ------------------------------------------------------------ training
+// One workgroup of 4 waves processes tiles of 64 samples (16 per wave).
+// Phase A, per wave: features, the forward GEMMs and the backward data GEMMs
+// chained in registers exactly like inference (MFMA 16x16x32, weights -- and
+// for the backward, the transposed weights -- staged in LDS in lane order;
+// the ReLU masks come from the activations the lane still holds).  Every
+// GEMM input of the weight gradients (features, activations H_l, output
+// gradients dZ_l, dY) is also written to LDS feature-major, one row of 64
+// samples per feature.  Phase B, per workgroup: the weight gradients
+// dW_l = dZ_l H_{l-1}^T contract over the tile's 64 samples, so each MFMA
+// operand is 8 consecutive samples of one row (one ds_read_b128); their 84
+// 16x16 blocks are split over the 4 waves and accumulate in registers across
+// the workgroup's tiles; bias gradients are row sums.
+constexpr int kRS = 72;                              // LDS row stride (bf16): 64 samples + 8
+constexpr int kRowX = 0, kRowH = kRowX + kFeat;      // X: 128 rows, H1..H4: 64 rows each
+constexpr int kRowDZ = kRowH + 4 * kHidden;          // dZ1..dZ4: 64 rows each
+constexpr int kRowDY = kRowDZ + 4 * kHidden;         // dY: 4 rows (outputs 0..2, row 3 zero)
+constexpr int kRows = kRowDY + 4;
+constexpr int kTW1 = 0;                              // bf16x8 [4 fb][4 kb][64]
+constexpr int kTWh = kTW1 + 16 * 64 * 16;            // bf16x8 [3 l][4 fb][2 kb][64] + output [2 kb][64]
+constexpr int kTWt = kTWh + 26 * 64 * 16;            // bf16x8 [3 l][4 ib][2 kb][64]: transposed W2..W4
+constexpr int kTW5t = kTWt + 24 * 64 * 16;           // bf16x4 [4 ib][64]: transposed W5 (K = 16)
+constexpr int kTB = kTW5t + 4 * 64 * 8;              // float [kBiasPad]
+constexpr int kTAct = kTB + kBiasPad * 4;            // bf16 [kRows][kRS]
+constexpr int kTLoss = kTAct + kRows * kRS * 2;      // float [kWaves]
+constexpr int kTrainLds = kTLoss + kWaves * 4;
+static_assert(kTrainLds <= 160 * 1024, "training LDS carve exceeds the CU's LDS");
+
+typedef __bf16 bf16x4b __attribute__((ext_vector_type(4)));
+
+__device__ inline f32x4 mfma16b(bf16x4b a, bf16x4b b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a), __builtin_bit_cast(bf16x4, b), c,
+                                                     0, 0, 0);
 }
 
-// forward layer for the 16 samples whose rows start at s0:
-// Z[s][f] = sum_k X[s][k] W[f][k] + b[f]; H = relu(Z) in bfloat16
-template <int K, int OUTB>
-__device__ void fwd_layer(const uint16_t *X, int xs, const uint16_t *W, int ws, const float *b, uint16_t *H,
-                          int hs, int s0) {
-    const int lane = __lane_id();
-    const int r16 = lane & 15, q4 = lane >> 4;
-#pragma unroll
-    for (int fb = 0; fb < OUTB; ++fb) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int kb = 0; kb < K / 16; ++kb) {
-            const bf16x4 a = ld4(W + (fb * 16 + r16) * ws + kb * 16 + 4 * q4);
-            const bf16x4 x = ld4(X + (s0 + r16) * xs + kb * 16 + 4 * q4);
-            acc = mfma16(a, x, acc);
-        }
-        uint16_t *dst = H + (s0 + r16) * hs + fb * 16 + 4 * q4;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) dst[i] = f2bf(fmaxf(acc[i] + b[fb * 16 + 4 * q4 + i], 0.0f));
-    }
-}
-
-// last layer: returns y (lanes 0..15 hold outputs 0..3 of sample s0 + lane)
-__device__ f32x4 out_layer(const uint16_t *X, int xs, const uint16_t *W5, const float *b5, int s0) {
-    const int lane = __lane_id();
-    const int r16 = lane & 15, q4 = lane >> 4;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int kb = 0; kb < kHidden / 16; ++kb) {
-        const bf16x4 a = ld4(W5 + r16 * kSH + kb * 16 + 4 * q4);
-        const bf16x4 x = ld4(X + (s0 + r16) * xs + kb * 16 + 4 * q4);
-        acc = mfma16(a, x, acc);
-    }
+// bfloat16 of x where the activation h (bfloat16, h layout) is positive, else 0
+__device__ inline bf16x8 mask_pack(f32x4 lo, f32x4 hi, bf16x8 h) {
+    const s16x8 hs = __builtin_bit_cast(s16x8, h);
+    bf16x8 z;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int f = 4 * q4 + i;
-        acc[i] += f < kOut ? b5[f] : 0.0f;
+        z[i] = hs[i] > 0 ? (__bf16)lo[i] : (__bf16)0.0f;
+        z[4 + i] = hs[4 + i] > 0 ? (__bf16)hi[i] : (__bf16)0.0f;
     }
-    return acc;
+    return z;
 }
 
-// backward data: dX[s][in] = sum_out G[s][out] W[out][in], masked by H > 0
-template <int OUTK, int INB>
-__device__ void bwd_layer(const uint16_t *G, int gs, const uint16_t *W, int ws, const uint16_t *Hm, int hs,
-                          uint16_t *DX, int dxs, int s0) {
-    const int lane = __lane_id();
-    const int r16 = lane & 15, q4 = lane >> 4;
+// write the h-layout pair hv (features 16 (2 kb + e / 4) + 4 g + e % 4 of
+// sample col) feature-major into the rows starting at row0
+__device__ inline void store_rows(uint16_t *act, int row0, const bf16x8 (&hv)[2], int g, int col) {
 #pragma unroll
-    for (int ib = 0; ib < INB; ++ib) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kb = 0; kb < 2; ++kb) {
+        const s16x8 v = __builtin_bit_cast(s16x8, hv[kb]);
 #pragma unroll
-        for (int kb = 0; kb < OUTK / 16; ++kb) {
-            const bf16x4 a = ld4_strided(W + (kb * 16 + 4 * q4) * ws + ib * 16 + r16, ws);
-            const bf16x4 g = ld4(G + (s0 + r16) * gs + kb * 16 + 4 * q4);
-            acc = mfma16(a, g, acc);
-        }
-        const uint16_t *hm = Hm + (s0 + r16) * hs + ib * 16 + 4 * q4;
-        uint16_t *dst = DX + (s0 + r16) * dxs + ib * 16 + 4 * q4;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint16_t hb = hm[i];
-            const bool on = hb != 0 && !(hb & 0x8000u);
-            dst[i] = f2bf(on ? acc[i] : 0.0f);
-        }
+        for (int e = 0; e < 8; ++e)
+            act[(row0 + (2 * kb + (e >> 2)) * 16 + 4 * g + (e & 3)) * kRS + col] = (uint16_t)v[e];
     }
 }
 
-// ------------------------------------------------------------ training
 __global__ __launch_bounds__(256) void k_train_step(const float *o, const float *d, const float *tgt,
                                                     int64_t n_pairs, int64_t base, int64_t count,
                                                     int tiles, float inv_batch, const uint16_t *wimg,
                                                     const float *bias, float *part, float *loss_part) {
     extern __shared__ __align__(16) char smem[];
-    uint16_t *sW = reinterpret_cast<uint16_t *>(smem + kOffW);
-    float *sB = reinterpret_cast<float *>(smem + kOffB);
-    uint16_t *sF = reinterpret_cast<uint16_t *>(smem + kOffF);
-    uint16_t *sH = reinterpret_cast<uint16_t *>(smem + kOffH);
-    uint16_t *sDZ = reinterpret_cast<uint16_t *>(smem + kOffDZ);
-    uint16_t *sDY = reinterpret_cast<uint16_t *>(smem + kOffDY);
-    float *sAct = reinterpret_cast<float *>(smem + kOffAct);
-    float *sLoss = reinterpret_cast<float *>(smem + kOffLoss);
-    auto Hl = [&](int l) { return sH + (l - 1) * kTile * kSH; };    // H_1..H_4
-    auto DZl = [&](int l) { return sDZ + (l - 1) * kTile * kSH; };  // dZ_1..dZ_4
+    bf16x8 *sW1 = reinterpret_cast<bf16x8 *>(smem + kTW1);
+    bf16x8 *sWh = reinterpret_cast<bf16x8 *>(smem + kTWh);
+    bf16x8 *sWt = reinterpret_cast<bf16x8 *>(smem + kTWt);
+    bf16x4b *sW5t = reinterpret_cast<bf16x4b *>(smem + kTW5t);
+    float *sB = reinterpret_cast<float *>(smem + kTB);
+    uint16_t *act = reinterpret_cast<uint16_t *>(smem + kTAct);
+    float *sLoss = reinterpret_cast<float *>(smem + kTLoss);
 
-    stage_weights(wimg, bias, sW, sB);
+    // ---- stage the weights in lane order
+    for (int i = threadIdx.x; i < 16 * 64; i += blockDim.x) {           // W1 (K in feature-slot order)
+        const int ln = i & 63, blk = i >> 6, rr = ln & 15, gg = ln >> 4;
+        const int fb = blk / 4, kb = blk % 4;
+        const uint16_t *row = wimg + kI1 + (fb * 16 + rr) * kFeat;
+        u16x8 v;
+        for (int e = 0; e < 8; ++e) v[e] = row[slot_feature(gg, kb * 8 + e)];
+        sW1[i] = __builtin_bit_cast(bf16x8, v);
+    }
+    for (int i = threadIdx.x; i < 26 * 64; i += blockDim.x) {           // W2..W4, W5
+        const int ln = i & 63, blk = i >> 6, rr = ln & 15, gg = ln >> 4;
+        const uint16_t *row;
+        int kb;
+        if (blk < 24) {
+            const int l = blk / 8, fb = (blk / 2) % 4;
+            kb = blk % 2;
+            row = wimg + kI2 + l * kHidden * kHidden + (fb * 16 + rr) * kHidden + 4 * gg;
+        } else {
+            kb = blk - 24;
+            row = wimg + kI5 + rr * kHidden + 4 * gg;
+        }
+        sWh[i] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
+    }
+    for (int i = threadIdx.x; i < 24 * 64; i += blockDim.x) {           // W2..W4 transposed
+        const int ln = i & 63, blk = i >> 6, rr = ln & 15, gg = ln >> 4;
+        const int l = blk / 8, ib = (blk / 2) % 4, kb = blk % 2;
+        const uint16_t *w = wimg + kI2 + l * kHidden * kHidden;
+        u16x8 v;
+        for (int e = 0; e < 8; ++e) {
+            const int out = (2 * kb + (e >> 2)) * 16 + 4 * gg + (e & 3);
+            v[e] = w[out * kHidden + ib * 16 + rr];
+        }
+        sWt[i] = __builtin_bit_cast(bf16x8, v);
+    }
+    for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {            // W5 transposed (16 padded rows)
+        const int ln = i & 63, ib = i >> 6, rr = ln & 15, gg = ln >> 4;
+        u16x8 v8;
+        for (int e = 0; e < 4; ++e) v8[e] = wimg[kI5 + (4 * gg + e) * kHidden + ib * 16 + rr];
+        for (int e = 4; e < 8; ++e) v8[e] = 0;
+        const bf16x8 t8 = __builtin_bit_cast(bf16x8, v8);
+        sW5t[i] = bf16x4b{t8[0], t8[1], t8[2], t8[3]};
+    }
+    for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
     __syncthreads();
 
     const int wave = threadIdx.x >> 6;
     const int lane = __lane_id();
-    const int r16 = lane & 15, q4 = lane >> 4;
-    const int s0 = wave * 16;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int col = wave * 16 + r16;     // this lane's sample column in the tile
 
     f32x4 gacc[21];
 #pragma unroll
     for (int j = 0; j < 21; ++j) gacc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float gbias = 0.0f, gb5 = 0.0f, lsum = 0.0f;
+    const bf16x8 zero8 = {};
 
     for (int tile = 0; tile < tiles; ++tile) {
-        const int64_t local0 = ((int64_t)blockIdx.x * tiles + tile) * kTile;
         // ---- phase A: this wave's 16 samples
-        const int64_t local = local0 + s0 + r16;
+        const int64_t local = ((int64_t)blockIdx.x * tiles + tile) * kTile + col;
         const bool valid = local < count;
-        const int64_t ray = (base + local) % n_pairs;
-        const bool act = wave_features(o, d, ray, valid, sF, s0 + r16);
-        if (q4 == 0) sAct[s0 + r16] = act ? 1.0f : 0.0f;
-        wave_sync();
-        fwd_layer<kFeat, 4>(sF, kSF, sW + kLW1, kSF, sB, Hl(1), kSH, s0);
-        wave_sync();
-        fwd_layer<kHidden, 4>(Hl(1), kSH, sW + kLW2, kSH, sB + 64, Hl(2), kSH, s0);
-        wave_sync();
-        fwd_layer<kHidden, 4>(Hl(2), kSH, sW + kLW3, kSH, sB + 128, Hl(3), kSH, s0);
-        wave_sync();
-        fwd_layer<kHidden, 4>(Hl(3), kSH, sW + kLW4, kSH, sB + 192, Hl(4), kSH, s0);
-        wave_sync();
-        const f32x4 y = out_layer(Hl(4), kSH, sW + kLW5, sB + 256, s0);
-        // loss (Eq. 8, channel-mean luminance held constant) and dL/dy
-        if (q4 == 0) {
-            float g[kOutPad];
-#pragma unroll
-            for (int c = 0; c < kOutPad; ++c) g[c] = 0.0f;
-            if (act) {
-                float e[3], lh[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    e[c] = expf(y[c]);
-                    lh[c] = e[c] - kEpsOut;
-                }
-                const float den = (lh[0] + lh[1] + lh[2]) * (1.0f / 3.0f) + kLossEps;
-                const float id2 = 1.0f / (den * den);
-                float l = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float diff = lh[c] - tgt[3 * ray + c];
-                    l += diff * diff * id2;
-                    g[c] = 2.0f * diff * e[c] * id2 * inv_batch;
-                }
-                lsum += l;
-            }
-            uint16_t *dst = sDY + (s0 + r16) * kSD;
-#pragma unroll
-            for (int c = 0; c < kOutPad; ++c) dst[c] = f2bf(g[c]);
+        const int64_t ray = valid ? (base + local) % n_pairs : 0;
+        float x6[6] = {0, 0, 0, 0, 0, 0};
+        bool actv = false;
+        if (valid) {
+            float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
+            float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
+            actv = sphere_x6(oo, dd, x6);
         }
-        wave_sync();
-        bwd_layer<kOutPad, 4>(sDY, kSD, sW + kLW5, kSH, Hl(4), kSH, DZl(4), kSH, s0);
-        wave_sync();
-        bwd_layer<kHidden, 4>(DZl(4), kSH, sW + kLW4, kSH, Hl(3), kSH, DZl(3), kSH, s0);
-        wave_sync();
-        bwd_layer<kHidden, 4>(DZl(3), kSH, sW + kLW3, kSH, Hl(2), kSH, DZl(2), kSH, s0);
-        wave_sync();
-        bwd_layer<kHidden, 4>(DZl(2), kSH, sW + kLW2, kSH, Hl(1), kSH, DZl(1), kSH, s0);
+        const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
+        float f[32];
+        const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));
+        const float vb = pick6(e0, e1, e2, e3, e4, e5, run_b(g));
+        sincos_run5(va, f);
+        sincos_run5(va * 32.0f, f + 10);
+        sincos_run5(run_b0(g) ? vb * 32.0f : vb, f + 20);
+        f[30] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g) : 0.0f;
+        f[31] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g + 1) : 0.0f;
+        bf16x8 x[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[kb][e] = (__bf16)f[kb * 8 + e];
+            x[kb] = actv ? x[kb] : zero8;
+            const s16x8 v = __builtin_bit_cast(s16x8, x[kb]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) act[(kRowX + slot_feature(g, kb * 8 + e)) * kRS + col] = (uint16_t)v[e];
+        }
+
+        // forward
+        f32x4 acc[4];
+        bf16x8 h[4][2];
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) acc[fb] = *reinterpret_cast<const f32x4 *>(sB + fb * 16 + 4 * g);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) acc[fb] = mfma32(sW1[(fb * 4 + kb) * 64 + lane], x[kb], acc[fb]);
+        h[0][0] = relu_pack(acc[0], acc[1]);
+        h[0][1] = relu_pack(acc[2], acc[3]);
+        store_rows(act, kRowH, h[0], g, col);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+                acc[fb] = *reinterpret_cast<const f32x4 *>(sB + (l + 1) * kHidden + fb * 16 + 4 * g);
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb)
+                    acc[fb] = mfma32(sWh[((l * 4 + fb) * 2 + kb) * 64 + lane], h[l][kb], acc[fb]);
+            h[l + 1][0] = relu_pack(acc[0], acc[1]);
+            h[l + 1][1] = relu_pack(acc[2], acc[3]);
+            store_rows(act, kRowH + (l + 1) * kHidden, h[l + 1], g, col);
+        }
+        f32x4 y = *reinterpret_cast<const f32x4 *>(sB + 4 * kHidden + 4 * g);
+        y = mfma32(sWh[24 * 64 + lane], h[3][0], y);
+        y = mfma32(sWh[25 * 64 + lane], h[3][1], y);
+
+        // loss (Eq. 8, channel-mean luminance held constant) and dL/dy:
+        // lanes of group 0 hold outputs 0..3 of their sample
+        float gy[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (g == 0 && actv) {
+            float ey[3], lh[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ey[c] = expf(y[c]);
+                lh[c] = ey[c] - kEpsOut;
+            }
+            const float den = (lh[0] + lh[1] + lh[2]) * (1.0f / 3.0f) + kLossEps;
+            const float id2 = 1.0f / (den * den);
+            float lsmp = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float diff = lh[c] - tgt[3 * ray + c];
+                lsmp += diff * diff * id2;
+                gy[c] = 2.0f * diff * ey[c] * id2 * inv_batch;
+            }
+            lsum += lsmp;
+        }
+        const bf16x4b dyb = {(__bf16)gy[0], (__bf16)gy[1], (__bf16)gy[2], (__bf16)gy[3]};
+        if (g == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) act[(kRowDY + c) * kRS + col] = __builtin_bit_cast(uint16_t, dyb[c]);
+        }
+
+        // backward data: dZ4 = (W5^T dY) masked by H4 > 0, then down to dZ1
+        bf16x8 z[2];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) acc[ib] = mfma16b(sW5t[ib * 64 + lane], dyb, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+        z[0] = mask_pack(acc[0], acc[1], h[3][0]);
+        z[1] = mask_pack(acc[2], acc[3], h[3][1]);
+        store_rows(act, kRowDZ + 3 * kHidden, z, g, col);
+#pragma unroll
+        for (int l = 2; l >= 0; --l) {    // dZ_{l+1} from dZ_{l+2} through W_{l+2}
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) acc[ib] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib)
+                    acc[ib] = mfma32(sWt[((l * 4 + ib) * 2 + kb) * 64 + lane], z[kb], acc[ib]);
+            z[0] = mask_pack(acc[0], acc[1], h[l][0]);
+            z[1] = mask_pack(acc[2], acc[3], h[l][1]);
+            store_rows(act, kRowDZ + l * kHidden, z, g, col);
+        }
         __syncthreads();
 
         // ---- phase B: weight-gradient blocks over the tile's 64 samples
 #pragma unroll
         for (int slot = 0; slot < 21; ++slot) {
             const int j = slot * kWaves + wave;   // block 0..83
-            const uint16_t *G, *X;
-            int gs, xs, ob, ib;
-            if (j < 32) { G = DZl(1); gs = kSH; X = sF; xs = kSF; ob = j >> 3; ib = j & 7; }
-            else if (j < 80) {
+            int arow, brow;
+            bool arow_ok = true;
+            if (j < 32) {
+                arow = kRowDZ + (j >> 3) * 16;
+                brow = kRowX + (j & 7) * 16;
+            } else if (j < 80) {
                 const int l = 2 + (j - 32) / 16, jj = (j - 32) % 16;
-                G = DZl(l); gs = kSH; X = Hl(l - 1); xs = kSH; ob = jj >> 2; ib = jj & 3;
-            } else { G = sDY; gs = kSD; X = Hl(4); xs = kSH; ob = 0; ib = j - 80; }
-            f32x4 acc = gacc[slot];
-#pragma unroll
-            for (int kb = 0; kb < kTile / 16; ++kb) {
-                const bf16x4 a = ld4_strided(G + (kb * 16 + 4 * q4) * gs + ob * 16 + r16, gs);
-                const bf16x4 b = ld4_strided(X + (kb * 16 + 4 * q4) * xs + ib * 16 + r16, xs);
-                acc = mfma16(a, b, acc);
+                arow = kRowDZ + (l - 1) * kHidden + (jj >> 2) * 16;
+                brow = kRowH + (l - 2) * kHidden + (jj & 3) * 16;
+            } else {
+                arow = kRowDY;
+                arow_ok = r16 < 4;                 // output rows 4..15 are padding
+                brow = kRowH + 3 * kHidden + (j - 80) * 16;
             }
-            gacc[slot] = acc;
+            f32x4 a_acc = gacc[slot];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const int c0 = kb * 32 + 8 * g;
+                const bf16x8 ar = *reinterpret_cast<const bf16x8 *>(act + (arow + (arow_ok ? r16 : 0)) * kRS + c0);
+                const bf16x8 av = arow_ok ? ar : zero8;
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(act + (brow + r16) * kRS + c0);
+                a_acc = mfma32(av, bv, a_acc);
+            }
+            gacc[slot] = a_acc;
         }
         // bias gradients: thread t owns b_{t/64 + 1}[t % 64]; threads 0..2 b_5
         {
             const int t = threadIdx.x;
-            const uint16_t *G = DZl(t / 64 + 1);
-            float s = 0.0f;
-            for (int smp = 0; smp < kTile; ++smp) s += bf2f(G[smp * kSH + (t & 63)]);
-            gbias += s;
+            const uint16_t *rowp = act + (kRowDZ + t) * kRS;     // dZ rows of the four hidden layers
+            float sacc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kTile; c += 8) {
+                const s16x8 v = *reinterpret_cast<const s16x8 *>(rowp + c);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sacc += bf2f((uint16_t)v[e]);
+            }
+            gbias += sacc;
             if (t < kOut) {
+                const uint16_t *r5 = act + (kRowDY + t) * kRS;
                 float s5 = 0.0f;
-                for (int smp = 0; smp < kTile; ++smp) s5 += bf2f(sDY[smp * kSD + t]);
+#pragma unroll
+                for (int c = 0; c < kTile; c += 8) {
+                    const s16x8 v = *reinterpret_cast<const s16x8 *>(r5 + c);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) s5 += bf2f((uint16_t)v[e]);
+                }
                 gb5 += s5;
             }
         }
@@ -375,7 +430,7 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
         } else { woff = kW5; in_dim = kHidden; out_dim = kOut; ob = 0; ib = j - 80; }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int out = ob * 16 + 4 * q4 + i;
+            const int out = ob * 16 + 4 * g + i;
             const int in = ib * 16 + r16;
             if (out < out_dim) P[woff + out * in_dim + in] = gacc[slot][i];
         }
@@ -393,9 +448,9 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
     if (lane == 0) sLoss[wave] = l;
     __syncthreads();
     if (threadIdx.x == 0) {
-        float s = 0.0f;
-        for (int w = 0; w < kWaves; ++w) s += sLoss[w];
-        loss_part[blockIdx.x] = s * inv_batch;
+        float sl = 0.0f;
+        for (int w = 0; w < kWaves; ++w) sl += sLoss[w];
+        loss_part[blockIdx.x] = sl * inv_batch;
     }
 }
 
@@ -519,35 +574,6 @@ __global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
 // (slot_feature below): lane group g evaluates 10 + 5 consecutive
 // frequencies of two input variables: the hardware sine and cosine at the
 // first frequency of each run of five, then angle doubling.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-
-__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ inline bf16x8 load_bf8(const uint16_t *p0, const uint16_t *p1) {
-    // four consecutive elements from p0, four from p1
-    const u16x8 v = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3]};
-    return __builtin_bit_cast(bf16x8, v);
-}
-
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-
-// bfloat16 of relu(x) for eight values: round first, then clear the negative
-// ones as signed 16-bit integers (a bfloat16 with its sign bit set is negative
-// as an int16), which equals rounding relu(x) and takes one packed max per pair
-__device__ inline bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
-    bf16x8 h;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        h[i] = (__bf16)lo[i];
-        h[4 + i] = (__bf16)hi[i];
-    }
-    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(s16x8, h), zero));
-}
-
 __device__ inline void load_ray(const float *o, const float *d, int64_t ray, bool valid, float *oo, float *dd) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
