@@ -149,6 +149,115 @@ constexpr int kTLoss = kTAct + kRows * kRS * 2;      // float [kWaves]
 constexpr int kTrainLds = kTLoss + kWaves * 4;
 static_assert(kTrainLds <= 160 * 1024, "training LDS carve exceeds the CU's LDS");
 
+// The bfloat16 weights are kept on the device in the byte order the kernels
+// stage into LDS (the first kTB bytes of the training carve: W1, W2..W5 as
+// the forward A operands, W2..W4 and W5 transposed as the backward ones), so
+// a workgroup stages them with contiguous 16-byte copies.  Positions are in
+// bfloat16 elements.
+constexpr int kLaneElems = kTB / 2;
+
+// slot (32 g + j) of feature f: the inverse of slot_feature
+__host__ __device__ constexpr int slot_of_feature(int f) {
+    if (f >= kFeatUsed) return 3 * 32 + 30 + (f - kFeatUsed);
+    const int v = f / (1 + 2 * kFreq), r = f % (1 + 2 * kFreq);
+    if (r == 0) return (v >> 1) * 32 + 30 + (v & 1);
+    const int k = r - 1;
+    if (v == 0 || v == 2 || v == 3 || v == 5) return (v == 0 ? 0 : v == 2 ? 1 : v == 3 ? 2 : 3) * 32 + k;
+    return ((v == 1 ? 0 : 2) + (k >= kFreq)) * 32 + 20 + (k >= kFreq ? k - kFreq : k);
+}
+constexpr bool slot_inverse_holds() {
+    for (int g = 0; g < 4; ++g)
+        for (int j = 0; j < 32; ++j)
+            if (slot_of_feature(slot_feature(g, j)) != 32 * g + j) return false;
+    return true;
+}
+static_assert(slot_inverse_holds(), "slot_of_feature must invert slot_feature");
+
+// parameter held at lane-image position u (-1: padding, kept zero)
+__host__ __device__ constexpr int lane_param(int u) {
+    if (u < kTWh / 2) {                                   // W1: [fb][kb][lane] x 8
+        const int e = u & 7, ln = (u >> 3) & 63, blk = u >> 9;
+        return kW1 + ((blk >> 2) * 16 + (ln & 15)) * kFeat + slot_feature(ln >> 4, (blk & 3) * 8 + e);
+    }
+    if (u < kTWt / 2) {                                   // W2..W4, W5: [blk][lane] x 8
+        const int v = u - kTWh / 2, e = v & 7, ln = (v >> 3) & 63, blk = v >> 9;
+        const int r = ln & 15, kb = blk < 24 ? (blk & 1) : blk - 24;
+        const int in = 32 * kb + 16 * (e >> 2) + 4 * (ln >> 4) + (e & 3);
+        if (blk < 24) return kW2 + (blk >> 3) * (kW3 - kW2) + (((blk >> 1) & 3) * 16 + r) * kHidden + in;
+        return r < kOut ? kW5 + r * kHidden + in : -1;
+    }
+    if (u < kTW5t / 2) {                                  // W2..W4 transposed: [l][ib][kb][lane] x 8
+        const int v = u - kTWt / 2, e = v & 7, ln = (v >> 3) & 63, blk = v >> 9;
+        const int out = (2 * (blk & 1) + (e >> 2)) * 16 + 4 * (ln >> 4) + (e & 3);
+        return kW2 + (blk >> 3) * (kW3 - kW2) + out * kHidden + ((blk >> 1) & 3) * 16 + (ln & 15);
+    }
+    const int v = u - kTW5t / 2, e = v & 3, ln = (v >> 2) & 63, ib = v >> 8;   // W5 transposed, x 4
+    const int o = 4 * (ln >> 4) + e;
+    return o < kOut ? kW5 + o * kHidden + ib * 16 + (ln & 15) : -1;
+}
+
+// lane-image positions of parameter p (W2..W5 appear twice, W1 once, biases
+// not at all; -1 where there is none)
+__host__ __device__ constexpr void lane_positions(int p, int &u0, int &u1) {
+    u0 = u1 = -1;
+    if (p < kB1) {
+        const int out = p / kFeat, sl = slot_of_feature(p % kFeat), j = sl & 31;
+        u0 = kTW1 / 2 + (((out >> 4) * 4 + (j >> 3)) * 64 + (sl >> 5) * 16 + (out & 15)) * 8 + (j & 7);
+        return;
+    }
+    int l = -1, q = 0;
+    if (p >= kW2 && p < kB2) { l = 0; q = p - kW2; }
+    else if (p >= kW3 && p < kB3) { l = 1; q = p - kW3; }
+    else if (p >= kW4 && p < kB4) { l = 2; q = p - kW4; }
+    if (l >= 0) {
+        const int out = q / kHidden, in = q % kHidden;
+        u0 = kTWh / 2 + (((l * 4 + (out >> 4)) * 2 + (in >> 5)) * 64 + ((in & 15) >> 2) * 16 + (out & 15)) * 8 +
+             4 * ((in >> 4) & 1) + (in & 3);
+        u1 = kTWt / 2 + (((l * 4 + (in >> 4)) * 2 + (out >> 5)) * 64 + ((out & 15) >> 2) * 16 + (in & 15)) * 8 +
+             4 * ((out >> 4) & 1) + (out & 3);
+        return;
+    }
+    if (p >= kW5 && p < kB5) {
+        const int o = (p - kW5) / kHidden, in = (p - kW5) % kHidden;
+        u0 = kTWh / 2 + ((24 + (in >> 5)) * 64 + ((in & 15) >> 2) * 16 + o) * 8 + 4 * ((in >> 4) & 1) + (in & 3);
+        u1 = kTW5t / 2 + ((in >> 4) * 64 + (in & 15)) * 4 + o;
+    }
+}
+
+// every position's parameter lists that position, every weight's positions
+// hold that weight (checked in ranges to stay within the constexpr step limit)
+constexpr bool lane_forward_agrees(int u_begin, int u_end) {
+    for (int u = u_begin; u < u_end; ++u) {
+        const int p = lane_param(u);
+        if (p < 0) continue;
+        int u0 = 0, u1 = 0;
+        lane_positions(p, u0, u1);
+        if (u != u0 && u != u1) return false;
+    }
+    return true;
+}
+constexpr bool lane_inverse_agrees(int p_begin, int p_end) {
+    for (int p = p_begin; p < p_end; ++p) {
+        int u0 = 0, u1 = 0;
+        lane_positions(p, u0, u1);
+        const bool weight = p < kB1 || (p >= kW2 && p < kB2) || (p >= kW3 && p < kB3) || (p >= kW4 && p < kB4) ||
+                            (p >= kW5 && p < kB5);
+        if (weight != (u0 >= 0)) return false;
+        if (u0 >= 0 && (u0 >= kLaneElems || lane_param(u0) != p)) return false;
+        if (u1 >= 0 && (u1 >= kLaneElems || lane_param(u1) != p)) return false;
+        if ((u1 >= 0) != (weight && p >= kW2)) return false;
+    }
+    return true;
+}
+static_assert(lane_forward_agrees(0, 4096) && lane_forward_agrees(4096, 8192), "lane image map, W1");
+static_assert(lane_forward_agrees(8192, 12288) && lane_forward_agrees(12288, 16384), "lane image map, W2..W5");
+static_assert(lane_forward_agrees(16384, 20480) && lane_forward_agrees(20480, 24576), "lane image map, W2..W5");
+static_assert(lane_forward_agrees(24576, 28672) && lane_forward_agrees(28672, 32768), "lane image map, transposed");
+static_assert(lane_forward_agrees(32768, kLaneElems), "lane image map, W5 transposed");
+static_assert(lane_inverse_agrees(0, 4096) && lane_inverse_agrees(4096, 8192), "lane image inverse, W1");
+static_assert(lane_inverse_agrees(8192, 12288) && lane_inverse_agrees(12288, 16384), "lane image inverse");
+static_assert(lane_inverse_agrees(16384, kParams), "lane image inverse");
+
 typedef __bf16 bf16x4b __attribute__((ext_vector_type(4)));
 
 __device__ inline f32x4 mfma16b(bf16x4b a, bf16x4b b, f32x4 c) {
@@ -182,7 +291,7 @@ __device__ inline void store_rows(uint16_t *act, int row0, const bf16x8 (&hv)[2]
 
 __global__ __launch_bounds__(256) void k_train_step(const float *o, const float *d, const float *tgt,
                                                     int64_t n_pairs, int64_t base, int64_t count,
-                                                    int tiles, float inv_batch, const uint16_t *wimg,
+                                                    int tiles, float inv_batch, const uint16_t *wlane,
                                                     const float *bias, float *part, float *loss_part) {
     extern __shared__ __align__(16) char smem[];
     bf16x8 *sW1 = reinterpret_cast<bf16x8 *>(smem + kTW1);
@@ -193,47 +302,13 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
     uint16_t *act = reinterpret_cast<uint16_t *>(smem + kTAct);
     float *sLoss = reinterpret_cast<float *>(smem + kTLoss);
 
-    // ---- stage the weights in lane order
-    for (int i = threadIdx.x; i < 16 * 64; i += blockDim.x) {           // W1 (K in feature-slot order)
-        const int ln = i & 63, blk = i >> 6, rr = ln & 15, gg = ln >> 4;
-        const int fb = blk / 4, kb = blk % 4;
-        const uint16_t *row = wimg + kI1 + (fb * 16 + rr) * kFeat;
-        u16x8 v;
-        for (int e = 0; e < 8; ++e) v[e] = row[slot_feature(gg, kb * 8 + e)];
-        sW1[i] = __builtin_bit_cast(bf16x8, v);
-    }
-    for (int i = threadIdx.x; i < 26 * 64; i += blockDim.x) {           // W2..W4, W5
-        const int ln = i & 63, blk = i >> 6, rr = ln & 15, gg = ln >> 4;
-        const uint16_t *row;
-        int kb;
-        if (blk < 24) {
-            const int l = blk / 8, fb = (blk / 2) % 4;
-            kb = blk % 2;
-            row = wimg + kI2 + l * kHidden * kHidden + (fb * 16 + rr) * kHidden + 4 * gg;
-        } else {
-            kb = blk - 24;
-            row = wimg + kI5 + rr * kHidden + 4 * gg;
-        }
-        sWh[i] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
-    }
-    for (int i = threadIdx.x; i < 24 * 64; i += blockDim.x) {           // W2..W4 transposed
-        const int ln = i & 63, blk = i >> 6, rr = ln & 15, gg = ln >> 4;
-        const int l = blk / 8, ib = (blk / 2) % 4, kb = blk % 2;
-        const uint16_t *w = wimg + kI2 + l * kHidden * kHidden;
-        u16x8 v;
-        for (int e = 0; e < 8; ++e) {
-            const int out = (2 * kb + (e >> 2)) * 16 + 4 * gg + (e & 3);
-            v[e] = w[out * kHidden + ib * 16 + rr];
-        }
-        sWt[i] = __builtin_bit_cast(bf16x8, v);
-    }
-    for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {            // W5 transposed (16 padded rows)
-        const int ln = i & 63, ib = i >> 6, rr = ln & 15, gg = ln >> 4;
-        u16x8 v8;
-        for (int e = 0; e < 4; ++e) v8[e] = wimg[kI5 + (4 * gg + e) * kHidden + ib * 16 + rr];
-        for (int e = 4; e < 8; ++e) v8[e] = 0;
-        const bf16x8 t8 = __builtin_bit_cast(bf16x8, v8);
-        sW5t[i] = bf16x4b{t8[0], t8[1], t8[2], t8[3]};
+    // ---- stage the lane-ordered weights: contiguous 16-byte copies
+    static_assert(kTB % (16 * 256) == 0, "the lane image is copied in whole rounds of the block");
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(wlane);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem);
+#pragma unroll
+        for (int k = 0; k < kTB / (16 * 256); ++k) dst[k * 256 + threadIdx.x] = src[k * 256 + threadIdx.x];
     }
     for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
     __syncthreads();
@@ -454,14 +529,6 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
     }
 }
 
-__device__ inline int image_index(int p) {
-    if (p < kB1) return kI1 + p;
-    if (p >= kW2 && p < kB2) return kI2 + (p - kW2);
-    if (p >= kW3 && p < kB3) return kI3 + (p - kW3);
-    if (p >= kW4 && p < kB4) return kI4 + (p - kW4);
-    if (p >= kW5 && p < kB5) return kI5 + (p - kW5);
-    return -1;
-}
 __device__ inline int bias_index(int p) {
     if (p >= kB1 && p < kW2) return p - kB1;
     if (p >= kB2 && p < kW3) return 64 + p - kB2;
@@ -481,7 +548,7 @@ __device__ inline int bias_index(int p) {
 constexpr int kRedParams = 64;
 
 __global__ __launch_bounds__(256) void k_reduce_adam(const float *part, int rows, float *theta, float *m, float *v,
-                                                     uint16_t *wimg, float *bias, const float *loss_part,
+                                                     uint16_t *wlane, float *bias, const float *loss_part,
                                                      float *loss_out, float *grad_out, int update, float lr,
                                                      float b1, float b2, float eps, float c1, float c2) {
     __shared__ float s_part[4][kRedParams];
@@ -524,20 +591,16 @@ __global__ __launch_bounds__(256) void k_reduce_adam(const float *part, int rows
     v[p] = vv;
     const float th = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
     theta[p] = th;
-    const int ii = image_index(p);
-    if (ii >= 0) wimg[ii] = f2bf(th);
+    int u0 = -1, u1 = -1;
+    lane_positions(p, u0, u1);
+    const uint16_t hb = f2bf(th);
+    if (u0 >= 0) wlane[u0] = hb;
+    if (u1 >= 0) wlane[u1] = hb;
     const int bi = bias_index(p);
     if (bi >= 0) bias[bi] = th;
 }
 
-// parameter that an image / bias slot holds (-1: padding, stays zero)
-__device__ inline int param_of_image(int i) {
-    if (i < kI2) return kW1 + i;
-    if (i < kI3) return kW2 + (i - kI2);
-    if (i < kI4) return kW3 + (i - kI3);
-    if (i < kI5) return kW4 + (i - kI4);
-    return i - kI5 < kOut * kHidden ? kW5 + (i - kI5) : -1;
-}
+// parameter that a bias slot holds (-1: padding, stays zero)
 __device__ inline int param_of_bias(int i) {
     if (i < 64) return kB1 + i;
     if (i < 128) return kB2 + i - 64;
@@ -546,11 +609,11 @@ __device__ inline int param_of_bias(int i) {
     return i - 256 < kOut ? kB5 + i - 256 : -1;
 }
 
-__global__ void k_pack(const float *theta, uint16_t *wimg, float *bias) {
+__global__ void k_pack(const float *theta, uint16_t *wlane, float *bias) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < kImage) {
-        const int p = param_of_image(i);
-        wimg[i] = p >= 0 ? f2bf(theta[p]) : (uint16_t)0;
+    if (i < kLaneElems) {
+        const int p = lane_param(i);
+        wlane[i] = p >= 0 ? f2bf(theta[p]) : (uint16_t)0;
     }
     if (i < kBiasPad) {
         const int p = param_of_bias(i);
@@ -592,7 +655,7 @@ constexpr int kInfWaves = kInfBlock / 64;
 
 __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_infer(
     const float *o, const float *d, int64_t n, const int64_t *index, const unsigned long long *n_dev,
-    const uint16_t *wimg, const float *bias, int mode, float *rgb, const float *ref, double *terr,
+    const uint16_t *wlane, const float *bias, int mode, float *rgb, const float *ref, double *terr,
     double *tref, unsigned *tcnt) {
     __shared__ __align__(16) float sB[kBiasPad];
     for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
@@ -601,34 +664,17 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
     const int lane = __lane_id();
     const int r16 = lane & 15, g = lane >> 4;
 
-    // hidden and output layers: lane-ordered bf16x8 operands in LDS,
-    // [l][fb][kb][lane] (l = 3: the output layer, fb = 0 only)
-    __shared__ __align__(16) bf16x8 sWh[(3 * 4 * 2 + 2) * 64];
-    for (int i = threadIdx.x; i < (3 * 4 * 2 + 2) * 64; i += blockDim.x) {
-        const int ln = i & 63, blk = i >> 6;
-        const int rr = ln & 15, gg = ln >> 4;
-        const uint16_t *row;
-        int kb;
-        if (blk < 24) {
-            const int l = blk / 8, fb = (blk / 2) % 4;
-            kb = blk % 2;
-            row = wimg + kI2 + l * kHidden * kHidden + (fb * 16 + rr) * kHidden + 4 * gg;
-        } else {
-            kb = blk - 24;
-            row = wimg + kI5 + rr * kHidden + 4 * gg;
-        }
-        sWh[i] = load_bf8(row + 32 * kb, row + 32 * kb + 16);
-    }
-    // first layer: [fb][kb][lane], K in the feature-slot order
-    __shared__ __align__(16) bf16x8 sW1[4 * 4 * 64];
-    for (int i = threadIdx.x; i < 4 * 4 * 64; i += blockDim.x) {
-        const int ln = i & 63, blk = i >> 6;
-        const int rr = ln & 15, gg = ln >> 4;
-        const int fb = blk / 4, kb = blk % 4;
-        const uint16_t *row = wimg + kI1 + (fb * 16 + rr) * kFeat;
-        u16x8 v;
-        for (int e = 0; e < 8; ++e) v[e] = row[slot_feature(gg, kb * 8 + e)];
-        sW1[i] = __builtin_bit_cast(bf16x8, v);
+    // first layer [fb][kb][lane] (K in the feature-slot order), then the
+    // hidden and output layers [l][fb][kb][lane] (l = 3: the output layer,
+    // fb = 0 only): the leading part of the lane-ordered weight image
+    __shared__ __align__(16) bf16x8 sW[(16 + 26) * 64];
+    const bf16x8 *sW1 = sW;
+    const bf16x8 *sWh = sW + 16 * 64;
+    static_assert(kTWh == 16 * 64 * 16 && kTWt == (16 + 26) * 64 * 16, "inference stages W1 and W2..W5");
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(wlane);
+        uint4 *dst = reinterpret_cast<uint4 *>(sW);
+        for (int i = threadIdx.x; i < kTWt / 16; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
 
@@ -809,7 +855,7 @@ __global__ void k_zero_bytes(unsigned char *p, size_t n) {
 struct lq_mlp {
     int device;
     float *theta, *m, *v;
-    uint16_t *wimg;
+    uint16_t *wlane;   // bfloat16 weights in LDS staging order
     float *bias;
     float *part;
     int part_rows;
@@ -861,7 +907,7 @@ static void free_mlp(lq_mlp *p) {
     (void)hipFree(p->theta);
     (void)hipFree(p->m);
     (void)hipFree(p->v);
-    (void)hipFree(p->wimg);
+    (void)hipFree(p->wlane);
     (void)hipFree(p->bias);
     (void)hipFree(p->part);
     (void)hipFree(p->loss_part);
@@ -890,7 +936,7 @@ static lq_status alloc_mlp(int device, lq_mlp **out) {
     bool ok = hipMalloc((void **)&p->theta, kParams * 4) == hipSuccess &&
               hipMalloc((void **)&p->m, kParams * 4) == hipSuccess &&
               hipMalloc((void **)&p->v, kParams * 4) == hipSuccess &&
-              hipMalloc((void **)&p->wimg, kImage * 2) == hipSuccess &&
+              hipMalloc((void **)&p->wlane, kLaneElems * 2) == hipSuccess &&
               hipMalloc((void **)&p->bias, kBiasPad * 4) == hipSuccess &&
               hipMalloc((void **)&p->part, (size_t)p->part_rows * kParams * 4) == hipSuccess &&
               hipMalloc((void **)&p->loss_part, (size_t)p->part_rows * 4) == hipSuccess &&
@@ -915,7 +961,7 @@ static lq_status upload_params(lq_mlp *p, const float *host_theta, bool reset_mo
     if (e == hipSuccess && reset_moments) e = hipMemset(p->m, 0, kParams * 4);
     if (e == hipSuccess && reset_moments) e = hipMemset(p->v, 0, kParams * 4);
     if (e != hipSuccess) return mhip(e, "uploading parameters");
-    hipLaunchKernelGGL(k_pack, dim3((kImage + 255) / 256), dim3(256), 0, 0, p->theta, p->wimg, p->bias);
+    hipLaunchKernelGGL(k_pack, dim3((kLaneElems + 255) / 256), dim3(256), 0, 0, p->theta, p->wlane, p->bias);
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return mhip(e, "packing parameters");
     return LQ_OK;
@@ -951,7 +997,7 @@ static hipError_t launch_step(lq_mlp *p, const float *o, const float *d, const f
     wg = (tiles_total + tiles - 1) / tiles;
     rows = (int)wg;
     hipLaunchKernelGGL(k_train_step, dim3((unsigned)wg), dim3(256), kTrainLds, s, o, d, t, n_pairs, base, count,
-                       tiles, 1.0f / (float)count, p->wimg, p->bias, p->part, p->loss_part);
+                       tiles, 1.0f / (float)count, p->wlane, p->bias, p->part, p->loss_part);
     return hipGetLastError();
 }
 
@@ -1024,7 +1070,7 @@ lq_status lq_mlp_grad(lq_mlp *p, const float *o, const float *d, const float *rg
     e = launch_step(p, o, d, rgb, n, 0, n, rows, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, p->part, rows, p->theta,
-                           p->m, p->v, p->wimg, p->bias, p->loss_part, loss_dev, grad, 0, 0.0f, 0.0f, 0.0f, 0.0f,
+                           p->m, p->v, p->wlane, p->bias, p->loss_part, loss_dev, grad, 0, 0.0f, 0.0f, 0.0f, 0.0f,
                            0.0f, 0.0f);
         e = hipGetLastError();
     }
@@ -1069,7 +1115,7 @@ lq_status lq_mlp_train(lq_mlp *p, const float *o, const float *d, const float *r
         const float c1 = (float)(1.0 / (1.0 - pow((double)cfg->beta1, t)));
         const float c2 = (float)(1.0 / (1.0 - pow((double)cfg->beta2, t)));
         hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, p->part, rows, p->theta,
-                           p->m, p->v, p->wimg, p->bias, p->loss_part, loss_dev + k, (float *)nullptr, 1, lr,
+                           p->m, p->v, p->wlane, p->bias, p->loss_part, loss_dev + k, (float *)nullptr, 1, lr,
                            cfg->beta1, cfg->beta2, cfg->eps, c1, c2);
         e = hipGetLastError();
         p->step++;
@@ -1113,7 +1159,7 @@ lq_status lq_mlp_forward(const lq_mlp *p, const float *o, const float *d, int64_
     if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
     if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, (hipStream_t)stream, o, d, n,
-                       (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wimg, p->bias, 0, rgb,
+                       (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 0, rgb,
                        (const float *)nullptr, (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
     e = hipGetLastError();
     return e == hipSuccess ? LQ_OK : mhip(e, "surrogate forward");
@@ -1138,7 +1184,7 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
     unsigned *tcnt = reinterpret_cast<unsigned *>(tref + kTrustBins);
     hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, (const int64_t *)nullptr,
-                       (const unsigned long long *)nullptr, p->wimg, p->bias, 2, (float *)nullptr, rgb_ref, terr,
+                       (const unsigned long long *)nullptr, p->wlane, p->bias, 2, (float *)nullptr, rgb_ref, terr,
                        tref, tcnt);
     hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tref, tcnt,
                        max_rel_err, 1e-3f, 4u, p->trust);
@@ -1188,7 +1234,7 @@ lq_status lq_mlp_infer(const lq_mlp *p, const lq_octree *fallback, const float *
     hipLaunchKernelGGL(k_classify, dim3((unsigned)cblocks), dim3(256), 0, s, o, d, n, p->trust, rgb, used_fallback,
                        mlp_list, cnt, oct_list, cnt + 1);
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, mlp_list,
-                       (const unsigned long long *)cnt, p->wimg, p->bias, 0, rgb, (const float *)nullptr,
+                       (const unsigned long long *)cnt, p->wlane, p->bias, 0, rgb, (const float *)nullptr,
                        (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
     e = hipGetLastError();
     if (e == hipSuccess) {

@@ -39,13 +39,6 @@ constexpr int kW4 = kB3 + kHidden, kB4 = kW4 + kHidden * kHidden;
 constexpr int kW5 = kB4 + kHidden, kB5 = kW5 + kOut * kHidden;
 constexpr int kParams = kB5 + kOut;                              // 20931
 
-// bfloat16 weight image offsets (elements)
-constexpr int kI1 = 0;
-constexpr int kI2 = kI1 + kHidden * kFeat;
-constexpr int kI3 = kI2 + kHidden * kHidden;
-constexpr int kI4 = kI3 + kHidden * kHidden;
-constexpr int kI5 = kI4 + kHidden * kHidden;
-constexpr int kImage = kI5 + kOutPad * kHidden;                  // 21504
 constexpr int kBiasPad = 4 * kHidden + kOutPad;                  // 272 floats
 
 // trust map: octahedral 32x32 cells for the entry direction and for the ray
