@@ -324,18 +324,47 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
     float gbias = 0.0f, gb5 = 0.0f, lsum = 0.0f;
     const bf16x8 zero8 = {};
 
+    // the pair of the lane's sample in tile t (false: past the batch)
+    auto pair_of = [&](int t, int64_t &ray) {
+        const int64_t local = ((int64_t)blockIdx.x * tiles + t) * kTile + col;
+        ray = local < count ? (base + local) % n_pairs : 0;
+        return local < count;
+    };
+    // each tile loads the next tile's pair while it computes
+    float nx[9];
+    {
+        int64_t r0;
+        pair_of(0, r0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            nx[c] = o[3 * r0 + c];
+            nx[3 + c] = d[3 * r0 + c];
+            nx[6 + c] = tgt[3 * r0 + c];
+        }
+    }
     for (int tile = 0; tile < tiles; ++tile) {
         // ---- phase A: this wave's 16 samples
-        const int64_t local = ((int64_t)blockIdx.x * tiles + tile) * kTile + col;
-        const bool valid = local < count;
-        const int64_t ray = valid ? (base + local) % n_pairs : 0;
-        float x6[6] = {0, 0, 0, 0, 0, 0};
-        bool actv = false;
-        if (valid) {
-            float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
-            float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
-            actv = sphere_x6(oo, dd, x6);
+        int64_t ray;
+        const bool valid = pair_of(tile, ray);
+        float oo[3], dd[3], tt[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            oo[c] = nx[c];
+            dd[c] = nx[3 + c];
+            tt[c] = nx[6 + c];
         }
+        if (tile + 1 < tiles) {
+            int64_t rn;
+            pair_of(tile + 1, rn);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                nx[c] = o[3 * rn + c];
+                nx[3 + c] = d[3 * rn + c];
+                nx[6 + c] = tgt[3 * rn + c];
+            }
+        }
+        float x6[6] = {0, 0, 0, 0, 0, 0};
+        const bool actv = valid && sphere_x6(oo, dd, x6);
         const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
         float f[32];
         const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));
@@ -401,7 +430,7 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
             float lsmp = 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float diff = lh[c] - tgt[3 * ray + c];
+                const float diff = lh[c] - tt[c];
                 lsmp += diff * diff * id2;
                 gy[c] = 2.0f * diff * ey[c] * id2 * inv_batch;
             }
@@ -538,37 +567,41 @@ __device__ inline int bias_index(int p) {
     return -1;
 }
 
-// sum the partial rows in a fixed order; optional Adam update
 // Sum of the partial gradient rows and the Adam update.  A block takes
-// kRedParams consecutive parameters; its four waves sum fixed quarters of the
-// rows (eight interleaved accumulators each, to keep eight loads in flight)
-// and wave 0 adds the quarters in a fixed order: the result does not depend
-// on scheduling, so a resumed run repeats an uninterrupted one bit for bit.
-// Block 0 also sums the per-workgroup losses with a fixed LDS tree.
+// kRedParams consecutive parameters; its kRedWaves waves sum fixed slices of
+// the rows with all of a slice's loads in flight, and wave 0 adds the slices
+// in a fixed order: the result does not depend on scheduling, so a resumed
+// run repeats an uninterrupted one bit for bit.  Block 0 also sums the
+// per-workgroup losses with a fixed LDS tree.
 constexpr int kRedParams = 64;
+constexpr int kRedWaves = 16;
+constexpr int kRedRows = 16;      // rows per slice loaded at once
 
-__global__ __launch_bounds__(256) void k_reduce_adam(const float *part, int rows, float *theta, float *m, float *v,
-                                                     uint16_t *wlane, float *bias, const float *loss_part,
-                                                     float *loss_out, float *grad_out, int update, float lr,
-                                                     float b1, float b2, float eps, float c1, float c2) {
-    __shared__ float s_part[4][kRedParams];
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduce_adam(const float *part, int rows, float *theta, float *m,
+                                                                float *v, uint16_t *wlane, float *bias,
+                                                                const float *loss_part, float *loss_out,
+                                                                float *grad_out, int update, float lr, float b1,
+                                                                float b2, float eps, float c1, float c2) {
+    __shared__ float s_part[kRedWaves][kRedParams];
     __shared__ float s_loss[256];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p = blockIdx.x * kRedParams + lane;
     float g = 0.0f;
     if (p < kParams) {
-        const int r0 = rows * w / 4, r1 = rows * (w + 1) / 4;
-        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        int r = r0;
-        for (; r + 8 <= r1; r += 8) {
+        const int r0 = rows * w / kRedWaves, r1 = rows * (w + 1) / kRedWaves;
+        for (int r = r0; r < r1; r += kRedRows) {
+            float a[kRedRows];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j] += part[(size_t)(r + j) * kParams + p];
+            for (int j = 0; j < kRedRows; ++j) a[j] = r + j < r1 ? part[(size_t)(r + j) * kParams + p] : 0.0f;
+#pragma unroll
+            for (int st = kRedRows / 2; st > 0; st >>= 1)
+#pragma unroll
+                for (int j = 0; j < st; ++j) a[j] += a[j + st];
+            g += a[0];
         }
-        for (; r < r1; ++r) acc[0] += part[(size_t)r * kParams + p];
-        g = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     }
     s_part[w][lane] = g;
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x < 256) {
         float l = 0.0f;
         for (int r = threadIdx.x; r < rows; r += 256) l += loss_part[r];
         s_loss[threadIdx.x] = l;
@@ -582,7 +615,14 @@ __global__ __launch_bounds__(256) void k_reduce_adam(const float *part, int rows
         if (threadIdx.x == 0) *loss_out = s_loss[0];
     }
     if (w != 0 || p >= kParams) return;
-    g = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
+    float sl[kRedWaves];
+#pragma unroll
+    for (int j = 0; j < kRedWaves; ++j) sl[j] = s_part[j][lane];
+#pragma unroll
+    for (int st = kRedWaves / 2; st > 0; st >>= 1)
+#pragma unroll
+        for (int j = 0; j < st; ++j) sl[j] += sl[j + st];
+    g = sl[0];
     if (grad_out) grad_out[p] = g;
     if (!update) return;
     const float mm = b1 * m[p] + (1.0f - b1) * g;
@@ -1069,7 +1109,7 @@ lq_status lq_mlp_grad(lq_mlp *p, const float *o, const float *d, const float *rg
     int rows = 0;
     e = launch_step(p, o, d, rgb, n, 0, n, rows, s);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, p->part, rows, p->theta,
+        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(64 * kRedWaves), 0, s, p->part, rows, p->theta,
                            p->m, p->v, p->wlane, p->bias, p->loss_part, loss_dev, grad, 0, 0.0f, 0.0f, 0.0f, 0.0f,
                            0.0f, 0.0f);
         e = hipGetLastError();
@@ -1114,7 +1154,7 @@ lq_status lq_mlp_train(lq_mlp *p, const float *o, const float *d, const float *r
         const double t = (double)(gstep + 1);
         const float c1 = (float)(1.0 / (1.0 - pow((double)cfg->beta1, t)));
         const float c2 = (float)(1.0 / (1.0 - pow((double)cfg->beta2, t)));
-        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, p->part, rows, p->theta,
+        hipLaunchKernelGGL(k_reduce_adam, dim3((kParams + kRedParams - 1) / kRedParams), dim3(64 * kRedWaves), 0, s, p->part, rows, p->theta,
                            p->m, p->v, p->wlane, p->bias, p->loss_part, loss_dev + k, (float *)nullptr, 1, lr,
                            cfg->beta1, cfg->beta2, cfg->eps, c1, c2);
         e = hipGetLastError();
