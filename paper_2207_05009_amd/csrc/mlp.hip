@@ -327,7 +327,12 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
     // the pair of the lane's sample in tile t (false: past the batch)
     auto pair_of = [&](int t, int64_t &ray) {
         const int64_t local = ((int64_t)blockIdx.x * tiles + t) * kTile + col;
-        ray = local < count ? (base + local) % n_pairs : 0;
+        // base < n_pairs: one conditional subtraction unless the batch is
+        // larger than the pair set
+        int64_t r = base + local;
+        if (r >= n_pairs) r -= n_pairs;
+        if (r >= n_pairs) r %= n_pairs;
+        ray = local < count ? r : 0;
         return local < count;
     };
     // each tile loads the next tile's pair while it computes
