@@ -74,6 +74,21 @@ def alg_bytes(trace, K, elem_bytes):
         "rays": n, "mean_leaves": occ / n, "mean_composited": comp / n, "mean_nodes": steps / n}
 
 
+def variant_record(oc, o, d, model, K, elem_bytes, vms, traffic_tag=None):
+    """rays/s of a timed query launch and its algorithmic bytes against the
+    HBM peak (per-ray counts from a trace launch over the same rays), plus the
+    measured HBM bytes per launch where a counter summary exists."""
+    n = o.shape[0]
+    nbytes, counts = alg_bytes(oc.trace(o, d, model=model), K, elem_bytes)
+    achieved = nbytes / (vms * 1e-3) / 1e9
+    rec = {"rays_per_s": n / (vms * 1e-3), "ms_per_step": vms, "alg_bytes_per_launch": nbytes,
+           "achieved_gbs": round(achieved, 1), "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
+           "per_ray": counts}
+    if traffic_tag:
+        rec["traffic"] = traffic_from_profiles(traffic_tag)
+    return rec
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (lines "key: value"), if it was taken on the current kernel sources
@@ -351,12 +366,12 @@ def main():
             oc = lumiq.Octree(tree, storage)
             vms, _ = time_launches(lambda: oc.query(o, d, model="linear", rgb=rgb, alpha=alpha),
                                    max(5, args.steps // 2), 2)
-            variants[f"camera_{storage}_linear"] = {"rays_per_s": n / (vms * 1e-3), "ms_per_step": vms}
+            variants[f"camera_{storage}_linear"] = variant_record(oc, o, d, "linear", tree.K, 2, vms)
             log(f"{storage}: {vms:.3f} ms/step")
             oc.free()
         vms, _ = time_launches(lambda: oct32.query(o, d, model="exp", rgb=rgb, alpha=alpha),
                                max(5, args.steps // 2), 2)
-        variants["camera_f32_exp"] = {"rays_per_s": n / (vms * 1e-3), "ms_per_step": vms}
+        variants["camera_f32_exp"] = variant_record(oct32, o, d, "exp", tree.K, 4, vms)
         # incoherent shading queries from a room around the luminaire
         ro, rd = inputs.rays.room_to_proxy(1 << 24, 20)
         ro_t, rd_t = torch.from_numpy(ro).cuda(), torch.from_numpy(rd).cuda()
@@ -366,8 +381,9 @@ def main():
             oc = oct32 if storage == "f32" else lumiq.Octree(tree, storage)
             vms, _ = time_launches(lambda: oc.query(ro_t, rd_t, model="linear", rgb=rrgb, alpha=ralpha),
                                    max(3, args.steps // 4), 1)
-            variants[f"room16M_{storage}_linear"] = {"rays_per_s": (1 << 24) / (vms * 1e-3),
-                                                     "ms_per_step": vms}
+            variants[f"room16M_{storage}_linear"] = variant_record(
+                oc, ro_t, rd_t, "linear", tree.K, 4 if storage == "f32" else 2, vms,
+                traffic_tag=f"query_{storage}_room")
             log(f"room {storage}: {vms:.3f} ms/step")
             if storage != "f32":
                 oc.free()
