@@ -89,7 +89,8 @@ def features(x6):
 
 def forward(theta, F, round_bf16=None):
     """Returns (y [n, 3], cache).  round_bf16, if given, is applied to every
-    GEMM input (weights and activations) to mirror a bfloat16 kernel."""
+    GEMM input (weights and activations; in loss_and_grad also the output
+    gradients) to mirror a bfloat16 kernel."""
     r = round_bf16 if round_bf16 is not None else (lambda a: a)
     layers = unpack(theta)
     h = r(F)
@@ -124,7 +125,9 @@ def loss_and_grad(theta, F, target, active, round_bf16=None):
     loss = per.sum() / B
     dy = np.where(active[:, None], 2.0 * diff * ey / (den * den)[:, None], 0.0) / B
     grads = []
-    g = dy
+    # the backward GEMM inputs (output gradients) are rounded like the forward
+    # ones when round_bf16 is given
+    g = r(dy)
     for li in range(len(layers) - 1, -1, -1):
         W, b = layers[li]
         h_in = hs[li]
@@ -132,7 +135,7 @@ def loss_and_grad(theta, F, target, active, round_bf16=None):
         gb = g.sum(0)
         grads.append((gW, gb))
         if li > 0:
-            g = (g @ r(W)) * (zs[li - 1] > 0.0)
+            g = r((g @ r(W)) * (zs[li - 1] > 0.0))
     grads.reverse()
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return loss, flat

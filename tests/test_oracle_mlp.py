@@ -114,6 +114,25 @@ def test_gradient_matches_central_differences():
     assert checked > 400
 
 
+def test_bfloat16_mirror_stays_within_rounding_error():
+    """With every GEMM input rounded to bfloat16 (weights, activations and
+    output gradients), the gradient stays within the rounding error of the
+    exact one: 8 significant bits per operand, so a few per cent per element
+    at most and a direction that barely moves."""
+    theta = mlp.he_uniform(9) * 0.7
+    theta[-3:] = 0.3
+    o, d, target = _batch(512, 5)
+    x6, hit = mlp.sphere_param(o, d)
+    F = mlp.features(x6)
+    _, g = mlp.loss_and_grad(theta, F, target, hit)
+    _, gr = mlp.loss_and_grad(theta, F, target, hit, round_bf16=mlp.bf16)
+    cos = g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr))
+    rel = np.linalg.norm(gr - g) / np.linalg.norm(g)
+    assert cos > 0.99 and 1e-4 < rel < 0.1
+    # rounding only a GEMM input that is already a bfloat16 value changes nothing
+    assert np.array_equal(mlp.bf16(mlp.bf16(F)), mlp.bf16(F))
+
+
 def test_adam_first_steps_closed_form():
     g = np.array([0.3, -2.0, 1e-3, -5e-5])
     theta = np.zeros(4)
