@@ -37,16 +37,9 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kTile = 64;                   // samples per tile (16 per wave)
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ inline bf16x8 load_bf8(const uint16_t *p0, const uint16_t *p1) {
-    // four consecutive elements from p0, four from p1
-    const u16x8 v = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3]};
-    return __builtin_bit_cast(bf16x8, v);
 }
 
 typedef short s16x8 __attribute__((ext_vector_type(8)));
@@ -261,8 +254,7 @@ static_assert(lane_inverse_agrees(16384, kParams), "lane image inverse");
 typedef __bf16 bf16x4b __attribute__((ext_vector_type(4)));
 
 __device__ inline f32x4 mfma16b(bf16x4b a, bf16x4b b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a), __builtin_bit_cast(bf16x4, b), c,
-                                                     0, 0, 0);
+    return mfma16(__builtin_bit_cast(bf16x4, a), __builtin_bit_cast(bf16x4, b), c);
 }
 
 // bfloat16 of x where the activation h (bfloat16, h layout) is positive, else 0
@@ -444,7 +436,7 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
         const bf16x4b dyb = {(__bf16)gy[0], (__bf16)gy[1], (__bf16)gy[2], (__bf16)gy[3]};
         if (g == 0) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) act[(kRowDY + c) * kRS + col] = __builtin_bit_cast(uint16_t, dyb[c]);
+            for (int c = 0; c < 4; ++c) act[(kRowDY + c) * kRS + col] = f2bf(gy[c]);   // = dyb[c]
         }
 
         // backward data: dZ4 = (W5^T dY) masked by H4 > 0, then down to dZ1

@@ -67,31 +67,65 @@ def test_forward_matches_oracle(lq):
     assert np.all(g[~hit] == 0)
 
 
-def test_gradient_matches_oracle(lq):
-    o, d = _rays(2048, 3)
-    tgt = np.exp(np.random.default_rng(4).uniform(-4, 5, size=(2048, 3))).astype(np.float32)
+# 37: one partial tile; 2048: whole tiles, one per workgroup; 70,001: several
+# tiles per workgroup and a ragged last tile.  The oracle mirrors the kernel's
+# bfloat16 GEMM inputs (weights, activations, output gradients); the
+# comparison with the exact FP64 gradient states the bfloat16 error.
+@pytest.mark.parametrize("n", [37, 2048, 70001])
+def test_gradient_matches_oracle(lq, n):
+    o, d = _rays(n, 3)
+    tgt = np.exp(np.random.default_rng(4).uniform(-4, 5, size=(n, 3))).astype(np.float32)
     sur = lq.Surrogate(seed=1)
     th = _theta(5, 0.7)
     sur.set_params(th)
-    _say("surrogate gradient")
+    _say(f"surrogate gradient, {n} samples")
     loss, g = sur.grad(_dev(o), _dev(d), _dev(tgt))
     g = g.cpu().numpy().astype(np.float64)
     x6, hit = omlp.sphere_param(o, d)
     F = omlp.features(x6)
     rl, rg = omlp.loss_and_grad(th.astype(np.float64), F, tgt.astype(np.float64), hit,
                                 round_bf16=omlp.bf16)
+    _, xg = omlp.loss_and_grad(th.astype(np.float64), F, tgt.astype(np.float64), hit)
     assert loss == pytest.approx(rl, rel=2e-2)
     cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
     rel_l2 = float(np.linalg.norm(g - rg) / np.linalg.norm(rg))
-    _say(f"gradient cosine {cos:.6f} rel-L2 {rel_l2:.3e}")
-    assert cos > 0.999 and rel_l2 < 3e-2
+    xcos = float(g @ xg / (np.linalg.norm(g) * np.linalg.norm(xg)))
+    xrel = float(np.linalg.norm(g - xg) / np.linalg.norm(xg))
+    _say(f"vs bf16-mirroring oracle: cosine {cos:.7f} rel-L2 {rel_l2:.3e}; "
+         f"vs exact FP64: cosine {xcos:.6f} rel-L2 {xrel:.3e}")
+    assert cos > 0.999 and rel_l2 < 1e-2
+    assert xcos > 0.99
     # layer by layer
     off = 0
     for i, o_ in omlp.LAYERS:
         sl = slice(off, off + i * o_ + o_)
         c = g[sl] @ rg[sl] / (np.linalg.norm(g[sl]) * np.linalg.norm(rg[sl]))
-        assert c > 0.998, (i, o_, c)
+        assert c > 0.999, (i, o_, c)
         off += i * o_ + o_
+
+
+@pytest.mark.parametrize("n", [32, 37])
+def test_gradient_ignores_padding(lq, n):
+    """The same n samples followed by n rays that miss the bounding sphere:
+    the misses contribute nothing, and the batch mean over 2n halves the
+    gradient and the loss exactly (a power-of-two scale commutes with every
+    rounding), so the two gradients agree bit for bit -- through a partial
+    tile, and through a second tile and workgroup of padding."""
+    o, d = _rays(n, 11)
+    tgt = np.exp(np.random.default_rng(12).uniform(-4, 5, size=(n, 3))).astype(np.float32)
+    o_miss = np.tile(np.float32([10.0, 10.0, 10.0]), (n, 1))
+    d_miss = np.tile(np.float32([1.0, 0.0, 0.0]), (n, 1))
+    sur = lq.Surrogate(seed=1)
+    sur.set_params(_theta(5, 0.7))
+    _say(f"surrogate gradient, {n} samples with and without {n} misses")
+    l1, g1 = sur.grad(_dev(o), _dev(d), _dev(tgt))
+    l2, g2 = sur.grad(_dev(np.concatenate([o, o_miss])), _dev(np.concatenate([d, d_miss])),
+                      _dev(np.concatenate([tgt, tgt])))
+    g1 = g1.cpu().numpy()
+    g2 = g2.cpu().numpy()
+    assert np.count_nonzero(g1) > 0.5 * g1.size
+    assert l2 == l1 / 2
+    assert np.array_equal(g2, g1 / 2)
 
 
 def test_adam_steps_match_oracle(lq):
