@@ -151,13 +151,14 @@ def cpu_baseline(tree, o, d, budget_s):
 def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
     """Learned surrogate: trained on (ray, radiance) pairs that the float32
     octree renders for incoherent room rays, trust map from held-out pairs
-    at 1% relative error (20,000,000 held-out rays), then inference with
-    octree fallback on the 16,777,216 room rays."""
+    at 1% relative error (30,000,000 held-out rays: 20M for the bin
+    statistics, 10M to calibrate the threshold), then inference with octree
+    fallback on the 16,777,216 room rays."""
     import torch
     import inputs
     t0 = time.perf_counter()
     o, d = inputs.rays.room_to_proxy(args.surrogate_pairs, 30)
-    ho, hd = inputs.rays.room_to_proxy(20_000_000, 32)
+    ho, hd = inputs.rays.room_to_proxy(30_000_000, 32)
     o, d, ho, hd = [torch.from_numpy(x).cuda() for x in (o, d, ho, hd)]
     rgb, _ = oct32.query(o, d)
     hrgb, _ = oct32.query(ho, hd)

@@ -223,9 +223,15 @@ lq_status lq_mlp_forward(const lq_mlp *mlp, const float *origins, const float *d
 /*
  * Trust map: held-out (ray, reference radiance) pairs are binned by the
  * octahedral cells (32 x 32) of the entry direction and of the ray
- * direction (1,048,576 bins); a bin is trusted when it holds at least 4 pairs and its
- * squared error sum is within max_rel_err^2 of its squared reference sum
- * (plus (1e-3)^2 per pair).  Synchronises the stream.
+ * direction (1,048,576 bins).  The first two thirds of the pairs give each
+ * bin its mean squared error per pair (bins with fewer than 4 pairs are never
+ * trusted); the last third calibrates: bins are trusted in increasing error
+ * per pair while the squared error that the calibration pairs of the trusted
+ * bins would leave stays within (0.75 max_rel_err)^2 of the calibration
+ * pairs' total squared reference, i.e. the bound is on the aggregate
+ * relative L2 error of the hybrid output, with a safety factor for the
+ * sampling error of the calibration.  The pairs must be in random order (the
+ * split is by position); n >= 3.  Synchronises the stream.
  */
 lq_status lq_mlp_build_trust(lq_mlp *mlp, const float *origins, const float *dirs,
                              const float *rgb_ref, int64_t n, float max_rel_err, void *hip_stream);

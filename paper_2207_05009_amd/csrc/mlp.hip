@@ -870,14 +870,66 @@ __global__ __launch_bounds__(256) void k_classify(const float *o, const float *d
     }
 }
 
-__global__ void k_trust_finalize(const double *terr, const double *tref, const unsigned *tcnt, float max_rel,
-                                 float abs_floor, unsigned min_count, uint8_t *trust) {
+// Calibrated trust map.  The held-out pairs are split: the first part gives
+// each bin its mean squared error per ray m = err^2 / pairs, the second part
+// (independent of the first) measures, per bucket of m, the squared error its
+// rays would leave in the output if those bins were trusted.  Bins are then
+// trusted in increasing m for as long as the calibration part's accumulated
+// error stays within the bound on its total reference energy: the bound is
+// on the aggregate error of the hybrid output, so the bins that cost least
+// error per ray served go first (dark bins with small absolute errors before
+// bright ones with a small relative error), and bins whose small first-part
+// error was luck (few rays, heavy tails) show it on the second part.
+// Buckets: half-octaves of m.
+constexpr int kCalBuckets = 128;
+constexpr int kCalBias = 80;          // bucket of m = 1 (m below 2^-39.5 shares bucket 1)
+constexpr double kCalMargin = 0.75;   // the calibration part is held to this fraction of the bound
+
+__device__ inline int cal_bucket(double terr, unsigned cnt) {
+    const double m = terr / (double)(cnt > 0 ? cnt : 1);
+    if (!(m > 0.0)) return 0;
+    const int k = (int)floor(2.0 * log2(m)) + kCalBias;
+    return k < 1 ? 1 : (k >= kCalBuckets ? kCalBuckets - 1 : k);
+}
+
+// hist[k] (k < kCalBuckets): calibration-part squared error of the bins in
+// bucket k (bins with at least min_count first-part pairs); hist[kCalBuckets
+// + k]: their calibration pairs; hist[2 kCalBuckets]: the calibration part's
+// total squared reference.
+__global__ __launch_bounds__(256) void k_trust_hist(const double *terr, const unsigned *tcnt, const double *cerr,
+                                                    const double *cref, const unsigned *ccnt, unsigned min_count,
+                                                    double *hist) {
+    __shared__ double s_err[kCalBuckets], s_cnt[kCalBuckets], s_ref[256];
+    for (int k = threadIdx.x; k < kCalBuckets; k += blockDim.x) s_err[k] = s_cnt[k] = 0.0;
+    __syncthreads();
+    double ref = 0.0;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < kTrustBins; b += gridDim.x * blockDim.x) {
+        ref += cref[b];
+        if (tcnt[b] < min_count || ccnt[b] == 0) continue;
+        const int k = cal_bucket(terr[b], tcnt[b]);
+        atomicAdd(&s_err[k], cerr[b]);
+        atomicAdd(&s_cnt[k], (double)ccnt[b]);
+    }
+    s_ref[threadIdx.x] = ref;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) s_ref[threadIdx.x] += s_ref[threadIdx.x + st];
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < kCalBuckets; k += blockDim.x) {
+        if (s_cnt[k] > 0.0) {
+            atomicAdd(hist + k, s_err[k]);
+            atomicAdd(hist + kCalBuckets + k, s_cnt[k]);
+        }
+    }
+    if (threadIdx.x == 0) atomicAdd(hist + 2 * kCalBuckets, s_ref[0]);
+}
+
+__global__ void k_trust_finalize(const double *terr, const unsigned *tcnt, unsigned min_count, int kmax,
+                                 uint8_t *trust) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= kTrustBins) return;
-    const double cnt = tcnt[b];
-    const bool ok = tcnt[b] >= min_count &&
-                    terr[b] <= (double)max_rel * max_rel * tref[b] + (double)abs_floor * abs_floor * cnt;
-    trust[b] = ok ? 1 : 0;
+    trust[b] = tcnt[b] >= min_count && cal_bucket(terr[b], tcnt[b]) <= kmax ? 1 : 0;
 }
 
 __global__ void k_zero_bytes(unsigned char *p, size_t n) {
@@ -1213,19 +1265,49 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
     if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
     if ((st = check_dev_ptr(rgb_ref, n * 12, p->device, "rgb_ref")) != LQ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = (size_t)kTrustBins * (8 + 8 + 4);
+    // first two thirds: per-bin statistics; last third: calibration
+    const int64_t n_cal = n / 3, n_bin = n - n_cal;
+    if (n_cal < 1) return mfail(LQ_ERR_INVALID_ARG, "at least 3 held-out pairs required");
+    const size_t stat_bytes = (size_t)kTrustBins * (8 + 8 + 4);
+    const size_t bytes = 2 * stat_bytes + (2 * kCalBuckets + 1) * 8;
     unsigned char *acc = nullptr;
     if ((e = hipMallocAsync((void **)&acc, bytes, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
     double *terr = reinterpret_cast<double *>(acc);
     double *tref = terr + kTrustBins;
     unsigned *tcnt = reinterpret_cast<unsigned *>(tref + kTrustBins);
+    double *cerr = reinterpret_cast<double *>(acc + stat_bytes);
+    double *cref = cerr + kTrustBins;
+    unsigned *ccnt = reinterpret_cast<unsigned *>(cref + kTrustBins);
+    double *hist = reinterpret_cast<double *>(acc + 2 * stat_bytes);
+    constexpr unsigned kMinCount = 4;
     hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, (const int64_t *)nullptr,
-                       (const unsigned long long *)nullptr, p->wlane, p->bias, 2, (float *)nullptr, rgb_ref, terr,
-                       tref, tcnt);
-    hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tref, tcnt,
-                       max_rel_err, 1e-3f, 4u, p->trust);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n_bin,
+                       (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 2,
+                       (float *)nullptr, rgb_ref, terr, tref, tcnt);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o + 3 * n_bin, d + 3 * n_bin,
+                       n_cal, (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 2,
+                       (float *)nullptr, rgb_ref + 3 * n_bin, cerr, cref, ccnt);
+    hipLaunchKernelGGL(k_trust_hist, dim3(256), dim3(256), 0, s, terr, tcnt, cerr, cref, ccnt, kMinCount, hist);
+    std::vector<double> h(2 * kCalBuckets + 1);
     e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), hist, h.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int kmax = -1;
+    if (e == hipSuccess) {
+        // trust buckets in increasing error per ray while the calibration
+        // part's accumulated error stays within the (margined) bound
+        const double lim = kCalMargin * (double)max_rel_err;
+        const double budget = lim * lim * h[2 * kCalBuckets];
+        double cum = 0.0;
+        for (int k = 0; k < kCalBuckets; ++k) {
+            cum += h[k];
+            if (cum > budget) break;
+            kmax = k;
+        }
+        hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tcnt,
+                           kMinCount, kmax, p->trust);
+        e = hipGetLastError();
+    }
     (void)hipFreeAsync(acc, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return mhip(e, "building the trust map");
