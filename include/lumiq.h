@@ -224,9 +224,9 @@ lq_status lq_mlp_forward(const lq_mlp *mlp, const float *origins, const float *d
  * Trust map: held-out (ray, reference radiance) pairs are binned by the
  * octahedral cells (32 x 32) of the entry direction and of the ray
  * direction (1,048,576 bins).  The first two thirds of the pairs give each
- * bin its mean squared error per pair (bins with fewer than 4 pairs are never
- * trusted); the last third calibrates: bins are trusted in increasing error
- * per pair while the squared error that the calibration pairs of the trusted
+ * bin the largest squared error of any of its pairs (bins with fewer than 4
+ * pairs are never trusted); the last third calibrates: bins are trusted in
+ * increasing largest error while the squared error that the calibration pairs of the trusted
  * bins would leave stays within (0.75 max_rel_err)^2 of the calibration
  * pairs' total squared reference, i.e. the bound is on the aggregate
  * relative L2 error of the hybrid output, with a safety factor for the

@@ -685,7 +685,8 @@ __device__ inline void load_ray(const float *o, const float *d, int64_t ray, boo
 __device__ inline int64_t ray_of(const int64_t *index, int64_t pos) { return index ? index[pos] : pos; }
 
 // mode 0: radiance; mode 2: accumulate trust statistics against the
-// reference radiance.  With an index list the kernel answers rays
+// reference radiance (per bin: squared error and reference sums, pair count,
+// largest squared error of a pair; null arrays are skipped).  With an index list the kernel answers rays
 // index[0 .. *n_dev) (the count read on the device), else rays 0 .. n.
 constexpr int kInfBlock = 512;               // inference block: eight waves share one copy of the weights
 constexpr int kInfWaves = kInfBlock / 64;
@@ -693,7 +694,7 @@ constexpr int kInfWaves = kInfBlock / 64;
 __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_infer(
     const float *o, const float *d, int64_t n, const int64_t *index, const unsigned long long *n_dev,
     const uint16_t *wlane, const float *bias, int mode, float *rgb, const float *ref, double *terr,
-    double *tref, unsigned *tcnt) {
+    double *tref, unsigned *tcnt, unsigned long long *tmax) {
     __shared__ __align__(16) float sB[kBiasPad];
     for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
     __syncthreads();
@@ -788,16 +789,18 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
                 if (act) {
                     const float p6[6] = {e0, e1, e2, e3, e4, e5};
                     const int bin = trust_bin(p6);
-                    double e2 = 0.0, r2 = 0.0;
+                    double se = 0.0, sr = 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const double rc = ref[3 * ray + c];
-                        e2 += ((double)L[c] - rc) * ((double)L[c] - rc);
-                        r2 += rc * rc;
+                        se += ((double)L[c] - rc) * ((double)L[c] - rc);
+                        sr += rc * rc;
                     }
-                    atomicAdd(terr + bin, e2);
-                    atomicAdd(tref + bin, r2);
+                    if (terr) atomicAdd(terr + bin, se);
+                    if (tref) atomicAdd(tref + bin, sr);
                     atomicAdd(tcnt + bin, 1u);
+                    // a non-negative double orders like its bit pattern
+                    if (tmax) atomicMax(tmax + bin, (unsigned long long)__double_as_longlong(se));
                 }
             } else {
                 rgb[3 * ray] = L[0];
@@ -871,22 +874,23 @@ __global__ __launch_bounds__(256) void k_classify(const float *o, const float *d
 }
 
 // Calibrated trust map.  The held-out pairs are split: the first part gives
-// each bin its mean squared error per ray m = err^2 / pairs, the second part
+// each bin the largest squared error m of any of its pairs, the second part
 // (independent of the first) measures, per bucket of m, the squared error its
 // rays would leave in the output if those bins were trusted.  Bins are then
 // trusted in increasing m for as long as the calibration part's accumulated
-// error stays within the bound on its total reference energy: the bound is
-// on the aggregate error of the hybrid output, so the bins that cost least
-// error per ray served go first (dark bins with small absolute errors before
-// bright ones with a small relative error), and bins whose small first-part
-// error was luck (few rays, heavy tails) show it on the second part.
-// Buckets: half-octaves of m.
+// error stays within the bound on its total reference energy.  The bound is
+// on the aggregate error of the hybrid output, so absolute errors rank the
+// bins (dark bins with small errors go before bright ones with a small
+// relative error), and the largest error rather than the mean: the per-ray
+// errors are heavy tailed (a ray grazing a bright shell the network misses
+// can cost more than the whole budget), and a bin that showed one such ray
+// in the first part is likely to show more.  Buckets: half-octaves of m.
 constexpr int kCalBuckets = 128;
 constexpr int kCalBias = 80;          // bucket of m = 1 (m below 2^-39.5 shares bucket 1)
 constexpr double kCalMargin = 0.75;   // the calibration part is held to this fraction of the bound
 
-__device__ inline int cal_bucket(double terr, unsigned cnt) {
-    const double m = terr / (double)(cnt > 0 ? cnt : 1);
+__device__ inline int cal_bucket(unsigned long long max_bits) {
+    const double m = __longlong_as_double((long long)max_bits);
     if (!(m > 0.0)) return 0;
     const int k = (int)floor(2.0 * log2(m)) + kCalBias;
     return k < 1 ? 1 : (k >= kCalBuckets ? kCalBuckets - 1 : k);
@@ -896,9 +900,9 @@ __device__ inline int cal_bucket(double terr, unsigned cnt) {
 // bucket k (bins with at least min_count first-part pairs); hist[kCalBuckets
 // + k]: their calibration pairs; hist[2 kCalBuckets]: the calibration part's
 // total squared reference.
-__global__ __launch_bounds__(256) void k_trust_hist(const double *terr, const unsigned *tcnt, const double *cerr,
-                                                    const double *cref, const unsigned *ccnt, unsigned min_count,
-                                                    double *hist) {
+__global__ __launch_bounds__(256) void k_trust_hist(const unsigned long long *tmax, const unsigned *tcnt,
+                                                    const double *cerr, const double *cref, const unsigned *ccnt,
+                                                    unsigned min_count, double *hist) {
     __shared__ double s_err[kCalBuckets], s_cnt[kCalBuckets], s_ref[256];
     for (int k = threadIdx.x; k < kCalBuckets; k += blockDim.x) s_err[k] = s_cnt[k] = 0.0;
     __syncthreads();
@@ -906,7 +910,7 @@ __global__ __launch_bounds__(256) void k_trust_hist(const double *terr, const un
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < kTrustBins; b += gridDim.x * blockDim.x) {
         ref += cref[b];
         if (tcnt[b] < min_count || ccnt[b] == 0) continue;
-        const int k = cal_bucket(terr[b], tcnt[b]);
+        const int k = cal_bucket(tmax[b]);
         atomicAdd(&s_err[k], cerr[b]);
         atomicAdd(&s_cnt[k], (double)ccnt[b]);
     }
@@ -925,11 +929,11 @@ __global__ __launch_bounds__(256) void k_trust_hist(const double *terr, const un
     if (threadIdx.x == 0) atomicAdd(hist + 2 * kCalBuckets, s_ref[0]);
 }
 
-__global__ void k_trust_finalize(const double *terr, const unsigned *tcnt, unsigned min_count, int kmax,
+__global__ void k_trust_finalize(const unsigned long long *tmax, const unsigned *tcnt, unsigned min_count, int kmax,
                                  uint8_t *trust) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= kTrustBins) return;
-    trust[b] = tcnt[b] >= min_count && cal_bucket(terr[b], tcnt[b]) <= kmax ? 1 : 0;
+    trust[b] = tcnt[b] >= min_count && cal_bucket(tmax[b]) <= kmax ? 1 : 0;
 }
 
 __global__ void k_zero_bytes(unsigned char *p, size_t n) {
@@ -1249,7 +1253,8 @@ lq_status lq_mlp_forward(const lq_mlp *p, const float *o, const float *d, int64_
     if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, (hipStream_t)stream, o, d, n,
                        (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 0, rgb,
-                       (const float *)nullptr, (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
+                       (const float *)nullptr, (double *)nullptr, (double *)nullptr, (unsigned *)nullptr,
+                       (unsigned long long *)nullptr);
     e = hipGetLastError();
     return e == hipSuccess ? LQ_OK : mhip(e, "surrogate forward");
 }
@@ -1268,33 +1273,33 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
     // first two thirds: per-bin statistics; last third: calibration
     const int64_t n_cal = n / 3, n_bin = n - n_cal;
     if (n_cal < 1) return mfail(LQ_ERR_INVALID_ARG, "at least 3 held-out pairs required");
-    const size_t stat_bytes = (size_t)kTrustBins * (8 + 8 + 4);
-    const size_t bytes = 2 * stat_bytes + (2 * kCalBuckets + 1) * 8;
+    // first part: largest squared error and pair count per bin; calibration
+    // part: squared error and reference sums and pair count per bin
+    const size_t bytes = (size_t)kTrustBins * (8 + 4) + (size_t)kTrustBins * (8 + 8 + 4) + (2 * kCalBuckets + 1) * 8;
     unsigned char *acc = nullptr;
     if ((e = hipMallocAsync((void **)&acc, bytes, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
-    double *terr = reinterpret_cast<double *>(acc);
-    double *tref = terr + kTrustBins;
-    unsigned *tcnt = reinterpret_cast<unsigned *>(tref + kTrustBins);
-    double *cerr = reinterpret_cast<double *>(acc + stat_bytes);
+    unsigned long long *tmax = reinterpret_cast<unsigned long long *>(acc);
+    double *cerr = reinterpret_cast<double *>(tmax + kTrustBins);
     double *cref = cerr + kTrustBins;
-    unsigned *ccnt = reinterpret_cast<unsigned *>(cref + kTrustBins);
-    double *hist = reinterpret_cast<double *>(acc + 2 * stat_bytes);
+    double *hist = cref + kTrustBins;
+    unsigned *tcnt = reinterpret_cast<unsigned *>(hist + 2 * kCalBuckets + 1);
+    unsigned *ccnt = tcnt + kTrustBins;
     constexpr unsigned kMinCount = 4;
     hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n_bin,
                        (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 2,
-                       (float *)nullptr, rgb_ref, terr, tref, tcnt);
+                       (float *)nullptr, rgb_ref, (double *)nullptr, (double *)nullptr, tcnt, tmax);
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o + 3 * n_bin, d + 3 * n_bin,
                        n_cal, (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 2,
-                       (float *)nullptr, rgb_ref + 3 * n_bin, cerr, cref, ccnt);
-    hipLaunchKernelGGL(k_trust_hist, dim3(256), dim3(256), 0, s, terr, tcnt, cerr, cref, ccnt, kMinCount, hist);
+                       (float *)nullptr, rgb_ref + 3 * n_bin, cerr, cref, ccnt, (unsigned long long *)nullptr);
+    hipLaunchKernelGGL(k_trust_hist, dim3(256), dim3(256), 0, s, tmax, tcnt, cerr, cref, ccnt, kMinCount, hist);
     std::vector<double> h(2 * kCalBuckets + 1);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), hist, h.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     int kmax = -1;
     if (e == hipSuccess) {
-        // trust buckets in increasing error per ray while the calibration
+        // trust buckets in increasing largest error while the calibration
         // part's accumulated error stays within the (margined) bound
         const double lim = kCalMargin * (double)max_rel_err;
         const double budget = lim * lim * h[2 * kCalBuckets];
@@ -1304,7 +1309,7 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
             if (cum > budget) break;
             kmax = k;
         }
-        hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, terr, tcnt,
+        hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, tmax, tcnt,
                            kMinCount, kmax, p->trust);
         e = hipGetLastError();
     }
@@ -1354,7 +1359,7 @@ lq_status lq_mlp_infer(const lq_mlp *p, const lq_octree *fallback, const float *
                        mlp_list, cnt, oct_list, cnt + 1);
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, mlp_list,
                        (const unsigned long long *)cnt, p->wlane, p->bias, 0, rgb, (const float *)nullptr,
-                       (double *)nullptr, (double *)nullptr, (unsigned *)nullptr);
+                       (double *)nullptr, (double *)nullptr, (unsigned *)nullptr, (unsigned long long *)nullptr);
     e = hipGetLastError();
     if (e == hipSuccess) {
         lq_status q = query_indexed(fallback, o, d, n, oct_list, cnt + 1, rgb, s);
