@@ -43,19 +43,32 @@ __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// v[j], v[j + 1] as bfloat16 (nearest even) in one word, v[j] in the low
+// half; converted as a two-element vector, which the compiler turns into one
+// packed conversion (element by element it converts each value alone and
+// merges the halves afterwards: three instructions per pair instead of one)
+template <int J>
+__device__ inline unsigned pk2(f32x4 v) {
+    const f32x2 p = __builtin_shufflevector(v, v, J, J + 1);
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(p, bf16x2));
+}
+
+// the eight values lo[0..3], hi[0..3] as bfloat16, in that order
+__device__ inline s16x8 pack8(f32x4 lo, f32x4 hi) {
+    const u32x4 w = {pk2<0>(lo), pk2<2>(lo), pk2<0>(hi), pk2<2>(hi)};
+    return __builtin_bit_cast(s16x8, w);
+}
 
 // bfloat16 of relu(x) for eight values: round first, then clear the negative
 // ones as signed 16-bit integers (a bfloat16 with its sign bit set is negative
 // as an int16), which equals rounding relu(x) and takes one packed max per pair
 __device__ inline bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
-    bf16x8 h;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        h[i] = (__bf16)lo[i];
-        h[4 + i] = (__bf16)hi[i];
-    }
     const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(s16x8, h), zero));
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(pack8(lo, hi), zero));
 }
 
 // variable whose 10 frequencies lane group g evaluates, the variable of its
@@ -257,16 +270,12 @@ __device__ inline f32x4 mfma16b(bf16x4b a, bf16x4b b, f32x4 c) {
     return mfma16(__builtin_bit_cast(bf16x4, a), __builtin_bit_cast(bf16x4, b), c);
 }
 
-// bfloat16 of x where the activation h (bfloat16, h layout) is positive, else 0
+// bfloat16 of x where the activation h (bfloat16, h layout) is positive, else
+// 0: the mask min(max(h, 0), 1) per 16-bit half, negated to all ones
 __device__ inline bf16x8 mask_pack(f32x4 lo, f32x4 hi, bf16x8 h) {
-    const s16x8 hs = __builtin_bit_cast(s16x8, h);
-    bf16x8 z;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        z[i] = hs[i] > 0 ? (__bf16)lo[i] : (__bf16)0.0f;
-        z[4 + i] = hs[4 + i] > 0 ? (__bf16)hi[i] : (__bf16)0.0f;
-    }
-    return z;
+    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0}, one = {1, 1, 1, 1, 1, 1, 1, 1};
+    const s16x8 pos = __builtin_elementwise_min(__builtin_elementwise_max(__builtin_bit_cast(s16x8, h), zero), one);
+    return __builtin_bit_cast(bf16x8, pack8(lo, hi) & (zero - pos));
 }
 
 // write the h-layout pair hv (features 16 (2 kb + e / 4) + 4 g + e % 4 of
@@ -374,9 +383,9 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
         bf16x8 x[4];
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[kb][e] = (__bf16)f[kb * 8 + e];
-            x[kb] = actv ? x[kb] : zero8;
+            const f32x4 lo = {f[kb * 8], f[kb * 8 + 1], f[kb * 8 + 2], f[kb * 8 + 3]};
+            const f32x4 hi = {f[kb * 8 + 4], f[kb * 8 + 5], f[kb * 8 + 6], f[kb * 8 + 7]};
+            x[kb] = actv ? __builtin_bit_cast(bf16x8, pack8(lo, hi)) : zero8;
             const s16x8 v = __builtin_bit_cast(s16x8, x[kb]);
 #pragma unroll
             for (int e = 0; e < 8; ++e) act[(kRowX + slot_feature(g, kb * 8 + e)) * kRS + col] = (uint16_t)v[e];
@@ -748,13 +757,14 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
         sincos_run5(run_b0(g) ? vb * 32.0f : vb, f + 20);
         f[30] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g) : 0.0f;
         f[31] = g < 3 ? pick6(e0, e1, e2, e3, e4, e5, 2 * g + 1) : 0.0f;
+        // (the features of rays that miss the sphere are finite and their
+        // outputs are discarded)
         bf16x8 x[4];
-        const bf16x8 zero8 = {};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[kb][e] = (__bf16)f[kb * 8 + e];
-            x[kb] = act ? x[kb] : zero8;   // rays that miss the sphere: zero features
+            const f32x4 lo = {f[kb * 8], f[kb * 8 + 1], f[kb * 8 + 2], f[kb * 8 + 3]};
+            const f32x4 hi = {f[kb * 8 + 4], f[kb * 8 + 5], f[kb * 8 + 6], f[kb * 8 + 7]};
+            x[kb] = __builtin_bit_cast(bf16x8, pack8(lo, hi));
         }
 
         f32x4 acc[4];
