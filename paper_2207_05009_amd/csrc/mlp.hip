@@ -369,8 +369,9 @@ __global__ __launch_bounds__(256) void k_train_step(const float *o, const float 
                 nx[6 + c] = tgt[3 * rn + c];
             }
         }
-        float x6[6] = {0, 0, 0, 0, 0, 0};
-        const bool actv = valid && sphere_x6(oo, dd, x6);
+        float x6[6];
+        const bool hit = sphere_x6(oo, dd, x6);
+        const bool actv = valid && hit;
         const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
         float f[32];
         const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));
@@ -683,11 +684,12 @@ __global__ void k_pack(const float *theta, uint16_t *wlane, float *bias) {
 // (slot_feature below): lane group g evaluates 10 + 5 consecutive
 // frequencies of two input variables: the hardware sine and cosine at the
 // first frequency of each run of five, then angle doubling.
-__device__ inline void load_ray(const float *o, const float *d, int64_t ray, bool valid, float *oo, float *dd) {
+// (lanes past the end load ray 0: their results are discarded)
+__device__ inline void load_ray(const float *o, const float *d, int64_t ray, float *oo, float *dd) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        oo[c] = valid ? o[3 * ray + c] : 0.0f;
-        dd[c] = valid ? d[3 * ray + c] : 0.0f;
+        oo[c] = o[3 * ray + c];
+        dd[c] = d[3 * ray + c];
     }
 }
 
@@ -733,7 +735,7 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
     bool nvalid = blk * 16 + r16 < n;
     int64_t nray = nvalid ? ray_of(index, blk * 16 + r16) : 0;
     float no[3], nd[3];
-    load_ray(o, d, nray, nvalid, no, nd);
+    load_ray(o, d, nray, no, nd);
     for (; blk < nblk; blk += wstride) {
         // a fence per tile keeps the weight reads inside the loop (hoisted,
         // the operands would need the register file of a single wave)
@@ -744,10 +746,11 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
         const int64_t nxt = blk + wstride;
         nvalid = nxt < nblk && nxt * 16 + r16 < n;
         nray = nvalid ? ray_of(index, nxt * 16 + r16) : 0;
-        load_ray(o, d, nray, nvalid, no, nd);
+        load_ray(o, d, nray, no, nd);
 
-        float x6[6] = {0, 0, 0, 0, 0, 0};
-        const bool act = valid && sphere_x6(oo, dd, x6);
+        float x6[6];
+        const bool hit = sphere_x6(oo, dd, x6);
+        const bool act = valid && hit;
         const float e0 = x6[0], e1 = x6[1], e2 = x6[2], e3 = x6[3], e4 = x6[4], e5 = x6[5];
         float f[32];
         const float va = pick6(e0, e1, e2, e3, e4, e5, run_a(g));

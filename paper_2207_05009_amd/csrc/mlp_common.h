@@ -64,18 +64,20 @@ __device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 }
 
 // sphere parameterisation of the line o + t d; returns false on a miss
-// (hardware reciprocal square root and square root, within a few units in
-// the last place: the features are rounded to bfloat16 afterwards)
+// (a direction whose squared length is zero -- also by underflow -- or not
+// finite, or a line that misses the sphere).  x6 is
+// written in every case, branch-free; after a miss its values mean nothing
+// and need not be finite.  Hardware reciprocal square root and square root,
+// within a few units in the last place: the features are rounded to
+// bfloat16 afterwards.
 __device__ inline bool sphere_x6(const float *o, const float *d, float *x6) {
     const float dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (!(dd > 0.0f) || !isfinite(dd)) return false;
     const float inv = __builtin_amdgcn_rsqf(dd);
     const float dn0 = d[0] * inv, dn1 = d[1] * inv, dn2 = d[2] * inv;
     const float b = o[0] * dn0 + o[1] * dn1 + o[2] * dn2;
     const float c = o[0] * o[0] + o[1] * o[1] + o[2] * o[2] - kR2;
     const float disc = b * b - c;
-    if (!(disc > 0.0f)) return false;
-    const float t = -b - __builtin_amdgcn_sqrtf(disc);
+    const float t = -b - __builtin_amdgcn_sqrtf(fmaxf(disc, 0.0f));
     const float s = 0.57735026918962576f;   // 1 / sqrt(3)
     x6[0] = (o[0] + t * dn0) * s;
     x6[1] = (o[1] + t * dn1) * s;
@@ -83,7 +85,7 @@ __device__ inline bool sphere_x6(const float *o, const float *d, float *x6) {
     x6[3] = dn0;
     x6[4] = dn1;
     x6[5] = dn2;
-    return true;
+    return dd > 0.0f && isfinite(dd) && disc > 0.0f;
 }
 
 // octahedral cell (0..kOctRes^2-1) of a unit vector
