@@ -151,9 +151,8 @@ def cpu_baseline(tree, o, d, budget_s):
 def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
     """Learned surrogate: trained on (ray, radiance) pairs that the float32
     octree renders for incoherent room rays, trust map from held-out pairs
-    at 1% relative error (30,000,000 held-out rays: 20M for the bin
-    statistics, 10M to calibrate the threshold), then inference with octree
-    fallback on the 16,777,216 room rays."""
+    at 1% relative error (30,000,000 held-out rays), then inference with
+    octree fallback on the 16,777,216 room rays."""
     import torch
     import inputs
     t0 = time.perf_counter()
@@ -254,7 +253,7 @@ def uneven_variant(lumiq):
         if b - a < (1 << 20):
             continue
         to_, td_ = inputs.rays.room_to_proxy(8_000_000, 100 + k)
-        ho_, hd_ = inputs.rays.room_to_proxy(8_000_000, 200 + k)
+        ho_, hd_ = inputs.rays.room_to_proxy(24_000_000, 200 + k)
         to_, td_, ho_, hd_ = [torch.from_numpy(x).cuda() for x in (to_, td_, ho_, hd_)]
         trgb, _ = oc.query(to_, td_)
         hrgb, _ = oc.query(ho_, hd_)
@@ -284,7 +283,7 @@ def uneven_variant(lumiq):
         log(f"uneven batch: luminaire {k} surrogate {surr[-1]}")
         sur.free()
     res["surrogates"] = {"train_steps": UNEVEN_SURROGATE_STEPS, "train_pairs": 8_000_000,
-                         "heldout_pairs": 8_000_000, "per_luminaire": surr}
+                         "heldout_pairs": 24_000_000, "per_luminaire": surr}
     for oc in octs:
         oc.free()
     return res

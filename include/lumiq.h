@@ -223,15 +223,11 @@ lq_status lq_mlp_forward(const lq_mlp *mlp, const float *origins, const float *d
 /*
  * Trust map: held-out (ray, reference radiance) pairs are binned by the
  * octahedral cells (32 x 32) of the entry direction and of the ray
- * direction (1,048,576 bins).  The first two thirds of the pairs give each
- * bin the largest squared error of any of its pairs (bins with fewer than 4
- * pairs are never trusted); the last third calibrates: bins are trusted in
- * increasing largest error while the squared error that the calibration pairs of the trusted
- * bins would leave stays within (0.75 max_rel_err)^2 of the calibration
- * pairs' total squared reference, i.e. the bound is on the aggregate
- * relative L2 error of the hybrid output, with a safety factor for the
- * sampling error of the calibration.  The pairs must be in random order (the
- * split is by position); n >= 3.  Synchronises the stream.
+ * direction (1,048,576 bins).  A bin is trusted when it holds at least 32
+ * pairs and every one of them is within the bound: sum_c (L_c - ref_c)^2 <=
+ * max_rel_err^2 sum_c ref_c^2 + (0.01)^2 (an absolute floor of 0.01 radiance
+ * units for dark rays).  The bins of lines that no held-out pair met, or met
+ * fewer than 32 times, fall back.  Synchronises the stream.
  */
 lq_status lq_mlp_build_trust(lq_mlp *mlp, const float *origins, const float *dirs,
                              const float *rgb_ref, int64_t n, float max_rel_err, void *hip_stream);

@@ -697,17 +697,17 @@ __device__ inline void load_ray(const float *o, const float *d, int64_t ray, flo
 
 __device__ inline int64_t ray_of(const int64_t *index, int64_t pos) { return index ? index[pos] : pos; }
 
-// mode 0: radiance; mode 2: accumulate trust statistics against the
-// reference radiance (per bin: squared error and reference sums, pair count,
-// largest squared error of a pair; null arrays are skipped).  With an index list the kernel answers rays
+// mode 0: radiance; mode 2: trust statistics against the reference radiance
+// (per bin: pairs, and pairs whose squared error exceeds max_rel2 times the
+// squared reference plus abs_floor2).  With an index list the kernel answers rays
 // index[0 .. *n_dev) (the count read on the device), else rays 0 .. n.
 constexpr int kInfBlock = 512;               // inference block: eight waves share one copy of the weights
 constexpr int kInfWaves = kInfBlock / 64;
 
 __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_infer(
     const float *o, const float *d, int64_t n, const int64_t *index, const unsigned long long *n_dev,
-    const uint16_t *wlane, const float *bias, int mode, float *rgb, const float *ref, double *terr,
-    double *tref, unsigned *tcnt, unsigned long long *tmax) {
+    const uint16_t *wlane, const float *bias, int mode, float *rgb, const float *ref, unsigned *tcnt,
+    unsigned *tbad, float max_rel2, float abs_floor2) {
     __shared__ __align__(16) float sB[kBiasPad];
     for (int i = threadIdx.x; i < kBiasPad; i += blockDim.x) sB[i] = bias[i];
     __syncthreads();
@@ -811,11 +811,8 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
                         se += ((double)L[c] - rc) * ((double)L[c] - rc);
                         sr += rc * rc;
                     }
-                    if (terr) atomicAdd(terr + bin, se);
-                    if (tref) atomicAdd(tref + bin, sr);
                     atomicAdd(tcnt + bin, 1u);
-                    // a non-negative double orders like its bit pattern
-                    if (tmax) atomicMax(tmax + bin, (unsigned long long)__double_as_longlong(se));
+                    if (se > (double)max_rel2 * sr + (double)abs_floor2) atomicAdd(tbad + bin, 1u);
                 }
             } else {
                 rgb[3 * ray] = L[0];
@@ -888,67 +885,15 @@ __global__ __launch_bounds__(256) void k_classify(const float *o, const float *d
     }
 }
 
-// Calibrated trust map.  The held-out pairs are split: the first part gives
-// each bin the largest squared error m of any of its pairs, the second part
-// (independent of the first) measures, per bucket of m, the squared error its
-// rays would leave in the output if those bins were trusted.  Bins are then
-// trusted in increasing m for as long as the calibration part's accumulated
-// error stays within the bound on its total reference energy.  The bound is
-// on the aggregate error of the hybrid output, so absolute errors rank the
-// bins (dark bins with small errors go before bright ones with a small
-// relative error), and the largest error rather than the mean: the per-ray
-// errors are heavy tailed (a ray grazing a bright shell the network misses
-// can cost more than the whole budget), and a bin that showed one such ray
-// in the first part is likely to show more.  Buckets: half-octaves of m.
-constexpr int kCalBuckets = 128;
-constexpr int kCalBias = 80;          // bucket of m = 1 (m below 2^-39.5 shares bucket 1)
-constexpr double kCalMargin = 0.75;   // the calibration part is held to this fraction of the bound
+// Trust map: a bin is trusted when it holds at least kTrustMinPairs held-out
+// pairs and every one of them is within the bound.
+constexpr unsigned kTrustMinPairs = 32;
+constexpr float kTrustAbsFloor = 1e-2f;   // radiance units: dark rays pass with errors below this
 
-__device__ inline int cal_bucket(unsigned long long max_bits) {
-    const double m = __longlong_as_double((long long)max_bits);
-    if (!(m > 0.0)) return 0;
-    const int k = (int)floor(2.0 * log2(m)) + kCalBias;
-    return k < 1 ? 1 : (k >= kCalBuckets ? kCalBuckets - 1 : k);
-}
-
-// hist[k] (k < kCalBuckets): calibration-part squared error of the bins in
-// bucket k (bins with at least min_count first-part pairs); hist[kCalBuckets
-// + k]: their calibration pairs; hist[2 kCalBuckets]: the calibration part's
-// total squared reference.
-__global__ __launch_bounds__(256) void k_trust_hist(const unsigned long long *tmax, const unsigned *tcnt,
-                                                    const double *cerr, const double *cref, const unsigned *ccnt,
-                                                    unsigned min_count, double *hist) {
-    __shared__ double s_err[kCalBuckets], s_cnt[kCalBuckets], s_ref[256];
-    for (int k = threadIdx.x; k < kCalBuckets; k += blockDim.x) s_err[k] = s_cnt[k] = 0.0;
-    __syncthreads();
-    double ref = 0.0;
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < kTrustBins; b += gridDim.x * blockDim.x) {
-        ref += cref[b];
-        if (tcnt[b] < min_count || ccnt[b] == 0) continue;
-        const int k = cal_bucket(tmax[b]);
-        atomicAdd(&s_err[k], cerr[b]);
-        atomicAdd(&s_cnt[k], (double)ccnt[b]);
-    }
-    s_ref[threadIdx.x] = ref;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) s_ref[threadIdx.x] += s_ref[threadIdx.x + st];
-        __syncthreads();
-    }
-    for (int k = threadIdx.x; k < kCalBuckets; k += blockDim.x) {
-        if (s_cnt[k] > 0.0) {
-            atomicAdd(hist + k, s_err[k]);
-            atomicAdd(hist + kCalBuckets + k, s_cnt[k]);
-        }
-    }
-    if (threadIdx.x == 0) atomicAdd(hist + 2 * kCalBuckets, s_ref[0]);
-}
-
-__global__ void k_trust_finalize(const unsigned long long *tmax, const unsigned *tcnt, unsigned min_count, int kmax,
-                                 uint8_t *trust) {
+__global__ void k_trust_finalize(const unsigned *tcnt, const unsigned *tbad, uint8_t *trust) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= kTrustBins) return;
-    trust[b] = tcnt[b] >= min_count && cal_bucket(tmax[b]) <= kmax ? 1 : 0;
+    trust[b] = tcnt[b] >= kTrustMinPairs && tbad[b] == 0 ? 1 : 0;
 }
 
 __global__ void k_zero_bytes(unsigned char *p, size_t n) {
@@ -1268,8 +1213,7 @@ lq_status lq_mlp_forward(const lq_mlp *p, const float *o, const float *d, int64_
     if ((st = check_dev_ptr(rgb, n * 12, p->device, "rgb")) != LQ_OK) return st;
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, (hipStream_t)stream, o, d, n,
                        (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 0, rgb,
-                       (const float *)nullptr, (double *)nullptr, (double *)nullptr, (unsigned *)nullptr,
-                       (unsigned long long *)nullptr);
+                       (const float *)nullptr, (unsigned *)nullptr, (unsigned *)nullptr, 0.0f, 0.0f);
     e = hipGetLastError();
     return e == hipSuccess ? LQ_OK : mhip(e, "surrogate forward");
 }
@@ -1285,49 +1229,17 @@ lq_status lq_mlp_build_trust(lq_mlp *p, const float *o, const float *d, const fl
     if ((st = check_dev_ptr(d, n * 12, p->device, "dirs")) != LQ_OK) return st;
     if ((st = check_dev_ptr(rgb_ref, n * 12, p->device, "rgb_ref")) != LQ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    // first two thirds: per-bin statistics; last third: calibration
-    const int64_t n_cal = n / 3, n_bin = n - n_cal;
-    if (n_cal < 1) return mfail(LQ_ERR_INVALID_ARG, "at least 3 held-out pairs required");
-    // first part: largest squared error and pair count per bin; calibration
-    // part: squared error and reference sums and pair count per bin
-    const size_t bytes = (size_t)kTrustBins * (8 + 4) + (size_t)kTrustBins * (8 + 8 + 4) + (2 * kCalBuckets + 1) * 8;
+    const size_t bytes = (size_t)kTrustBins * 8;   // pair count and out-of-bound count per bin
     unsigned char *acc = nullptr;
     if ((e = hipMallocAsync((void **)&acc, bytes, s)) != hipSuccess) return mhip(e, "hipMallocAsync");
-    unsigned long long *tmax = reinterpret_cast<unsigned long long *>(acc);
-    double *cerr = reinterpret_cast<double *>(tmax + kTrustBins);
-    double *cref = cerr + kTrustBins;
-    double *hist = cref + kTrustBins;
-    unsigned *tcnt = reinterpret_cast<unsigned *>(hist + 2 * kCalBuckets + 1);
-    unsigned *ccnt = tcnt + kTrustBins;
-    constexpr unsigned kMinCount = 4;
+    unsigned *tcnt = reinterpret_cast<unsigned *>(acc);
+    unsigned *tbad = tcnt + kTrustBins;
     hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(256), 0, s, acc, bytes);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n_bin,
-                       (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 2,
-                       (float *)nullptr, rgb_ref, (double *)nullptr, (double *)nullptr, tcnt, tmax);
-    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o + 3 * n_bin, d + 3 * n_bin,
-                       n_cal, (const int64_t *)nullptr, (const unsigned long long *)nullptr, p->wlane, p->bias, 2,
-                       (float *)nullptr, rgb_ref + 3 * n_bin, cerr, cref, ccnt, (unsigned long long *)nullptr);
-    hipLaunchKernelGGL(k_trust_hist, dim3(256), dim3(256), 0, s, tmax, tcnt, cerr, cref, ccnt, kMinCount, hist);
-    std::vector<double> h(2 * kCalBuckets + 1);
+    hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, (const int64_t *)nullptr,
+                       (const unsigned long long *)nullptr, p->wlane, p->bias, 2, (float *)nullptr, rgb_ref, tcnt, tbad,
+                       max_rel_err * max_rel_err, kTrustAbsFloor * kTrustAbsFloor);
+    hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, tcnt, tbad, p->trust);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), hist, h.size() * 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    int kmax = -1;
-    if (e == hipSuccess) {
-        // trust buckets in increasing largest error while the calibration
-        // part's accumulated error stays within the (margined) bound
-        const double lim = kCalMargin * (double)max_rel_err;
-        const double budget = lim * lim * h[2 * kCalBuckets];
-        double cum = 0.0;
-        for (int k = 0; k < kCalBuckets; ++k) {
-            cum += h[k];
-            if (cum > budget) break;
-            kmax = k;
-        }
-        hipLaunchKernelGGL(k_trust_finalize, dim3((kTrustBins + 255) / 256), dim3(256), 0, s, tmax, tcnt,
-                           kMinCount, kmax, p->trust);
-        e = hipGetLastError();
-    }
     (void)hipFreeAsync(acc, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return mhip(e, "building the trust map");
@@ -1374,7 +1286,7 @@ lq_status lq_mlp_infer(const lq_mlp *p, const lq_octree *fallback, const float *
                        mlp_list, cnt, oct_list, cnt + 1);
     hipLaunchKernelGGL(k_infer, dim3(infer_grid(p->device)), dim3(kInfBlock), 0, s, o, d, n, mlp_list,
                        (const unsigned long long *)cnt, p->wlane, p->bias, 0, rgb, (const float *)nullptr,
-                       (double *)nullptr, (double *)nullptr, (unsigned *)nullptr, (unsigned long long *)nullptr);
+                       (unsigned *)nullptr, (unsigned *)nullptr, 0.0f, 0.0f);
     e = hipGetLastError();
     if (e == hipSuccess) {
         lq_status q = query_indexed(fallback, o, d, n, oct_list, cnt + 1, rgb, s);

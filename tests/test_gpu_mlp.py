@@ -207,10 +207,10 @@ def test_trust_map_and_fallback(lq, c0_tree):
     assert float((hit & ~u).float().mean()) < 0.01
     assert torch.equal(out[u], ref[u])
     assert bool((out[~hit] == 0).all())
-    # a loose bound: the bins with enough samples are trusted, those rays keep
+    # a loose bound: the bins with enough pairs are trusted, those rays keep
     # the surrogate's value (enough held-out rays to fill most bins they meet)
     _say("trust map, loose")
-    ho, hd, hrgb = _training_set(lq, oct_, 1 << 21, 42)
+    ho, hd, hrgb = _training_set(lq, oct_, 1 << 24, 42)
     sur.build_trust(ho, hd, hrgb, max_rel_err=1e9)
     tm = sur.trust_map()
     assert tm.sum() > 0
@@ -219,8 +219,9 @@ def test_trust_map_and_fallback(lq, c0_tree):
     u = used.bool()
     assert torch.equal(out[~u], plain[~u])
     assert torch.equal(out[u], ref[u])
-    # only rays in bins with fewer than 4 held-out pairs still fall back
-    assert float(u.float().mean()) < 0.9
+    # only rays in bins with fewer than 32 held-out pairs still fall back
+    # (most bins at this held-out size: 16.7M pairs spread over the bins)
+    assert float(u.float().mean()) < 0.97
 
 
 def test_multi_tree_query_matches_single(lq):
@@ -259,7 +260,7 @@ def test_trained_surrogate_serves_rays_the_untrained_cannot(lq, c0_tree):
     import torch
     oct_ = lq.Octree(c0_tree, "f32")
     o, d, rgb = _training_set(lq, oct_, 1 << 20, 50)
-    ho, hd, hrgb = _training_set(lq, oct_, 1 << 22, 51)
+    ho, hd, hrgb = _training_set(lq, oct_, 1 << 25, 51)
     qo, qd = _rays(1 << 18, 52)
     qo, qd = _dev(qo), _dev(qd)
     tr = oct_.trace(qo, qd)
