@@ -131,6 +131,29 @@ def test_plain_query_parity(lq, c0_tree, storage):
         assert err.max() < parity.RTOL, (storage, model, err.max())
 
 
+@pytest.mark.parametrize("deg", [0, 1, 2, 3, 4])
+def test_sh_degrees_parity(lq, deg):
+    """Every SH degree the library takes (0..4), each storage, both
+    transmittance models: trace records bit-exact and radiance within the
+    tolerance against the oracle, and the plain query equal to the trace
+    kernel's radiance."""
+    import torch
+    tree = inputs.random_tree(5, 0.35, seed=90 + deg, sh_degree=deg)
+    o, d = inputs.rays.sphere_to_cube(20000, 91 + deg)
+    for storage in ("f32", "f16", "bf16"):
+        oct_ = lq.Octree(tree, storage)
+        for model, m in (("linear", 0), ("exp", 1)):
+            _say(f"SH degree {deg} {storage} {model}")
+            g = _run_trace(oct_, o, d, model)
+            orc = core.query(tree, o, d, model=m, storage=storage)
+            rep = parity.compare(g, orc, tree.l_max)
+            assert rep["ok"], (deg, storage, model, rep)
+            rgb, _ = oct_.query(_dev(o), _dev(d), model=model)
+            torch.cuda.synchronize()
+            assert np.array_equal(rgb.cpu().numpy(), g["rgb"]), (deg, storage, model)
+        oct_.free()
+
+
 def test_empty_tree_and_misses(lq):
     import torch
     tree = inputs.empty_tree(4)
