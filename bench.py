@@ -211,6 +211,33 @@ def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
 UNEVEN_SURROGATE_STEPS = 5000
 
 
+def sh_sweep_variant(lumiq, o, d, steps):
+    """Cost of the SH degree and of the transmittance model: the depth-9
+    luminaire's geometry with SH degree 0..4 (one degree-4 tree, lower
+    degrees by keeping its first (l+1)^2 coefficients, so every degree sees
+    the same leaves), camera rays, float32 and float16 storage."""
+    import dataclasses
+    import inputs
+    t0 = time.perf_counter()
+    full = inputs.cached_tree(dataclasses.replace(inputs.C1_TREE, sh_degree=4))
+    log(f"SH sweep: degree-4 tree ready in {time.perf_counter() - t0:.1f} s")
+    out = {}
+    for deg in range(5):
+        K = (deg + 1) ** 2
+        tree = dataclasses.replace(full, sh_degree=deg, sh=full.sh[:, :, :K].copy())
+        for storage in ("f32", "f16"):
+            oc = lumiq.Octree(tree, storage)
+            rec = {}
+            for model in ("linear", "exp"):
+                ms, _ = time_launches(lambda: oc.query(o, d, model=model), steps, 2)
+                rec[f"{model}_ms"] = ms
+            rec["linear_speedup_over_exp"] = rec["exp_ms"] / rec["linear_ms"]
+            out[f"deg{deg}_{storage}"] = rec
+            log(f"SH sweep: degree {deg} {storage}: linear {rec['linear_ms']:.3f} ms, exp {rec['exp_ms']:.3f} ms")
+            oc.free()
+    return out
+
+
 def uneven_variant(lumiq):
     """The uneven multi-luminaire batch (16 trees of depth 6 to 10, SH degree
     3, float16, log-uniform ray counts): one persistent launch over all rays
@@ -300,6 +327,9 @@ def main():
     ap.add_argument("--surrogate-steps", type=int, default=20000,
                     help="optimiser steps of the surrogate (0: skip the surrogate variant)")
     ap.add_argument("--surrogate-pairs", type=int, default=50_000_000)
+    ap.add_argument("--sh-sweep", action="store_true",
+                    help="also time SH degrees 0..4 x linear/exponential on the depth-9 geometry "
+                         "(generates a degree-4 tree: a minute of CPU)")
     ap.add_argument("--uneven", action="store_true",
                     help="also run the uneven 16-luminaire batch (generates depth-10 trees: minutes of CPU)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -390,6 +420,9 @@ def main():
         if args.surrogate_steps > 0:
             variants["surrogate"] = surrogate_variant(args, lumiq, tree, oct32, ro_t, rd_t, rrgb)
         del ro_t, rd_t, rrgb, ralpha
+
+    if args.sh_sweep:
+        variants["sh_sweep_camera"] = sh_sweep_variant(lumiq, o, d, max(5, args.steps // 2))
 
     if args.uneven:
         variants["uneven_batch"] = uneven_variant(lumiq)

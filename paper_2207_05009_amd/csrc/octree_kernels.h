@@ -159,10 +159,21 @@ __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryAr
 // The plain query (float32 accumulation, no trace) with a register budget
 // for five waves per SIMD: it waits on dependent loads, and a fifth wave
 // hides more of that than the few values the budget moves out of registers
-// (spilled only on the path of rays that miss the box) cost.  The
-// validation variants keep the default budget, which they need.
+// (spilled only on the path of rays that miss the box) cost.  Larger leaf
+// rows (SH degree 3 and 4) hold more values per lane -- the row and the
+// (l+1)^2 basis values -- and get a budget for fewer waves instead of
+// spilling them.  The validation variants keep the default budget, which
+// they need.
+template <int ST, int DEG>
+constexpr int plain_waves_per_simd() {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int row_regs = ((1 + 3 * K) * Storage<ST>::bytes + 15) / 16 * 4;
+    return row_regs + K <= 40 ? 5 : (row_regs + K <= 70 ? 4 : 3);
+}
+
 template <int ST, int DEG, bool SKIP, int MODEL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_query_plain(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(plain_waves_per_simd<ST, DEG>())))
+void k_query_plain(
     const DevTree t, const QueryArgs a, unsigned long long *queue) {
     persistent_query<ST, DEG, false, false, SKIP, true, MODEL>(
         a, queue, [](int64_t) { return 0; }, [&](int) -> const DevTree & { return t; });
