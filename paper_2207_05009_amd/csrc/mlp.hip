@@ -17,7 +17,8 @@
 //   bias gradients are row sums.  Each workgroup writes one partial gradient
 //   row.
 //   k_reduce_adam: sums the rows in a fixed order (deterministic), applies
-//   Adam to the float32 master weights and refreshes the bfloat16 image.
+//   Adam to the float32 master weights and scatters them to the bfloat16
+//   lane-ordered copy the kernels stage.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
