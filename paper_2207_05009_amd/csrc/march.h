@@ -232,7 +232,7 @@ LQ_HD inline int cross_cmp(const Ray &r, int a, float Pa, float ta, int b, float
     if (r.filter_ok) {
         float df = ta - tb;
         float bound = fmaf(kFilterRel, fabsf(ta) + fabsf(tb), kFilterAbs);
-        if (fabsf(df) > bound) return df > 0.0f ? 1 : -1;
+        if (__builtin_expect(fabsf(df) > bound, 1)) return df > 0.0f ? 1 : -1;
     }
     return cross_cmp_exact(Pa, sel3(r.o, a), sel3(r.d, a), Pb, sel3(r.o, b), sel3(r.d, b));
 }
@@ -394,7 +394,7 @@ struct Marcher {
         }
         dlen = sqrtf(r.d[0] * r.d[0] + r.d[1] * r.d[1] + r.d[2] * r.d[2]);
         ok = ok && anyd && dlen > 0.0f && isfinite(dlen);
-        if (!ok) return false;
+        if (__builtin_expect(!ok, 0)) return false;
 
         // ---- clip to the proxy box [-1, 1)^3
         int in_ax = -1;
@@ -428,7 +428,7 @@ struct Marcher {
                 ok = ok && cmp_event(r, ax, Pf, ev) > 0;
             }
         }
-        if (!ok) return false;
+        if (__builtin_expect(!ok, 0)) return false;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             float dx = r.d[ax], ox = r.o[ax];
@@ -474,7 +474,7 @@ struct Marcher {
         const int N = 1 << D;
         const float h = 2.0f / (float)N;
         const int32_t *child = SKIP ? t.child_skip : t.child;
-        if (--steps_left < 0) return true;
+        if (__builtin_expect(--steps_left < 0, 0)) return true;
 
         int node = 0, level = 0, c = 0;
         if (path_top >= 0) {
@@ -573,7 +573,7 @@ struct Marcher {
                 }
             }
         }
-        if (!fast) {
+        if (__builtin_expect(!fast, 0)) {
             xa = -1;
             xmask = 0;
 #pragma unroll
@@ -669,7 +669,7 @@ struct Marcher {
                 }
             }
         }
-        if (leave) return true;
+        if (__builtin_expect(leave, 0)) return true;
         qdiff = (uint32_t)((q[0] ^ nq[0]) | (q[1] ^ nq[1]) | (q[2] ^ nq[2]));
         q[0] = nq[0]; q[1] = nq[1]; q[2] = nq[2];
         ev = nev;
