@@ -100,7 +100,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         bool want = ray < 0 && used_up != kAllRanges;
         uint64_t need = __ballot(want);
         const int busy = __popcll(__ballot(ray >= 0));
-        if (need && busy < kRefillBelow) {
+        if (__builtin_expect(need && busy < kRefillBelow, 0)) {
             for (int tries = 0; need && tries < kXcds; ++tries) {
                 const int cnt = __popcll(need);
                 const int leader = __ffsll((unsigned long long)need) - 1;
@@ -139,7 +139,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         if (__all(ray < 0 && used_up == kAllRanges)) break;
         for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
             const DevTree &tr = tree_at(tk);
-            if (m.step(tr, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock, top_of(tr))) {
+            if (__builtin_expect(m.step(tr, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock, top_of(tr)), 0)) {
                 write_ray(a, ray, m, TRACE);
                 ray = -1;
             }
