@@ -229,7 +229,7 @@ def sh_sweep_variant(lumiq, o, d, steps):
             oc = lumiq.Octree(tree, storage)
             rec = {}
             for model in ("linear", "exp"):
-                ms, _ = time_launches(lambda: oc.query(o, d, model=model), steps, 2)
+                ms, _ = time_launches(lambda: oc.query_image(o, d, 2048, 2048, model=model), steps, 2)
                 rec[f"{model}_ms"] = ms
             rec["linear_speedup_over_exp"] = rec["exp_ms"] / rec["linear_ms"]
             out[f"deg{deg}_{storage}"] = rec
@@ -363,8 +363,10 @@ def main():
     oct32 = lumiq.Octree(tree, "f32")
     log(f"tree uploaded: {oct32.info()}")
 
+    # the camera batch goes through the camera-batch entry point (rays taken
+    # up in 8x8 pixel tiles; results bit-identical to the batch-order query)
     def step():
-        oct32.query(o, d, model="linear", rgb=rgb, alpha=alpha)
+        oct32.query_image(o, d, 2048, 2048, model="linear", rgb=rgb, alpha=alpha)
 
     ms, wall = time_launches(step, args.steps, args.warmup)
     value = n / (ms * 1e-3)
@@ -387,21 +389,26 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": nbytes, "per_ray": counts,
-                "kernel": "k_query_plain<F32, SH deg 2, sigma_min-pruned table, linear>",
+                "kernel": "k_query_plain<F32, SH deg 2, sigma_min-pruned table, linear, 8x8 pixel tiles>",
                 "kernel_sources": kernel_sources_hash()}
 
     variants = {}
     if not args.no_variants:
         for storage in ("f16", "bf16"):
             oc = lumiq.Octree(tree, storage)
-            vms, _ = time_launches(lambda: oc.query(o, d, model="linear", rgb=rgb, alpha=alpha),
+            vms, _ = time_launches(lambda: oc.query_image(o, d, 2048, 2048, model="linear", rgb=rgb, alpha=alpha),
                                    max(5, args.steps // 2), 2)
             variants[f"camera_{storage}_linear"] = variant_record(oc, o, d, "linear", tree.K, 2, vms)
             log(f"{storage}: {vms:.3f} ms/step")
             oc.free()
-        vms, _ = time_launches(lambda: oct32.query(o, d, model="exp", rgb=rgb, alpha=alpha),
+        vms, _ = time_launches(lambda: oct32.query_image(o, d, 2048, 2048, model="exp", rgb=rgb, alpha=alpha),
                                max(5, args.steps // 2), 2)
         variants["camera_f32_exp"] = variant_record(oct32, o, d, "exp", tree.K, 4, vms)
+        # the same camera batch through the batch-order entry point (row by row)
+        vms, _ = time_launches(lambda: oct32.query(o, d, model="linear", rgb=rgb, alpha=alpha),
+                               max(5, args.steps // 2), 2)
+        variants["camera_f32_linear_row_order"] = variant_record(oct32, o, d, "linear", tree.K, 4, vms)
+        log(f"f32 linear, row order: {vms:.3f} ms/step")
         # incoherent shading queries from a room around the luminaire
         ro, rd = inputs.rays.room_to_proxy(1 << 24, 20)
         ro_t, rd_t = torch.from_numpy(ro).cuda(), torch.from_numpy(rd).cuda()
@@ -439,7 +446,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "depth-9 synthetic luminaire plenoctree (512^3, SH degree 2, "
-                               "float32) x 2048x2048 pinhole camera rays, linear transmittance",
+                               "float32) x 2048x2048 pinhole camera rays (one image, row-major), "
+                               "linear transmittance",
                    "rays": n, "n_leaves": tree.n_leaves, "n_nodes": tree.n_nodes,
                    "sh_degree": tree.sh_degree, "storage": "f32", "transmittance": "linear",
                    "sigma_min": 0.1, "alpha_max": 0.9},

@@ -126,6 +126,22 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
                             void *hip_stream);
 
 /*
+ * Camera batch: the query of lq_query_radiance over the width * height rays
+ * of an image stored row-major (ray y * width + x belongs to pixel (x, y)),
+ * e.g. the primary rays of a rendered frame.  The results are those of
+ * lq_query_radiance on the same arrays, ray for ray and bit for bit; only
+ * the order in which the device takes the rays up differs: 8 x 8 pixel tiles
+ * (the columns and rows beyond the last whole tile after them), so that the
+ * 64 lanes of a wave march neighbouring pixels, which cross mostly the same
+ * octree nodes.  Arrays hold width * height rays; width * height = 0 is a
+ * no-op.  Errors: those of lq_query_radiance, and LQ_ERR_INVALID_ARG for a
+ * negative width or height or width * height >= 2^31.
+ */
+lq_status lq_query_radiance_image(const lq_octree *tree, const float *origins, const float *dirs,
+                                  int32_t width, int32_t height, float *rgb, float *alpha,
+                                  int model, uint32_t flags, void *hip_stream);
+
+/*
  * Validation variant of lq_query_radiance: same traversal and compositing,
  * plus per-ray records of the visited data leaves.  For each ray:
  *   count[i]     data leaves visited, up to and including the stop leaf;

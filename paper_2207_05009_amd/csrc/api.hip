@@ -467,6 +467,25 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
     return query_common(tree, a, false, hip_stream);
 }
 
+lq_status lq_query_radiance_image(const lq_octree *tree, const float *origins, const float *dirs, int32_t width,
+                                  int32_t height, float *rgb, float *alpha, int model, uint32_t flags,
+                                  void *hip_stream) {
+    if (width < 0 || height < 0) return fail(LQ_ERR_INVALID_ARG, "width and height must be >= 0");
+    const int64_t n = (int64_t)width * height;
+    if (n > INT32_MAX) return fail(LQ_ERR_INVALID_ARG, "width * height must be < 2^31");
+    QueryArgs a{};
+    a.o = origins;
+    a.d = dirs;
+    a.n = n;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.model = model;
+    a.flags = flags;
+    a.img_w = (uint32_t)width;
+    a.img_h = (uint32_t)height;
+    return query_common(tree, a, false, hip_stream);
+}
+
 lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees, const int64_t *ray_offsets,
                                   const float *origins, const float *dirs, float *rgb, float *alpha, int model,
                                   uint32_t flags, void *hip_stream) {

@@ -58,7 +58,34 @@ struct QueryArgs {
     // the launch covers *n_dev rays when n_dev is set (n is then a bound)
     const int64_t *index;
     const unsigned long long *n_dev;
+    // camera batch: when img_w > 0 the n = img_w * img_h rays are the pixels
+    // of a row-major image and the waves take them up in 8 x 8 pixel tiles
+    // (tile_order_pixel); excludes index
+    uint32_t img_w, img_h;
 };
+
+// Pixel taken up at position v (< w h) of a camera batch's tile order, a
+// bijection of [0, w h): whole 8 x 8 tiles first, tile by tile along each
+// band of 8 rows (a tile row-major inside), then the pixels right of the
+// last whole tile of each band, then the rows below the last whole band,
+// both row-major.  A wave's 64 lanes thus take one tile: neighbouring
+// pixels, whose rays cross mostly the same octree nodes.  w h < 2^32.
+__host__ __device__ inline uint32_t tile_order_pixel(uint32_t v, uint32_t w, uint32_t h) {
+    const uint32_t w8 = w & ~7u, h8 = h & ~7u;   // columns and rows of whole tiles
+    const uint32_t n_tiled = h8 * w8;
+    if (v < n_tiled) {                           // then w8 >= 8
+        const uint32_t band = v / (8u * w8), j = v - band * (8u * w8);
+        const uint32_t p = j & 63u;
+        return (band * 8u + (p >> 3)) * w + (j >> 6) * 8u + (p & 7u);
+    }
+    v -= n_tiled;
+    const uint32_t ws = w - w8, n_side = h8 * ws;
+    if (v < n_side) {                            // then ws >= 1
+        const uint32_t r = v / ws;
+        return r * w + w8 + (v - r * ws);
+    }
+    return h8 * w + (v - n_side);
+}
 
 // launch the emission query; returns hipSuccess or the launch error
 hipError_t launch_query(const DevTree &t, const QueryArgs &a, bool trace, hipStream_t s);

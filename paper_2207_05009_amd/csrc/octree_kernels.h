@@ -18,6 +18,11 @@
 // L2 sees are neighbours in the batch (for a camera, a band of image rows),
 // not every kXcds-th chunk.  A wave whose range is used up continues on the
 // next ranges, so the tail stays balanced.
+//
+// Camera batches are split by position in their tile order instead
+// (tile_order_pixel): the 64 rays one refill hands a wave then form an 8 x 8
+// pixel tile rather than a 1 x 64 strip of a row, so the lanes of a wave
+// descend through mostly the same nodes and read mostly the same leaf rows.
 #include <mutex>
 #include <unordered_map>
 
@@ -67,8 +72,13 @@ __device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; 
 // tree_index(ray) finds the tree a ray queries (once, when a lane takes the
 // ray) and tree_at(k) returns tree k.  With TOP_LDS (one tree)
 // the block copies the tree's top grid into LDS; otherwise each ray reads
-// its tree's grid from global memory.
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, int MODEL, class TreeIndex,
+// its tree's grid from global memory.  ORDER maps a position of the split
+// to a ray: kOrderAny takes a.index, then the image tile order, then the
+// position itself, whichever the arguments set; kOrderBatch only a.index or
+// the position; kOrderTiles only the tile order.
+enum { kOrderAny = 0, kOrderBatch = 1, kOrderTiles = 2 };
+
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, bool TOP_LDS, int MODEL, int ORDER, class TreeIndex,
           class TreeAt>
 __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *queue, TreeIndex tree_index,
                                         TreeAt tree_at) {
@@ -114,7 +124,14 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
                 if (want) {
                     const int64_t slot = (int64_t)base + __popcll(need & lanemask_lt());
                     if (slot < len) {
-                        const int64_t idx = a.index ? a.index[start + slot] : start + slot;
+                        const int64_t pos = start + slot;
+                        int64_t idx = pos;
+                        if constexpr (ORDER == kOrderTiles) {
+                            idx = tile_order_pixel((uint32_t)pos, a.img_w, a.img_h);
+                        } else {
+                            if (a.index) idx = a.index[pos];
+                            else if (ORDER == kOrderAny && a.img_w) idx = tile_order_pixel((uint32_t)pos, a.img_w, a.img_h);
+                        }
                         ids = TRACE && a.max_ids > 0 ? a.leaf_ids + (size_t)idx * a.max_ids : nullptr;
                         tk = tree_index(idx);
                         if (m.init(tree_at(tk), a.o + 3 * idx, a.d + 3 * idx)) {
@@ -152,7 +169,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
 template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL>
 __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryArgs a,
                                                   unsigned long long *queue) {
-    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true, MODEL>(
+    persistent_query<ST, DEG, ACC64, TRACE, SKIP, true, MODEL, kOrderAny>(
         a, queue, [](int64_t) { return 0; }, [&](int) -> const DevTree & { return t; });
 }
 
@@ -163,7 +180,9 @@ __global__ __launch_bounds__(kBlock) void k_query(const DevTree t, const QueryAr
 // rows (SH degree 3 and 4) hold more values per lane -- the row and the
 // (l+1)^2 basis values -- and get a budget for fewer waves instead of
 // spilling them.  The validation variants keep the default budget, which
-// they need.
+// they need.  The kernels for one transmittance model take rays in batch
+// order or, with TILES, in the tile order of a camera batch; the
+// model-generic one (the validation flags) in whichever the arguments give.
 template <int ST, int DEG>
 constexpr int plain_waves_per_simd() {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -171,17 +190,18 @@ constexpr int plain_waves_per_simd() {
     return row_regs + K <= 40 ? 5 : (row_regs + K <= 70 ? 4 : 3);
 }
 
-template <int ST, int DEG, bool SKIP, int MODEL>
+template <int ST, int DEG, bool SKIP, int MODEL, bool TILES>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(plain_waves_per_simd<ST, DEG>())))
 void k_query_plain(
     const DevTree t, const QueryArgs a, unsigned long long *queue) {
-    persistent_query<ST, DEG, false, false, SKIP, true, MODEL>(
+    constexpr int order = TILES ? kOrderTiles : (MODEL < 0 ? kOrderAny : kOrderBatch);
+    persistent_query<ST, DEG, false, false, SKIP, true, MODEL, order>(
         a, queue, [](int64_t) { return 0; }, [&](int) -> const DevTree & { return t; });
 }
 
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL>
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL, bool TILES>
 constexpr auto query_kernel() {
-    if constexpr (!ACC64 && !TRACE) return k_query_plain<ST, DEG, SKIP, MODEL>;
+    if constexpr (!ACC64 && !TRACE) return k_query_plain<ST, DEG, SKIP, MODEL, TILES>;
     else return k_query<ST, DEG, ACC64, TRACE, SKIP, MODEL>;
 }
 
@@ -202,7 +222,7 @@ __device__ inline void multi_query(const DevTree *trees, const int64_t *offsets,
         }
         return lo;
     };
-    persistent_query<ST, DEG, ACC64, false, SKIP, false, MODEL>(
+    persistent_query<ST, DEG, ACC64, false, SKIP, false, MODEL, kOrderBatch>(
         a, queue, tree_index, [&](int k) -> const DevTree & { return trees[k]; });
 }
 
@@ -242,9 +262,9 @@ int resident_blocks(Kern kern) {
     return nb;
 }
 
-template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL = -1>
+template <int ST, int DEG, bool ACC64, bool TRACE, bool SKIP, int MODEL = -1, bool TILES = false>
 hipError_t launch_one(const DevTree &t, const QueryArgs &a, hipStream_t s) {
-    auto kern = query_kernel<ST, DEG, ACC64, TRACE, SKIP, MODEL>();
+    auto kern = query_kernel<ST, DEG, ACC64, TRACE, SKIP, MODEL, TILES>();
     const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
     const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
     unsigned long long *queue = nullptr;
@@ -268,6 +288,10 @@ hipError_t launch_deg(const DevTree &t, const QueryArgs &a, bool trace, hipStrea
     if (full) return acc64 ? launch_one<ST, DEG, true, false, false>(t, a, s)
                            : launch_one<ST, DEG, false, false, false>(t, a, s);
     if (acc64) return launch_one<ST, DEG, true, false, true>(t, a, s);
+    // the plain kernels of camera batches have the tile order built in
+    if (a.img_w)
+        return a.model == LQ_EXP ? launch_one<ST, DEG, false, false, true, LQ_EXP, true>(t, a, s)
+                                 : launch_one<ST, DEG, false, false, true, LQ_LINEAR, true>(t, a, s);
     return a.model == LQ_EXP ? launch_one<ST, DEG, false, false, true, LQ_EXP>(t, a, s)
                              : launch_one<ST, DEG, false, false, true, LQ_LINEAR>(t, a, s);
 }

@@ -62,8 +62,9 @@ def lib():
             L.lq_query_radiance.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32, vp]
             L.lq_query_trace.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32,
                                          vp, vp, vp, vp, vp, vp, i32, vp]
+            L.lq_query_radiance_image.argtypes = [vp, vp, vp, i32, i32, vp, vp, C.c_int, u32, vp]
             for name in ("lq_load_octree_desc", "lq_load_octree", "lq_octree_info",
-                         "lq_query_radiance", "lq_query_trace"):
+                         "lq_query_radiance", "lq_query_trace", "lq_query_radiance_image"):
                 getattr(L, name).restype = C.c_int
             _lib = L
     return _lib
@@ -138,6 +139,24 @@ class Octree:
             alpha = torch.empty((n,), dtype=torch.float32, device=origins.device)
         check(lib().lq_query_radiance(self.handle, _ptr(origins), _ptr(dirs), n, _ptr(rgb),
                                       _ptr(alpha), MODEL[model], flags, _stream(stream)))
+        return rgb, alpha
+
+    def query_image(self, origins, dirs, width: int, height: int, model: str = "linear",
+                    flags: int = 0, rgb=None, alpha=None, want_alpha: bool = True, stream=None):
+        """Emission query of a camera batch: origins/dirs float32 [height * width, 3]
+        CUDA tensors in row-major pixel order.  Same results as query(); the
+        device takes the rays up in 8 x 8 pixel tiles.  Returns (rgb, alpha)."""
+        import torch
+        n = width * height
+        if origins.shape[0] != n or dirs.shape[0] != n:
+            raise ValueError(f"expected {n} rays for a {width} x {height} image")
+        if rgb is None:
+            rgb = torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+        if alpha is None and want_alpha:
+            alpha = torch.empty((n,), dtype=torch.float32, device=origins.device)
+        check(lib().lq_query_radiance_image(self.handle, _ptr(origins), _ptr(dirs), width, height,
+                                            _ptr(rgb), _ptr(alpha), MODEL[model], flags,
+                                            _stream(stream)))
         return rgb, alpha
 
     def trace(self, origins, dirs, model: str = "linear", flags: int = 0, max_ids: int = 0,

@@ -117,3 +117,12 @@ def test_no_device_is_reported(L):
 def test_query_argument_errors(L):
     assert L.lq_query_radiance(None, None, None, 4, None, None, 0, 0, None) == -1
     assert b"tree" in L.lq_last_error()
+
+
+def test_image_query_argument_errors(L):
+    assert L.lq_query_radiance_image(None, None, None, -1, 4, None, None, 0, 0, None) == -1
+    assert b"width" in L.lq_last_error()
+    assert L.lq_query_radiance_image(None, None, None, 65536, 32768, None, None, 0, 0, None) == -1
+    assert b"2^31" in L.lq_last_error()
+    assert L.lq_query_radiance_image(None, None, None, 4, 4, None, None, 0, 0, None) == -1
+    assert b"tree" in L.lq_last_error()

@@ -253,6 +253,45 @@ def test_full_size_camera_sampled_parity(lq, c1_tree):
     assert np.all(out["rgb"] <= c1_tree.l_max * out["alpha"][:, None] * (1 + 1e-5) + 1e-6)
 
 
+@pytest.mark.parametrize("wh", [(1, 1), (7, 5), (8, 8), (13, 11), (64, 3), (3, 64), (100, 37), (517, 259)])
+def test_camera_batch_order_is_bit_identical(lq, c0_tree, wh):
+    """The camera-batch entry point takes rays up in 8x8 pixel tiles (then
+    the columns and rows beyond the last whole tile); each ray's result is
+    that of the batch-order query: every pixel written once, bit-identical,
+    whatever the image's remainder modulo 8 and whatever the flags."""
+    import torch
+    w, h = wh
+    o, d = inputs.rays.pinhole(w, h)
+    _say(f"camera batch order, {w}x{h}")
+    oct_ = lq.Octree(c0_tree, "f32")
+    O, D = _dev(o), _dev(d)
+    for model in ("linear", "exp"):
+        for flags in (0, lq.LQ_NO_EARLY_TERM, lq.LQ_NO_SIGMA_SKIP, lq.LQ_FP64_ACCUM):
+            ref_rgb, ref_alpha = oct_.query(O, D, model=model, flags=flags)
+            rgb = torch.full((w * h, 3), float("nan"), device="cuda")
+            alpha = torch.full((w * h,), float("nan"), device="cuda")
+            oct_.query_image(O, D, w, h, model=model, flags=flags, rgb=rgb, alpha=alpha)
+            torch.cuda.synchronize()
+            assert torch.equal(rgb, ref_rgb) and torch.equal(alpha, ref_alpha), (model, flags)
+    e = torch.empty((0, 3), device="cuda")
+    assert oct_.query_image(e, e, 0, 5)[0].shape == (0, 3)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_full_size_camera_batch_order(lq, c1_tree, storage):
+    """The 2048x2048 camera batch through the camera-batch entry point:
+    bit-identical to the batch-order query on every ray."""
+    import torch
+    o, d = inputs.rays.pinhole(2048, 2048)
+    _say(f"full-size camera batch in tile order, {storage}")
+    oct_ = lq.Octree(c1_tree, storage)
+    O, D = _dev(o), _dev(d)
+    ref_rgb, ref_alpha = oct_.query(O, D)
+    rgb, alpha = oct_.query_image(O, D, 2048, 2048)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, ref_rgb) and torch.equal(alpha, ref_alpha)
+
+
 def test_abi_rejects_bad_pointers(lq, c0_tree):
     import ctypes as C
     import torch
