@@ -38,6 +38,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRefillBelow = 32;     // refill when fewer lanes of a wave are busy
 constexpr int kStepsPerCheck = 16;   // steps between refill checks
+// the same for camera batches in tile order, whose rays in a wave (one
+// pixel tile) end at similar steps: fewer checks pay more than early refills
+constexpr int kTileRefillBelow = 16;
+constexpr int kTileStepsPerCheck = 32;
 constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
 static_assert(kXcds >= 1 && kXcds <= 31, "one bit per range in a 32-bit mask");
 constexpr unsigned kAllRanges = (1u << kXcds) - 1u;   // every range used up
@@ -99,6 +103,8 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         if constexpr (TOP_LDS) return top_lds;
         return SKIP ? t.top_skip : t.top;
     };
+    constexpr int refill_below = ORDER == kOrderTiles ? kTileRefillBelow : kRefillBelow;
+    constexpr int steps_per_check = ORDER == kOrderTiles ? kTileStepsPerCheck : kStepsPerCheck;
     Marcher<ST, DEG, ACC64, TRACE, SKIP, MODEL> m;
     int64_t ray = -1;            // ray held by this lane, -1 when idle
     int tk = 0;                  // tree of that ray
@@ -110,7 +116,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
         bool want = ray < 0 && used_up != kAllRanges;
         uint64_t need = __ballot(want);
         const int busy = __popcll(__ballot(ray >= 0));
-        if (__builtin_expect(need && busy < kRefillBelow, 0)) {
+        if (__builtin_expect(need && busy < refill_below, 0)) {
             for (int tries = 0; need && tries < kXcds; ++tries) {
                 const int cnt = __popcll(need);
                 const int leader = __ffsll((unsigned long long)need) - 1;
@@ -154,7 +160,7 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
             }
         }
         if (__all(ray < 0 && used_up == kAllRanges)) break;
-        for (int k = 0; k < kStepsPerCheck && ray >= 0; ++k) {
+        for (int k = 0; k < steps_per_check && ray >= 0; ++k) {
             const DevTree &tr = tree_at(tk);
             if (__builtin_expect(m.step(tr, a.model, a.flags, ids, TRACE ? a.max_ids : 0, path, kBlock, top_of(tr)), 0)) {
                 write_ray(a, ray, m, TRACE);

@@ -234,7 +234,7 @@ def test_full_size_camera_sampled_parity(lq, c1_tree):
     _say(f"full-size camera batch: {len(o)} rays, {c1_tree.n_leaves} leaves")
     oct_ = lq.Octree(c1_tree, "f32")
     out = parity.to_numpy(oct_.trace(_dev(o), _dev(d), model="linear"))
-    rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")     # the timed entry point
+    rgb, alpha = oct_.query_image(_dev(o), _dev(d), 2048, 2048, model="linear")   # the timed entry point
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(7).choice(len(o), 20000, replace=False))
     orc = core.query(c1_tree, o[idx], d[idx], model=0)
@@ -336,7 +336,10 @@ def test_full_size_error_against_oracle(lq, c1_tree, full_rays, workload, storag
     o, d = full_rays[workload]
     _say(f"full-size {workload} batch, {len(o)} rays, storage {storage}")
     oct_ = lq.Octree(c1_tree, storage)
-    rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")
+    if workload == "camera":   # one 2048x2048 image: the camera-batch entry point
+        rgb, alpha = oct_.query_image(_dev(o), _dev(d), 2048, 2048, model="linear")
+    else:
+        rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(11).choice(len(o), 20000, replace=False))
     g_rgb = rgb.cpu().numpy()[idx].astype(np.float64)
