@@ -157,3 +157,35 @@ def adversarial(depth: int, seed: int, n: int = 512):
     o = np.ascontiguousarray(np.array(O, dtype=np.float32))
     d = np.ascontiguousarray(np.array(D, dtype=np.float32))
     return o, d
+
+
+def floor_points(nx: int, ny: int, z: float = -1.5, half: float = 5.0):
+    """Shading points on the floor of the room around the luminaire: an
+    nx x ny grid of cell centres on [-half, half]^2 at height z, normal +z
+    (row-major, x fastest)."""
+    xs = (np.arange(nx, dtype=np.float64) + 0.5) / nx * 2.0 * half - half
+    ys = (np.arange(ny, dtype=np.float64) + 0.5) / ny * 2.0 * half - half
+    yy, xx = np.meshgrid(ys, xs, indexing="ij")
+    p = np.stack([xx.ravel(), yy.ravel(), np.full(nx * ny, z)], axis=1).astype(np.float32)
+    nrm = np.zeros_like(p)
+    nrm[:, 2] = 1.0
+    return np.ascontiguousarray(p), nrm
+
+
+def scattered_points(n: int, seed: int, radius=(1.2, 6.0)):
+    """Shading points outside the proxy box, at distances in `radius` from
+    the origin in uniform directions, each with a normal toward the origin
+    tilted by up to ~35 degrees (some samples then fall below the tangent
+    plane)."""
+    rng = np.random.default_rng(seed)
+    p = _uniform_sphere(rng, n) * rng.uniform(radius[0], radius[1], size=(n, 1))
+    out = np.abs(p).max(axis=1) <= 1.05             # keep every point outside the box
+    p[out] *= 1.2 / np.abs(p[out]).max(axis=1, keepdims=True)
+    nrm = -p / np.linalg.norm(p, axis=1, keepdims=True) + rng.normal(0, 0.35, size=(n, 3))
+    return p.astype(np.float32), nrm.astype(np.float32)
+
+
+def sample_numbers(n: int, samples: int, seed: int):
+    """Uniform numbers in [0, 1) for the proxy samples, [n, samples, 3] float32."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n, samples, 3), dtype=np.float32)

@@ -1,0 +1,89 @@
+"""FP64 oracle of the consumer side of the emission query (test
+infrastructure only: tests/, the smoke check and the benchmark's CPU leg use
+it; the GPU library never does).
+
+Irradiance at a shading point x with normal n from the light that leaves the
+luminaire's proxy box toward x.  The radiance leaving the proxy along a ray
+is the luminaire's emission plus the scene light seen through it, weighted
+by the ray's transparency (Sec. 3, Eq. 2): L_o = L_e + (1 - alpha) L_b,
+where alpha is the opacity the query returns (Sec. 4.1, Eq. 5) and L_b the
+radiance behind the luminaire (here one constant colour).  The proxy is
+sampled uniformly over its surface (Sec. 6, Sampling): the box [-1,1]^3 has
+six faces of area 4, so a sample picks face f = floor(6 u0) and the point
+(2 u1 - 1, 2 u2 - 1) on it, with area density p_A = 1/24.  A sample on a
+face that x does not see from the front, or below x's tangent plane,
+contributes 0; otherwise its Monte Carlo term is
+
+    L_o(x <- y) cos(theta_x) cos(theta_y) / (|y - x|^2 p_A),
+
+and the estimate is the mean of the terms over a point's samples.  Every
+direction toward the box meets exactly one front-facing face point, so the
+estimate is unbiased for the irradiance (the integral of L_o cos(theta_x)
+over the box's solid angle).  A Lambertian surface of albedo rho then
+reflects rho / pi times it.
+
+The sample ray is built in float32 with the operations the definition
+lists (the query's inputs are float32): y as above, d = y - x per
+component; the weight and the sum are FP64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import core
+
+P_AREA = 1.0 / 24.0
+
+
+def proxy_rays(points, normals, u):
+    """Rays and weights of the samples.  points, normals: [n, 3]; u: [n, S, 3]
+    in [0, 1).  Returns o, d (float32 [n S, 3]) and w (float64 [n S]); the
+    direction of a zero-weight sample is zeroed (the query returns 0 for it)."""
+    x = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
+    nrm = np.asarray(normals, np.float64).reshape(-1, 3)
+    u = np.ascontiguousarray(u, np.float32)
+    n, S = u.shape[0], u.shape[1]
+    u = u.reshape(n * S, 3)
+    f = np.clip((u[:, 0] * np.float32(6.0)).astype(np.int32), 0, 5)
+    axis = f >> 1
+    sgn = np.where(f & 1, np.float32(1.0), np.float32(-1.0)).astype(np.float32)
+    a = u[:, 1] * np.float32(2.0) - np.float32(1.0)
+    b = u[:, 2] * np.float32(2.0) - np.float32(1.0)
+    y = np.empty((n * S, 3), np.float32)
+    rows = np.arange(n * S)
+    y[rows, axis] = sgn
+    y[rows, (axis + 1) % 3] = a
+    y[rows, (axis + 2) % 3] = b
+    xs = np.repeat(x, S, axis=0)
+    d = (y - xs).astype(np.float32)
+    # weights in FP64 from the float32 geometry
+    d64 = d.astype(np.float64)
+    dist2 = np.einsum("ij,ij->i", d64, d64)
+    dist = np.sqrt(dist2)
+    ns = np.repeat(nrm, S, axis=0)
+    nlen = np.linalg.norm(ns, axis=1)
+    cos_x = np.einsum("ij,ij->i", ns, d64) / np.where(nlen * dist > 0, nlen * dist, 1.0)
+    h = sgn.astype(np.float64) * xs.astype(np.float64)[rows, axis] - 1.0   # x in front of the face plane
+    cos_y = h / np.where(dist > 0, dist, 1.0)
+    ok = (h > 0) & (cos_x > 0) & (dist2 > 0) & (nlen > 0)
+    w = np.where(ok, cos_x * cos_y / np.where(dist2 > 0, dist2, 1.0) / P_AREA, 0.0)
+    d[~ok] = 0.0
+    return xs, d, w
+
+
+def proxy_irradiance(tree, points, normals, u, background=(0.0, 0.0, 0.0), model: int = core.LINEAR,
+                     storage: str = "f32") -> dict:
+    """Irradiance estimate per point (E [n, 3]) and the Monte Carlo terms
+    (terms [n, S, 3]); terms_alt uses the query's alternative candidate
+    where the oracle marks a ray threshold-ambiguous (alt_valid)."""
+    u = np.asarray(u, np.float32)
+    n, S = u.shape[0], u.shape[1]
+    o, d, w = proxy_rays(points, normals, u)
+    q = core.query(tree, o, d, model=model, storage=storage)
+    B = np.asarray(background, np.float64)[None, :]
+    lo = q["L"] + (1.0 - q["alpha"])[:, None] * B
+    lo_alt = q["alt_L"] + (1.0 - q["alt_alpha"])[:, None] * B
+    terms = (w[:, None] * lo).reshape(n, S, 3)
+    terms_alt = (w[:, None] * lo_alt).reshape(n, S, 3)
+    return {"E": terms.mean(axis=1), "terms": terms, "terms_alt": terms_alt,
+            "alt_valid": q["alt_valid"].reshape(n, S).astype(bool), "w": w.reshape(n, S)}
