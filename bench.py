@@ -238,6 +238,25 @@ def sh_sweep_variant(lumiq, o, d, steps):
     return out
 
 
+def floor_variant(inputs, oct32, steps):
+    """The consumer side: irradiance from the luminaire's proxy (emission plus
+    background through it) on a 1024 x 1024 floor grid 0.5 below the proxy,
+    16 uniform proxy samples per point, one call per step (sample rays, the
+    query over them, the per-point blend and sum)."""
+    import torch
+    pts, nrm = inputs.rays.floor_points(1024, 1024)
+    u = inputs.rays.sample_numbers(len(pts), 16, 5)
+    P, N, U = (torch.from_numpy(a).cuda() for a in (pts, nrm, u))
+    E = torch.empty((len(pts), 3), device="cuda")
+    ms, _ = time_launches(lambda: oct32.proxy_irradiance(P, N, U, background=(0.05, 0.05, 0.08), irradiance=E),
+                          steps, 2)
+    n_rays = len(pts) * 16
+    rec = {"points": len(pts), "samples_per_point": 16, "ms": ms, "points_per_s": len(pts) / (ms * 1e-3),
+           "sample_rays_per_s": n_rays / (ms * 1e-3)}
+    log(f"floor irradiance: {ms:.3f} ms for {n_rays} sample rays")
+    return rec
+
+
 def uneven_variant(lumiq):
     """The uneven multi-luminaire batch (16 trees of depth 6 to 10, SH degree
     3, float16, log-uniform ray counts): one persistent launch over all rays
@@ -427,6 +446,9 @@ def main():
         if args.surrogate_steps > 0:
             variants["surrogate"] = surrogate_variant(args, lumiq, tree, oct32, ro_t, rd_t, rrgb)
         del ro_t, rd_t, rrgb, ralpha
+
+    if not args.no_variants:
+        variants["floor_irradiance"] = floor_variant(inputs, oct32, max(5, args.steps // 4))
 
     if args.sh_sweep:
         variants["sh_sweep_camera"] = sh_sweep_variant(lumiq, o, d, max(5, args.steps // 2))

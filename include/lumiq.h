@@ -176,6 +176,39 @@ lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees
                                   const float *dirs, float *rgb, float *alpha, int model,
                                   uint32_t flags, void *hip_stream);
 
+/*
+ * Consumer side: irradiance at shading points from the light leaving the
+ * proxy box.  The radiance leaving the proxy along a ray is the emission
+ * plus the light behind the luminaire seen through it (Sec. 3, Eq. 2):
+ *     L_o = L_e + (1 - alpha) L_b,
+ * with L_e and alpha as lq_query_radiance returns them and L_b the constant
+ * colour background_rgb (host float[3]; NULL = black).  The proxy is sampled
+ * uniformly over its surface (Sec. 6, Sampling): sample s of point i reads
+ * u[i][s][0..2] in [0,1) (values outside give unspecified finite results),
+ * picks face f = floor(6 u0) (axis f/2; the face at -1 for even f, +1 for
+ * odd) and on it the point with coordinates 2 u1 - 1 and 2 u2 - 1 on the
+ * next two axes in cyclic order, at area density 1/24.  The ray goes from
+ * the point x to that face point y (float32: d = y - x).  A sample whose
+ * face x does not see from the front, or that lies below x's tangent plane
+ * (normal[i], any nonzero length), weighs 0; otherwise its term is
+ *     L_o cos(theta_x) cos(theta_y) / (|y - x|^2 / 24),
+ * and irradiance[i][c] is the mean of the terms over the n_samples samples
+ * (an unbiased estimate of the integral of L_o cos(theta_x) over the box's
+ * solid angle; a Lambertian surface of albedo rho reflects rho / pi of it).
+ * Points inside the proxy receive 0.  model: LQ_LINEAR or LQ_EXP, default
+ * query flags.  points, normals [n_points][3], u [n_points][n_samples][3],
+ * irradiance [n_points][3] and the optional sample_terms
+ * [n_points][n_samples][3] (each sample's term) are float32 device arrays.
+ * Scratch: 44 bytes per sample, stream-ordered.  Sums are FP64 in sample
+ * order (deterministic).  Errors: LQ_ERR_INVALID_ARG for a NULL tree, a bad
+ * model, n_samples outside 1..65536, n_points * n_samples >= 2^36, or a bad
+ * array; LQ_ERR_OOM; LQ_ERR_HIP.
+ */
+lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const float *normals,
+                              int64_t n_points, const float *u, int32_t n_samples,
+                              const float *background_rgb, int model, float *irradiance,
+                              float *sample_terms, void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate.  A ray is reduced to the point where its line enters
  * the sphere of radius sqrt(3) bounding the proxy box and its unit direction

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblumiq.so")
-SOURCES = ["api.hip", "octree_query.hip", "octree_query_f32.hip", "octree_query_f16.hip",
+SOURCES = ["api.hip", "proxy_shade.hip", "octree_query.hip", "octree_query_f32.hip", "octree_query_f16.hip",
            "octree_query_bf16.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [

@@ -401,6 +401,12 @@ static lq_status check_dev(const void *ptr, size_t bytes, int device, const char
     return LQ_OK;
 }
 
+lq_status check_device_array(const void *ptr, size_t bytes, int device, const char *name) {
+    return check_dev(ptr, bytes, device, name);
+}
+
+int octree_device(const lq_octree *t) { return t->device; }
+
 static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace, void *stream) {
     if (!t) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");
     if (a.n < 0) return fail(LQ_ERR_INVALID_ARG, "n must be >= 0");
@@ -430,6 +436,20 @@ static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace
             return st;
     }
     e = launch_query(t->t, a, trace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the emission query");
+    return LQ_OK;
+}
+
+lq_status query_scratch(const lq_octree *t, const float *o, const float *d, int64_t n, float *rgb, float *alpha,
+                        int model, hipStream_t s) {
+    QueryArgs a{};
+    a.o = o;
+    a.d = d;
+    a.n = n;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.model = model;
+    hipError_t e = launch_query(t->t, a, false, s);
     if (e != hipSuccess) return hip_fail(e, "launching the emission query");
     return LQ_OK;
 }

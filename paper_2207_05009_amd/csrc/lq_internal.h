@@ -100,6 +100,17 @@ uint16_t f32_to_bf16_rne(float x);
 
 void set_error(const std::string &msg);
 
+// a device array on `device` holding `bytes` from ptr on (else an error
+// status, with the message set)
+lq_status check_device_array(const void *ptr, size_t bytes, int device, const char *name);
+// device of a tree
+int octree_device(const lq_octree *t);
+
+// emission query (default flags) of n rays held in the library's own
+// device scratch: no pointer checks (the caller made the arrays)
+lq_status query_scratch(const lq_octree *t, const float *o, const float *d, int64_t n, float *rgb, float *alpha,
+                        int model, hipStream_t s);
+
 // emission query (linear model, default flags) of the rays listed in
 // index[0 .. *n_dev) of origins/dirs, writing rgb at those rays
 lq_status query_indexed(const lq_octree *tree, const float *o, const float *d, int64_t n_max,

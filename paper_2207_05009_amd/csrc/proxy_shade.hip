@@ -1,0 +1,158 @@
+// proxy_shade.hip -- the consumer side of the emission query: irradiance at
+// shading points from the light leaving the luminaire's proxy box.
+//
+// The radiance leaving the proxy along a ray is the luminaire's emission
+// plus the scene light behind it seen through the luminaire's transparency
+// (Sec. 3, Eq. 2): L_o = L_e + (1 - alpha) L_b, with alpha the opacity the
+// query returns (Sec. 4.1, Eq. 5) and L_b one background colour.  The proxy
+// is sampled uniformly over its surface (Sec. 6, Sampling): face
+// f = floor(6 u0) of the six faces of area 4, point (2 u1 - 1, 2 u2 - 1) on
+// it, area density 1/24.  A sample on a face that the shading point does not
+// see from the front, or below its tangent plane, weighs 0; otherwise
+//     w = cos(theta_x) cos(theta_y) / (|y - x|^2 / 24),
+// and the estimate is the mean of w L_o over the point's samples.
+//
+// Three stream-ordered steps: k_proxy_rays builds every sample's ray and
+// weight, the persistent emission query marches the rays, k_proxy_reduce
+// blends and sums per point in a fixed order (FP64 sums).
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "lq_internal.h"
+
+namespace lq {
+namespace {
+
+constexpr int kShadeBlock = 256;
+constexpr float kInvAreaDensity = 24.0f;   // total area of the faces of [-1,1]^3
+
+// one thread per sample j = i * S + s of point i
+__global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points, const float *normals,
+                                                            int64_t n_samples_total, int S, const float *u,
+                                                            float *o, float *d, float *w) {
+    const int64_t j = (int64_t)blockIdx.x * kShadeBlock + threadIdx.x;
+    if (j >= n_samples_total) return;
+    const int64_t i = j / S;
+    const float x0 = points[3 * i], x1 = points[3 * i + 1], x2 = points[3 * i + 2];
+    const float n0 = normals[3 * i], n1 = normals[3 * i + 1], n2 = normals[3 * i + 2];
+    const float u0 = u[3 * j], u1 = u[3 * j + 1], u2 = u[3 * j + 2];
+    int f = (int)(u0 * 6.0f);
+    f = f < 0 ? 0 : (f > 5 ? 5 : f);
+    const int axis = f >> 1;
+    const float sgn = (f & 1) ? 1.0f : -1.0f;
+    const float a = u1 * 2.0f - 1.0f, b = u2 * 2.0f - 1.0f;
+    // the face point: sgn on `axis`, then a and b on the next two axes (cyclic)
+    const float y0 = axis == 0 ? sgn : (axis == 1 ? b : a);
+    const float y1 = axis == 1 ? sgn : (axis == 2 ? b : a);
+    const float y2 = axis == 2 ? sgn : (axis == 0 ? b : a);
+    const float d0 = y0 - x0, d1 = y1 - x1, d2 = y2 - x2;
+    const float xa = axis == 0 ? x0 : (axis == 1 ? x1 : x2);
+    const float h = sgn * xa - 1.0f;          // height of x in front of the face's plane
+    const float dist2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const float nlen = sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+    const float ndot = n0 * d0 + n1 * d1 + n2 * d2;
+    float wt = 0.0f;
+    if (h > 0.0f && ndot > 0.0f && dist2 > 0.0f && nlen > 0.0f) {
+        const float dist = sqrtf(dist2);
+        const float cos_x = ndot / (nlen * dist), cos_y = h / dist;
+        wt = cos_x * cos_y / dist2 * kInvAreaDensity;
+    }
+    const bool live = wt > 0.0f;              // a dead sample's ray has no direction: the query skips it
+    o[3 * j] = x0;
+    o[3 * j + 1] = x1;
+    o[3 * j + 2] = x2;
+    d[3 * j] = live ? d0 : 0.0f;
+    d[3 * j + 1] = live ? d1 : 0.0f;
+    d[3 * j + 2] = live ? d2 : 0.0f;
+    w[j] = wt;
+}
+
+// one thread per point: terms w (L_e + (1 - alpha) L_b) in sample order
+__global__ __launch_bounds__(kShadeBlock) void k_proxy_reduce(const float *rgb, const float *alpha, const float *w,
+                                                              int64_t n_points, int S, float b0, float b1, float b2,
+                                                              float *irradiance, float *terms) {
+    const int64_t i = (int64_t)blockIdx.x * kShadeBlock + threadIdx.x;
+    if (i >= n_points) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const int64_t j = i * S + s;
+        const float wt = w[j];
+        const float tr = 1.0f - alpha[j];
+        const float t0 = wt * (rgb[3 * j] + tr * b0);
+        const float t1 = wt * (rgb[3 * j + 1] + tr * b1);
+        const float t2 = wt * (rgb[3 * j + 2] + tr * b2);
+        if (terms) {
+            terms[3 * j] = t0;
+            terms[3 * j + 1] = t1;
+            terms[3 * j + 2] = t2;
+        }
+        s0 += t0;
+        s1 += t1;
+        s2 += t2;
+    }
+    irradiance[3 * i] = (float)(s0 / S);
+    irradiance[3 * i + 1] = (float)(s1 / S);
+    irradiance[3 * i + 2] = (float)(s2 / S);
+}
+
+lq_status shade_fail(lq_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+}  // namespace
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const float *normals,
+                                         int64_t n_points, const float *u, int32_t n_samples,
+                                         const float *background_rgb, int model, float *irradiance,
+                                         float *sample_terms, void *hip_stream) {
+    if (!tree) return shade_fail(LQ_ERR_INVALID_ARG, "tree is NULL");
+    if (n_points < 0) return shade_fail(LQ_ERR_INVALID_ARG, "n_points must be >= 0");
+    if (n_samples < 1 || n_samples > 65536) return shade_fail(LQ_ERR_INVALID_ARG, "n_samples must be in 1..65536");
+    if (model != LQ_LINEAR && model != LQ_EXP) return shade_fail(LQ_ERR_INVALID_ARG, "model must be LQ_LINEAR or LQ_EXP");
+    if (n_points > ((int64_t)1 << 36) / n_samples) return shade_fail(LQ_ERR_INVALID_ARG, "n_points * n_samples too large");
+    if (n_points == 0) return LQ_OK;
+    const float b0 = background_rgb ? background_rgb[0] : 0.0f;
+    const float b1 = background_rgb ? background_rgb[1] : 0.0f;
+    const float b2 = background_rgb ? background_rgb[2] : 0.0f;
+    const int dev = octree_device(tree);
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return shade_fail(LQ_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    const int64_t m = n_points * n_samples;
+    lq_status st;
+    if ((st = check_device_array(points, (size_t)n_points * 12, dev, "points")) != LQ_OK) return st;
+    if ((st = check_device_array(normals, (size_t)n_points * 12, dev, "normals")) != LQ_OK) return st;
+    if ((st = check_device_array(u, (size_t)m * 12, dev, "u")) != LQ_OK) return st;
+    if ((st = check_device_array(irradiance, (size_t)n_points * 12, dev, "irradiance")) != LQ_OK) return st;
+    if (sample_terms && (st = check_device_array(sample_terms, (size_t)m * 12, dev, "sample_terms")) != LQ_OK)
+        return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    // stream-ordered scratch: per sample a ray (24 B), its weight (4 B), its radiance and opacity (16 B)
+    float *buf = nullptr;
+    if ((e = hipMallocAsync((void **)&buf, (size_t)m * 44, s)) != hipSuccess)
+        return shade_fail(LQ_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    float *o = buf, *d = buf + 3 * m, *w = buf + 6 * m, *rgb = buf + 7 * m, *alpha = buf + 10 * m;
+    hipLaunchKernelGGL(k_proxy_rays, dim3((unsigned)((m + kShadeBlock - 1) / kShadeBlock)), dim3(kShadeBlock), 0, s,
+                       points, normals, m, (int)n_samples, u, o, d, w);
+    e = hipGetLastError();
+    st = LQ_OK;
+    if (e != hipSuccess) {
+        st = shade_fail(LQ_ERR_HIP, std::string("launching the proxy samples: ") + hipGetErrorString(e));
+    } else {
+        st = query_scratch(tree, o, d, m, rgb, alpha, model, s);
+        if (st == LQ_OK) {
+            hipLaunchKernelGGL(k_proxy_reduce, dim3((unsigned)((n_points + kShadeBlock - 1) / kShadeBlock)),
+                               dim3(kShadeBlock), 0, s, rgb, alpha, w, n_points, (int)n_samples, b0, b1, b2,
+                               irradiance, sample_terms);
+            if ((e = hipGetLastError()) != hipSuccess)
+                st = shade_fail(LQ_ERR_HIP, std::string("launching the proxy reduction: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t f = hipFreeAsync(buf, s);
+    if (st == LQ_OK && f != hipSuccess) st = shade_fail(LQ_ERR_HIP, std::string("hipFreeAsync: ") + hipGetErrorString(f));
+    return st;
+}

@@ -63,8 +63,10 @@ def lib():
             L.lq_query_trace.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int, u32,
                                          vp, vp, vp, vp, vp, vp, i32, vp]
             L.lq_query_radiance_image.argtypes = [vp, vp, vp, i32, i32, vp, vp, C.c_int, u32, vp]
+            L.lq_proxy_irradiance.argtypes = [vp, vp, vp, i64, vp, i32, vp, C.c_int, vp, vp, vp]
             for name in ("lq_load_octree_desc", "lq_load_octree", "lq_octree_info",
-                         "lq_query_radiance", "lq_query_trace", "lq_query_radiance_image"):
+                         "lq_query_radiance", "lq_query_trace", "lq_query_radiance_image",
+                         "lq_proxy_irradiance"):
                 getattr(L, name).restype = C.c_int
             _lib = L
     return _lib
@@ -158,6 +160,25 @@ class Octree:
                                             _ptr(rgb), _ptr(alpha), MODEL[model], flags,
                                             _stream(stream)))
         return rgb, alpha
+
+    def proxy_irradiance(self, points, normals, u, background=None, model: str = "linear",
+                         want_terms: bool = False, irradiance=None, stream=None):
+        """Irradiance [n, 3] at shading points from the light leaving the proxy
+        (emission plus the background through the luminaire), estimated with
+        u.shape[1] uniform proxy samples per point.  points/normals: float32
+        [n, 3], u: float32 [n, S, 3] CUDA tensors.  Returns (irradiance,
+        terms [n, S, 3] or None)."""
+        import torch
+        n, S = u.shape[0], u.shape[1]
+        if points.shape[0] != n or normals.shape[0] != n:
+            raise ValueError("points, normals and u disagree on the number of points")
+        if irradiance is None:
+            irradiance = torch.empty((n, 3), dtype=torch.float32, device=points.device)
+        terms = torch.empty((n, S, 3), dtype=torch.float32, device=points.device) if want_terms else None
+        bg = (C.c_float * 3)(*background) if background is not None else None
+        check(lib().lq_proxy_irradiance(self.handle, _ptr(points), _ptr(normals), n, _ptr(u), S, bg,
+                                        MODEL[model], _ptr(irradiance), _ptr(terms), _stream(stream)))
+        return irradiance, terms
 
     def trace(self, origins, dirs, model: str = "linear", flags: int = 0, max_ids: int = 0,
               stream=None) -> dict:

@@ -126,3 +126,8 @@ def test_image_query_argument_errors(L):
     assert b"2^31" in L.lq_last_error()
     assert L.lq_query_radiance_image(None, None, None, 4, 4, None, None, 0, 0, None) == -1
     assert b"tree" in L.lq_last_error()
+
+
+def test_proxy_irradiance_argument_errors(L):
+    assert L.lq_proxy_irradiance(None, None, None, 4, None, 8, None, 0, None, None, None) == -1
+    assert b"tree" in L.lq_last_error()

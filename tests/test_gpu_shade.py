@@ -1,0 +1,148 @@
+"""GPU parity of the proxy-irradiance entry point (the consumer side: the
+Eq. 2 blend and uniform proxy sampling) against the oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import shade
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lq():
+    import torch
+    import paper_2207_05009_amd as lq
+    assert torch.cuda.is_available()
+    lq.lib()
+    return lq
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check(tree, pts, nrm, u, B, model, terms_g, E_g, idx=None):
+    """Per-sample terms (if given) and per-point estimates against the oracle;
+    a threshold-ambiguous sample may match either oracle candidate."""
+    m = 0 if model == "linear" else 1
+    orc = shade.proxy_irradiance(tree, pts, nrm, u, background=B, model=m)
+    Bc = np.abs(np.asarray(B, np.float64))[None, None, :]
+    floor = orc["w"][:, :, None] * (parity.FLOOR * tree.l_max + Bc)
+    t_ref = orc["terms"]
+    if terms_g is not None:
+        e_main = np.abs(terms_g - orc["terms"]) / np.maximum(np.abs(orc["terms"]), floor + 1e-30)
+        e_alt = np.abs(terms_g - orc["terms_alt"]) / np.maximum(np.abs(orc["terms_alt"]), floor + 1e-30)
+        use_alt = orc["alt_valid"][:, :, None] & (e_alt < e_main)
+        err = np.where(use_alt, e_alt, e_main)
+        _say(f"terms: max rel {err.max():.2e}, {int(orc['alt_valid'].sum())} ambiguous samples")
+        assert err.max() <= parity.RTOL, err.max()
+        assert np.all(terms_g[orc["w"] == 0] == 0)
+        t_ref = np.where(use_alt, orc["terms_alt"], orc["terms"])
+    else:
+        assert not orc["alt_valid"].any()
+    E_ref = t_ref.mean(axis=1)
+    e = np.abs(E_g - E_ref) / np.maximum(np.abs(E_ref), floor.mean(axis=1) + 1e-30)
+    _say(f"irradiance: max rel {e.max():.2e} over {len(E_ref)} points")
+    assert e.max() <= parity.RTOL, e.max()
+
+
+def _trees(c0_tree):
+    return {"c0": c0_tree, "empty": inputs.empty_tree(3),
+            "opaque": inputs.uniform_tree(2, 1e6, np.array([[-1.0], [0.5], [2.0]]))}
+
+
+@pytest.mark.parametrize("which", ["c0", "empty", "opaque"])
+@pytest.mark.parametrize("model", ["linear", "exp"])
+def test_proxy_irradiance_parity(lq, c0_tree, which, model):
+    import torch
+    tree = _trees(c0_tree)[which]
+    pts, nrm = inputs.rays.scattered_points(400, 21)
+    u = inputs.rays.sample_numbers(400, 64, 22)
+    B = (0.2, 0.5, 1.0)
+    _say(f"proxy irradiance {which} {model}: 400 points x 64 samples")
+    oct_ = lq.Octree(tree, "f32")
+    E, terms = oct_.proxy_irradiance(_dev(pts), _dev(nrm), _dev(u), background=B, model=model,
+                                     want_terms=True)
+    torch.cuda.synchronize()
+    _check(tree, pts, nrm, u, B, model, terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64))
+    # deterministic: a second call gives the same bits, with or without the terms
+    E2, _ = oct_.proxy_irradiance(_dev(pts), _dev(nrm), _dev(u), background=B, model=model)
+    torch.cuda.synchronize()
+    assert torch.equal(E, E2)
+
+
+def test_proxy_irradiance_edge_cases(lq, c0_tree):
+    import torch
+    oct_ = lq.Octree(c0_tree, "f32")
+    _say("proxy irradiance edge cases")
+    # no points
+    z = torch.empty((0, 3), device="cuda")
+    E, _ = oct_.proxy_irradiance(z, z, torch.empty((0, 4, 3), device="cuda"))
+    assert E.shape == (0, 3)
+    # one sample per point, a ragged count of points; a point inside the proxy
+    # and one facing away receive exactly 0; no background (black)
+    pts, nrm = inputs.rays.scattered_points(333, 31)
+    pts[0] = (0.2, -0.1, 0.3)
+    pts[1], nrm[1] = (0.0, 0.0, -3.0), (0.0, 0.0, -1.0)
+    u = inputs.rays.sample_numbers(333, 1, 32)
+    E, terms = oct_.proxy_irradiance(_dev(pts), _dev(nrm), _dev(u), want_terms=True)
+    torch.cuda.synchronize()
+    E = E.cpu().numpy().astype(np.float64)
+    assert np.all(E[:2] == 0)
+    _check(c0_tree, pts, nrm, u, (0.0, 0.0, 0.0), "linear", terms.cpu().numpy().astype(np.float64), E)
+
+
+def test_proxy_irradiance_rejects_bad_arguments(lq, c0_tree):
+    import ctypes as C
+    import torch
+    L = lq.lib()
+    oct_ = lq.Octree(c0_tree, "f32")
+    p = torch.zeros((8, 3), device="cuda")
+    u = torch.zeros((8, 2, 3), device="cuda")
+    out = torch.zeros((8, 3), device="cuda")
+    host = np.zeros((8, 3), np.float32)
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    assert L.lq_proxy_irradiance(oct_.handle, ptr(p), ptr(p), 8, ptr(u), 0, None, 0, ptr(out), None, None) == -1
+    assert L.lq_proxy_irradiance(oct_.handle, ptr(p), ptr(p), 8, ptr(u), 2, None, 5, ptr(out), None, None) == -1
+    assert L.lq_proxy_irradiance(oct_.handle, C.c_void_p(host.ctypes.data), ptr(p), 8, ptr(u), 2, None, 0,
+                                 ptr(out), None, None) == -1
+    assert b"device pointer" in L.lq_last_error()
+    assert L.lq_proxy_irradiance(oct_.handle, ptr(p), ptr(p), 8, ptr(u), 65536, None, 0, ptr(out), None,
+                                 None) == -1
+    assert b"smaller" in L.lq_last_error()          # u holds 2 samples per point
+
+
+def test_full_size_floor_sampled_parity(lq, c1_tree):
+    """The benchmarked configuration: the depth-9 tree lighting a 1024 x 1024
+    floor grid with 16 proxy samples per point, in one call; a seeded sample
+    of points is checked against the oracle."""
+    import torch
+    pts, nrm = inputs.rays.floor_points(1024, 1024)
+    u = inputs.rays.sample_numbers(len(pts), 16, 5)
+    B = (0.05, 0.05, 0.08)
+    _say(f"full-size floor: {len(pts)} points x 16 samples")
+    oct_ = lq.Octree(c1_tree, "f32")
+    E, _ = oct_.proxy_irradiance(_dev(pts), _dev(nrm), _dev(u), background=B)
+    torch.cuda.synchronize()
+    E = E.cpu().numpy().astype(np.float64)
+    oct_.free()
+    idx = np.sort(np.random.default_rng(3).choice(len(pts), 2000, replace=False))
+    orc = shade.proxy_irradiance(c1_tree, pts[idx], nrm[idx], u[idx], background=B)
+    amb = orc["alt_valid"].any(axis=1)
+    Bc = np.abs(np.asarray(B))[None, :]
+    floor = orc["w"].mean(axis=1)[:, None] * (parity.FLOOR * c1_tree.l_max + Bc)
+    e = np.abs(E[idx] - orc["E"]) / np.maximum(np.abs(orc["E"]), floor + 1e-30)
+    _say(f"floor: max rel {e[~amb].max():.2e} over {int((~amb).sum())} points ({int(amb.sum())} with an ambiguous sample)")
+    assert e[~amb].max() <= parity.RTOL
+    assert np.all(np.isfinite(E)) and np.all(E >= 0)
