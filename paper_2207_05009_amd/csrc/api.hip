@@ -440,15 +440,17 @@ static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace
     return LQ_OK;
 }
 
-lq_status query_scratch(const lq_octree *t, const float *o, const float *d, int64_t n, float *rgb, float *alpha,
-                        int model, hipStream_t s) {
+lq_status query_scratch(const lq_octree *t, const float *o, const float *d, int64_t n_max, const int64_t *index,
+                        const unsigned long long *n_dev, float *rgb, float *alpha, int model, hipStream_t s) {
     QueryArgs a{};
     a.o = o;
     a.d = d;
-    a.n = n;
+    a.n = n_max;
     a.rgb = rgb;
     a.alpha = alpha;
     a.model = model;
+    a.index = index;
+    a.n_dev = n_dev;
     hipError_t e = launch_query(t->t, a, false, s);
     if (e != hipSuccess) return hip_fail(e, "launching the emission query");
     return LQ_OK;

@@ -106,10 +106,11 @@ lq_status check_device_array(const void *ptr, size_t bytes, int device, const ch
 // device of a tree
 int octree_device(const lq_octree *t);
 
-// emission query (default flags) of n rays held in the library's own
-// device scratch: no pointer checks (the caller made the arrays)
-lq_status query_scratch(const lq_octree *t, const float *o, const float *d, int64_t n, float *rgb, float *alpha,
-                        int model, hipStream_t s);
+// emission query (default flags) over rays in the library's own device
+// scratch (no pointer checks: the caller made the arrays): the rays listed
+// in index[0 .. *n_dev) of o/d, writing rgb and alpha at those rays
+lq_status query_scratch(const lq_octree *t, const float *o, const float *d, int64_t n_max, const int64_t *index,
+                        const unsigned long long *n_dev, float *rgb, float *alpha, int model, hipStream_t s);
 
 // emission query (linear model, default flags) of the rays listed in
 // index[0 .. *n_dev) of origins/dirs, writing rgb at those rays

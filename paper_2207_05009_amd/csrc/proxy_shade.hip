@@ -12,9 +12,12 @@
 //     w = cos(theta_x) cos(theta_y) / (|y - x|^2 / 24),
 // and the estimate is the mean of w L_o over the point's samples.
 //
-// Three stream-ordered steps: k_proxy_rays builds every sample's ray and
-// weight, the persistent emission query marches the rays, k_proxy_reduce
-// blends and sums per point in a fixed order (FP64 sums).
+// Three stream-ordered steps: k_proxy_rays weighs every sample and lists the
+// live ones (weight > 0) with their rays, the persistent emission query
+// marches the listed rays only, k_proxy_reduce blends and sums per point in
+// sample order (FP64 sums).  Listing first matters: rays that need no march
+// interleaved with live ones would make the query's refills draw again and
+// again from its shared ray counters.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -25,47 +28,87 @@ namespace lq {
 namespace {
 
 constexpr int kShadeBlock = 256;
+constexpr int kShadeWaves = kShadeBlock / 64;
+constexpr int kSamplesPerThread = 8;
+constexpr int kSamplesPerBlock = kShadeBlock * kSamplesPerThread;
 constexpr float kInvAreaDensity = 24.0f;   // total area of the faces of [-1,1]^3
 
-// one thread per sample j = i * S + s of point i
-__global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points, const float *normals,
-                                                            int64_t n_samples_total, int S, const float *u,
-                                                            float *o, float *d, float *w) {
-    const int64_t j = (int64_t)blockIdx.x * kShadeBlock + threadIdx.x;
-    if (j >= n_samples_total) return;
-    const int64_t i = j / S;
-    const float x0 = points[3 * i], x1 = points[3 * i + 1], x2 = points[3 * i + 2];
-    const float n0 = normals[3 * i], n1 = normals[3 * i + 1], n2 = normals[3 * i + 2];
-    const float u0 = u[3 * j], u1 = u[3 * j + 1], u2 = u[3 * j + 2];
-    int f = (int)(u0 * 6.0f);
-    f = f < 0 ? 0 : (f > 5 ? 5 : f);
-    const int axis = f >> 1;
-    const float sgn = (f & 1) ? 1.0f : -1.0f;
-    const float a = u1 * 2.0f - 1.0f, b = u2 * 2.0f - 1.0f;
-    // the face point: sgn on `axis`, then a and b on the next two axes (cyclic)
-    const float y0 = axis == 0 ? sgn : (axis == 1 ? b : a);
-    const float y1 = axis == 1 ? sgn : (axis == 2 ? b : a);
-    const float y2 = axis == 2 ? sgn : (axis == 0 ? b : a);
-    const float d0 = y0 - x0, d1 = y1 - x1, d2 = y2 - x2;
-    const float xa = axis == 0 ? x0 : (axis == 1 ? x1 : x2);
-    const float h = sgn * xa - 1.0f;          // height of x in front of the face's plane
-    const float dist2 = d0 * d0 + d1 * d1 + d2 * d2;
-    const float nlen = sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
-    const float ndot = n0 * d0 + n1 * d1 + n2 * d2;
-    float wt = 0.0f;
-    if (h > 0.0f && ndot > 0.0f && dist2 > 0.0f && nlen > 0.0f) {
-        const float dist = sqrtf(dist2);
-        const float cos_x = ndot / (nlen * dist), cos_y = h / dist;
-        wt = cos_x * cos_y / dist2 * kInvAreaDensity;
+__global__ void k_proxy_zero(unsigned long long *p) { p[0] = 0ull; }
+
+// Samples j = blockIdx.x * kSamplesPerBlock + k * kShadeBlock + threadIdx.x
+// (k < kSamplesPerThread) of the flattened [point][sample] grid: each
+// sample's weight, and for the samples that weigh more than 0 (live) the ray
+// and a place in the live list (one atomic per block; the list's order
+// across blocks is arbitrary, each ray's result does not depend on it).
+__global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points, const float *normals, int64_t m,
+                                                            int S, const float *u, float *o, float *d, float *w,
+                                                            int64_t *live, unsigned long long *n_live) {
+    __shared__ unsigned s_off[kSamplesPerThread][kShadeWaves];
+    __shared__ unsigned long long s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t j0 = (int64_t)blockIdx.x * kSamplesPerBlock + threadIdx.x;
+    uint64_t mask[kSamplesPerThread];
+#pragma unroll
+    for (int k = 0; k < kSamplesPerThread; ++k) {
+        const int64_t j = j0 + (int64_t)k * kShadeBlock;
+        bool is_live = false;
+        if (j < m) {
+            const int64_t i = j / S;
+            const float x0 = points[3 * i], x1 = points[3 * i + 1], x2 = points[3 * i + 2];
+            const float n0 = normals[3 * i], n1 = normals[3 * i + 1], n2 = normals[3 * i + 2];
+            const float u0 = u[3 * j], u1 = u[3 * j + 1], u2 = u[3 * j + 2];
+            int f = (int)(u0 * 6.0f);
+            f = f < 0 ? 0 : (f > 5 ? 5 : f);
+            const int axis = f >> 1;
+            const float sgn = (f & 1) ? 1.0f : -1.0f;
+            const float a = u1 * 2.0f - 1.0f, b = u2 * 2.0f - 1.0f;
+            // the face point: sgn on `axis`, then a and b on the next two axes (cyclic)
+            const float y0 = axis == 0 ? sgn : (axis == 1 ? b : a);
+            const float y1 = axis == 1 ? sgn : (axis == 2 ? b : a);
+            const float y2 = axis == 2 ? sgn : (axis == 0 ? b : a);
+            const float d0 = y0 - x0, d1 = y1 - x1, d2 = y2 - x2;
+            const float xa = axis == 0 ? x0 : (axis == 1 ? x1 : x2);
+            const float h = sgn * xa - 1.0f;          // height of x in front of the face's plane
+            const float dist2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const float nlen = sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+            const float ndot = n0 * d0 + n1 * d1 + n2 * d2;
+            float wt = 0.0f;
+            if (h > 0.0f && ndot > 0.0f && dist2 > 0.0f && nlen > 0.0f) {
+                const float dist = sqrtf(dist2);
+                const float cos_x = ndot / (nlen * dist), cos_y = h / dist;
+                wt = cos_x * cos_y / dist2 * kInvAreaDensity;
+            }
+            w[j] = wt;
+            is_live = wt > 0.0f;
+            if (is_live) {
+                o[3 * j] = x0;
+                o[3 * j + 1] = x1;
+                o[3 * j + 2] = x2;
+                d[3 * j] = d0;
+                d[3 * j + 1] = d1;
+                d[3 * j + 2] = d2;
+            }
+        }
+        mask[k] = __ballot(is_live);
+        if (lane == 0) s_off[k][wave] = (unsigned)__popcll(mask[k]);
     }
-    const bool live = wt > 0.0f;              // a dead sample's ray has no direction: the query skips it
-    o[3 * j] = x0;
-    o[3 * j + 1] = x1;
-    o[3 * j + 2] = x2;
-    d[3 * j] = live ? d0 : 0.0f;
-    d[3 * j + 1] = live ? d1 : 0.0f;
-    d[3 * j + 2] = live ? d2 : 0.0f;
-    w[j] = wt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int k = 0; k < kSamplesPerThread; ++k)
+            for (int v = 0; v < kShadeWaves; ++v) {
+                const unsigned c = s_off[k][v];
+                s_off[k][v] = tot;
+                tot += c;
+            }
+        s_base = tot ? atomicAdd(n_live, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSamplesPerThread; ++k)
+        if (mask[k] & (1ull << lane))
+            live[s_base + s_off[k][wave] + __popcll(mask[k] & below)] = j0 + (int64_t)k * kShadeBlock;
 }
 
 // one thread per point: terms w (L_e + (1 - alpha) L_b) in sample order
@@ -78,10 +121,13 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_reduce(const float *rgb, 
     for (int s = 0; s < S; ++s) {
         const int64_t j = i * S + s;
         const float wt = w[j];
-        const float tr = 1.0f - alpha[j];
-        const float t0 = wt * (rgb[3 * j] + tr * b0);
-        const float t1 = wt * (rgb[3 * j + 1] + tr * b1);
-        const float t2 = wt * (rgb[3 * j + 2] + tr * b2);
+        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
+        if (wt > 0.0f) {                      // only live samples were queried
+            const float tr = 1.0f - alpha[j];
+            t0 = wt * (rgb[3 * j] + tr * b0);
+            t1 = wt * (rgb[3 * j + 1] + tr * b1);
+            t2 = wt * (rgb[3 * j + 2] + tr * b2);
+        }
         if (terms) {
             terms[3 * j] = t0;
             terms[3 * j + 1] = t1;
@@ -131,19 +177,24 @@ extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *poi
     if (sample_terms && (st = check_device_array(sample_terms, (size_t)m * 12, dev, "sample_terms")) != LQ_OK)
         return st;
     hipStream_t s = (hipStream_t)hip_stream;
-    // stream-ordered scratch: per sample a ray (24 B), its weight (4 B), its radiance and opacity (16 B)
-    float *buf = nullptr;
-    if ((e = hipMallocAsync((void **)&buf, (size_t)m * 44, s)) != hipSuccess)
+    // stream-ordered scratch: the live-ray counter (256 B), then per sample a
+    // list slot (8 B), a ray (24 B), its weight (4 B), its radiance and opacity (16 B)
+    unsigned char *buf = nullptr;
+    if ((e = hipMallocAsync((void **)&buf, 256 + (size_t)m * 52, s)) != hipSuccess)
         return shade_fail(LQ_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    float *o = buf, *d = buf + 3 * m, *w = buf + 6 * m, *rgb = buf + 7 * m, *alpha = buf + 10 * m;
-    hipLaunchKernelGGL(k_proxy_rays, dim3((unsigned)((m + kShadeBlock - 1) / kShadeBlock)), dim3(kShadeBlock), 0, s,
-                       points, normals, m, (int)n_samples, u, o, d, w);
+    unsigned long long *n_live = reinterpret_cast<unsigned long long *>(buf);
+    int64_t *live = reinterpret_cast<int64_t *>(buf + 256);
+    float *o = reinterpret_cast<float *>(buf + 256 + (size_t)m * 8);
+    float *d = o + 3 * m, *w = o + 6 * m, *rgb = o + 7 * m, *alpha = o + 10 * m;
+    hipLaunchKernelGGL(k_proxy_zero, dim3(1), dim3(1), 0, s, n_live);
+    hipLaunchKernelGGL(k_proxy_rays, dim3((unsigned)((m + kSamplesPerBlock - 1) / kSamplesPerBlock)),
+                       dim3(kShadeBlock), 0, s, points, normals, m, (int)n_samples, u, o, d, w, live, n_live);
     e = hipGetLastError();
     st = LQ_OK;
     if (e != hipSuccess) {
         st = shade_fail(LQ_ERR_HIP, std::string("launching the proxy samples: ") + hipGetErrorString(e));
     } else {
-        st = query_scratch(tree, o, d, m, rgb, alpha, model, s);
+        st = query_scratch(tree, o, d, m, live, n_live, rgb, alpha, model, s);
         if (st == LQ_OK) {
             hipLaunchKernelGGL(k_proxy_reduce, dim3((unsigned)((n_points + kShadeBlock - 1) / kShadeBlock)),
                                dim3(kShadeBlock), 0, s, rgb, alpha, w, n_points, (int)n_samples, b0, b1, b2,
