@@ -200,7 +200,7 @@ lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees
  * irradiance [n_points][3] and the optional sample_terms
  * [n_points][n_samples][3] (each sample's term) are float32 device arrays.
  * Scratch: 52 bytes per sample, stream-ordered; only samples that weigh
- * more than 0 are marched.  Sums are FP64 in sample
+ * more than 0 are marched.  Sums are FP64 in a fixed
  * order (deterministic).  Errors: LQ_ERR_INVALID_ARG for a NULL tree, a bad
  * model, n_samples outside 1..65536, n_points * n_samples >= 2^36, or a bad
  * array; LQ_ERR_OOM; LQ_ERR_HIP.

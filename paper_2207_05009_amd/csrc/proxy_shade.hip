@@ -20,6 +20,7 @@
 // again from its shared ray counters.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "lq_internal.h"
@@ -111,35 +112,69 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
             live[s_base + s_off[k][wave] + __popcll(mask[k] & below)] = j0 + (int64_t)k * kShadeBlock;
 }
 
-// one thread per point: terms w (L_e + (1 - alpha) L_b) in sample order
+// Blend and per-point sums.  Block b takes points [b P, b P + P) with
+// P = min(kShadeBlock, max(1, kReduceChunk / S)), so that their samples fit
+// one chunk of kReduceChunk (a point with more samples is summed chunk by
+// chunk).  The terms w (L_e + (1 - alpha) L_b) of a chunk are computed from
+// coalesced loads into LDS; one thread per point then adds its terms in
+// sample order (FP64 partial sums per chunk, added in chunk order): the same
+// order for every launch.
+constexpr int kReduceChunk = kSamplesPerBlock;
+
 __global__ __launch_bounds__(kShadeBlock) void k_proxy_reduce(const float *rgb, const float *alpha, const float *w,
-                                                              int64_t n_points, int S, float b0, float b1, float b2,
-                                                              float *irradiance, float *terms) {
-    const int64_t i = (int64_t)blockIdx.x * kShadeBlock + threadIdx.x;
-    if (i >= n_points) return;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int s = 0; s < S; ++s) {
-        const int64_t j = i * S + s;
-        const float wt = w[j];
-        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
-        if (wt > 0.0f) {                      // only live samples were queried
-            const float tr = 1.0f - alpha[j];
-            t0 = wt * (rgb[3 * j] + tr * b0);
-            t1 = wt * (rgb[3 * j + 1] + tr * b1);
-            t2 = wt * (rgb[3 * j + 2] + tr * b2);
+                                                              int64_t n_points, int S, int P, float b0, float b1,
+                                                              float b2, float *irradiance, float *terms) {
+    __shared__ float s_t[3][kReduceChunk];
+    const int64_t p0 = (int64_t)blockIdx.x * P;
+    const int np = (int)(n_points - p0 < P ? n_points - p0 : P);
+    const int64_t span = (int64_t)np * S;            // samples of this block's points
+    const int64_t j_first = p0 * S;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t c0 = 0; c0 < span; c0 += kReduceChunk) {
+        const int len = (int)(span - c0 < kReduceChunk ? span - c0 : kReduceChunk);
+        for (int t = threadIdx.x; t < len; t += kShadeBlock) {
+            const int64_t j = j_first + c0 + t;
+            const float wt = w[j];
+            float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
+            if (wt > 0.0f) {                      // only live samples were queried
+                const float tr = 1.0f - alpha[j];
+                t0 = wt * (rgb[3 * j] + tr * b0);
+                t1 = wt * (rgb[3 * j + 1] + tr * b1);
+                t2 = wt * (rgb[3 * j + 2] + tr * b2);
+            }
+            if (terms) {
+                terms[3 * j] = t0;
+                terms[3 * j + 1] = t1;
+                terms[3 * j + 2] = t2;
+            }
+            s_t[0][t] = t0;
+            s_t[1][t] = t1;
+            s_t[2][t] = t2;
         }
-        if (terms) {
-            terms[3 * j] = t0;
-            terms[3 * j + 1] = t1;
-            terms[3 * j + 2] = t2;
+        __syncthreads();
+        if ((int)threadIdx.x < np) {             // thread q sums point p0 + q (P <= kShadeBlock)
+            const int64_t q = threadIdx.x;
+            // this point's samples within the chunk, in order
+            const int64_t lo = q * S > c0 ? q * S : c0;
+            const int64_t hi = q * S + S < c0 + len ? q * S + S : c0 + len;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int64_t k = lo; k < hi; ++k) {
+                s0 += s_t[0][k - c0];
+                s1 += s_t[1][k - c0];
+                s2 += s_t[2][k - c0];
+            }
+            a0 += s0;
+            a1 += s1;
+            a2 += s2;
         }
-        s0 += t0;
-        s1 += t1;
-        s2 += t2;
+        __syncthreads();
     }
-    irradiance[3 * i] = (float)(s0 / S);
-    irradiance[3 * i + 1] = (float)(s1 / S);
-    irradiance[3 * i + 2] = (float)(s2 / S);
+    if ((int)threadIdx.x < np) {
+        const int64_t i = p0 + threadIdx.x;
+        irradiance[3 * i] = (float)(a0 / S);
+        irradiance[3 * i + 1] = (float)(a1 / S);
+        irradiance[3 * i + 2] = (float)(a2 / S);
+    }
 }
 
 lq_status shade_fail(lq_status st, const std::string &msg) {
@@ -196,9 +231,9 @@ extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *poi
     } else {
         st = query_scratch(tree, o, d, m, live, n_live, rgb, alpha, model, s);
         if (st == LQ_OK) {
-            hipLaunchKernelGGL(k_proxy_reduce, dim3((unsigned)((n_points + kShadeBlock - 1) / kShadeBlock)),
-                               dim3(kShadeBlock), 0, s, rgb, alpha, w, n_points, (int)n_samples, b0, b1, b2,
-                               irradiance, sample_terms);
+            const int P = n_samples >= kReduceChunk ? 1 : std::min(kShadeBlock, kReduceChunk / n_samples);
+            hipLaunchKernelGGL(k_proxy_reduce, dim3((unsigned)((n_points + P - 1) / P)), dim3(kShadeBlock), 0, s,
+                               rgb, alpha, w, n_points, (int)n_samples, P, b0, b1, b2, irradiance, sample_terms);
             if ((e = hipGetLastError()) != hipSuccess)
                 st = shade_fail(LQ_ERR_HIP, std::string("launching the proxy reduction: ") + hipGetErrorString(e));
         }

@@ -103,6 +103,22 @@ def test_proxy_irradiance_edge_cases(lq, c0_tree):
     _check(c0_tree, pts, nrm, u, (0.0, 0.0, 0.0), "linear", terms.cpu().numpy().astype(np.float64), E)
 
 
+@pytest.mark.parametrize("n,S", [(3, 5000), (100, 37), (1000, 2), (5, 2048)])
+def test_proxy_irradiance_sample_counts(lq, c0_tree, n, S):
+    """Sample counts that split a point over several reduction chunks, that
+    do not divide the chunk, and that pack many points per chunk."""
+    import torch
+    pts, nrm = inputs.rays.scattered_points(n, 60 + S)
+    u = inputs.rays.sample_numbers(n, S, 61 + S)
+    B = (1.0, 0.0, 0.5)
+    _say(f"proxy irradiance: {n} points x {S} samples")
+    oct_ = lq.Octree(c0_tree, "f32")
+    E, terms = oct_.proxy_irradiance(_dev(pts), _dev(nrm), _dev(u), background=B, want_terms=True)
+    torch.cuda.synchronize()
+    _check(c0_tree, pts, nrm, u, B, "linear", terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64))
+
+
 def test_proxy_irradiance_rejects_bad_arguments(lq, c0_tree):
     import ctypes as C
     import torch
