@@ -93,3 +93,17 @@ def test_uneven_batch_recipe():
     c = uneven.ray_counts()
     assert len(c) == 16 and all(2 ** 10 <= x <= 2 ** 23 for x in c)
     assert c == uneven.ray_counts()   # deterministic
+
+
+def test_shading_point_recipes():
+    p, n = inputs.rays.floor_points(8, 4)
+    assert p.shape == (32, 3) and p.dtype == np.float32 and np.all(p[:, 2] == -1.5)
+    assert np.all(np.abs(p[:, :2]) < 5) and np.all(n == np.array([0, 0, 1], np.float32))
+    assert np.allclose(p[1, 0] - p[0, 0], 10 / 8) and np.allclose(p[8, 1] - p[0, 1], 10 / 4)
+    p, n = inputs.rays.scattered_points(5000, 3)
+    assert p.dtype == np.float32 and np.all(np.abs(p).max(1) > 1.05)
+    assert np.all(np.linalg.norm(p, axis=1) <= 6.0 + 1e-5)
+    assert np.mean(np.einsum("ij,ij->i", n, -p) > 0) > 0.9      # mostly facing the luminaire
+    u = inputs.rays.sample_numbers(10, 7, 4)
+    assert u.shape == (10, 7, 3) and u.dtype == np.float32 and u.min() >= 0 and u.max() < 1
+    assert np.array_equal(u, inputs.rays.sample_numbers(10, 7, 4))
