@@ -12,12 +12,15 @@
 // while the atomic's latency and the per-ray set-up are paid for many lanes
 // at once.
 //
-// XCD-aware work split: the batch is cut into kXcds contiguous ranges with a
-// counter each.  Workgroups are dispatched to the accelerator dies round
-// robin, so a wave of block b starts on range b % kXcds: the rays one die's
-// L2 sees are neighbours in the batch (for a camera, a band of image rows),
-// not every kXcds-th chunk.  A wave whose range is used up continues on the
-// next ranges, so the tail stays balanced.
+// XCD-aware work split: the batch is cut into kXcds groups of kRangesPerXcd
+// contiguous ranges, with a counter each.  Workgroups are dispatched to the
+// accelerator dies round robin, so a wave of block b starts on a range of
+// group b % kXcds: the rays one die's L2 sees are neighbours in the batch
+// (for a camera, a band of image rows), not every kXcds-th chunk.  Two
+// counters per die rather than one halve the same-address atomics of the
+// refills, which bound batches of short or dead rays; more counters spread a
+// die's waves over too many places of the batch for its L2.  A wave whose
+// range is used up continues on the next ranges, so the tail stays balanced.
 //
 // Camera batches are split by position in their tile order instead
 // (tile_order_pixel): the 64 rays one refill hands a wave then form an 8 x 8
@@ -43,8 +46,11 @@ constexpr int kStepsPerCheck = 16;   // steps between refill checks
 constexpr int kTileRefillBelow = 16;
 constexpr int kTileStepsPerCheck = 32;
 constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
-static_assert(kXcds >= 1 && kXcds <= 31, "one bit per range in a 32-bit mask");
-constexpr unsigned kAllRanges = (1u << kXcds) - 1u;   // every range used up
+constexpr int kRangesPerXcd = 2;     // ray counters (contiguous ranges) per die
+constexpr int kRanges = kXcds * kRangesPerXcd;
+static_assert(kRanges >= 1 && kRanges <= 64, "one bit per range in a 64-bit mask");
+constexpr uint64_t kAllRanges = kRanges == 64 ? ~0ull : (1ull << kRanges) - 1ull;   // every range used up
+constexpr int kMaxTries = 8;         // refill attempts per check
 
 __device__ inline uint64_t lanemask_lt() {
     const unsigned lane = __lane_id();
@@ -70,7 +76,7 @@ __device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool
     }
 }
 
-__device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kXcds; }
+__device__ inline int64_t range_begin(int x, int64_t n) { return n * x / kRanges; }
 
 // the persistent loop shared by the single- and multi-tree kernels;
 // tree_index(ray) finds the tree a ray queries (once, when a lane takes the
@@ -109,15 +115,16 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
     int64_t ray = -1;            // ray held by this lane, -1 when idle
     int tk = 0;                  // tree of that ray
     uint32_t *ids = nullptr;
-    int cur = blockIdx.x % kXcds;   // range this wave draws from (wave-uniform)
-    unsigned used_up = 0;           // ranges known to be exhausted (wave-uniform)
+    // range this wave draws from (wave-uniform): one of its die's ranges
+    int cur = (int)(blockIdx.x % kXcds) * kRangesPerXcd + (int)((blockIdx.x / kXcds) % kRangesPerXcd);
+    uint64_t used_up = 0;           // ranges known to be exhausted (wave-uniform)
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
     for (;;) {
         bool want = ray < 0 && used_up != kAllRanges;
         uint64_t need = __ballot(want);
         const int busy = __popcll(__ballot(ray >= 0));
         if (__builtin_expect(need && busy < refill_below, 0)) {
-            for (int tries = 0; need && tries < kXcds; ++tries) {
+            for (int tries = 0; need && tries < kMaxTries; ++tries) {
                 const int cnt = __popcll(need);
                 const int leader = __ffsll((unsigned long long)need) - 1;
                 unsigned long long base = 0;
@@ -149,10 +156,10 @@ __device__ inline void persistent_query(const QueryArgs &a, unsigned long long *
                     }
                 }
                 if ((int64_t)base + cnt >= len) {   // this range is used up: move on
-                    used_up |= 1u << cur;
-                    for (int j = 1; j <= kXcds; ++j) {
-                        const int c = (cur + j) % kXcds;
-                        if (!(used_up & (1u << c))) { cur = c; break; }
+                    used_up |= 1ull << cur;
+                    for (int j = 1; j <= kRanges; ++j) {
+                        const int c = (cur + j) % kRanges;
+                        if (!(used_up & (1ull << c))) { cur = c; break; }
                     }
                 }
                 want = want && used_up != kAllRanges;
@@ -274,9 +281,9 @@ hipError_t launch_one(const DevTree &t, const QueryArgs &a, hipStream_t s) {
     const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
     const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
     unsigned long long *queue = nullptr;
-    hipError_t e = hipMallocAsync((void **)&queue, kXcds * sizeof(unsigned long long), s);
+    hipError_t e = hipMallocAsync((void **)&queue, kRanges * sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kXcds), 0, s, queue);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kRanges), 0, s, queue);
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, t, a, queue);
     e = hipGetLastError();
     hipError_t f = hipFreeAsync(queue, s);
@@ -324,9 +331,9 @@ hipError_t launch_multi_one(const DevTree *trees, const int64_t *offsets, int n_
     const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
     const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
     unsigned long long *queue = nullptr;
-    hipError_t e = hipMallocAsync((void **)&queue, kXcds * sizeof(unsigned long long), s);
+    hipError_t e = hipMallocAsync((void **)&queue, kRanges * sizeof(unsigned long long), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kXcds), 0, s, queue);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kRanges), 0, s, queue);
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, trees, offsets, n_trees, a, queue);
     e = hipGetLastError();
     hipError_t f = hipFreeAsync(queue, s);
