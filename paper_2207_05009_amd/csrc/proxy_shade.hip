@@ -29,7 +29,6 @@ namespace lq {
 namespace {
 
 constexpr int kShadeBlock = 256;
-constexpr int kShadeWaves = kShadeBlock / 64;
 constexpr int kSamplesPerThread = 8;
 constexpr int kSamplesPerBlock = kShadeBlock * kSamplesPerThread;
 constexpr float kInvAreaDensity = 24.0f;   // total area of the faces of [-1,1]^3
@@ -39,21 +38,29 @@ __global__ void k_proxy_zero(unsigned long long *p) { p[0] = 0ull; }
 // Samples j = blockIdx.x * kSamplesPerBlock + k * kShadeBlock + threadIdx.x
 // (k < kSamplesPerThread) of the flattened [point][sample] grid: each
 // sample's weight, and for the samples that weigh more than 0 (live) the ray
-// and a place in the live list (one atomic per block; the list's order
-// across blocks is arbitrary, each ray's result does not depend on it).
+// and a place in the live list (one atomic per block).  Inside a block the
+// live samples are listed grouped by the cell of the proxy they aim at (face
+// x 4 x 4 cells), so that the rays one wave marches come from neighbouring
+// shading points toward the same part of the luminaire.  The list's order
+// (across blocks, and within a cell) is arbitrary; no ray's result depends
+// on it.
+constexpr int kCellsPerSide = 4;
+constexpr int kAimCells = 6 * kCellsPerSide * kCellsPerSide;
 __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points, const float *normals, int64_t m,
                                                             int S, const float *u, float *o, float *d, float *w,
                                                             int64_t *live, unsigned long long *n_live) {
-    __shared__ unsigned s_off[kSamplesPerThread][kShadeWaves];
+    __shared__ unsigned s_cell[kAimCells];
     __shared__ unsigned long long s_base;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int c = threadIdx.x; c < kAimCells; c += kShadeBlock) s_cell[c] = 0;
+    __syncthreads();
     const int64_t j0 = (int64_t)blockIdx.x * kSamplesPerBlock + threadIdx.x;
-    uint64_t mask[kSamplesPerThread];
+    int cell[kSamplesPerThread];              // aim cell of a live sample, -1 for a dead one
+    unsigned rank[kSamplesPerThread];         // its place among the block's samples of that cell
 #pragma unroll
     for (int k = 0; k < kSamplesPerThread; ++k) {
         const int64_t j = j0 + (int64_t)k * kShadeBlock;
-        bool is_live = false;
+        cell[k] = -1;
+        rank[k] = 0;
         if (j < m) {
             const int64_t i = j / S;
             const float x0 = points[3 * i], x1 = points[3 * i + 1], x2 = points[3 * i + 2];
@@ -81,35 +88,36 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
                 wt = cos_x * cos_y / dist2 * kInvAreaDensity;
             }
             w[j] = wt;
-            is_live = wt > 0.0f;
-            if (is_live) {
+            if (wt > 0.0f) {
                 o[3 * j] = x0;
                 o[3 * j + 1] = x1;
                 o[3 * j + 2] = x2;
                 d[3 * j] = d0;
                 d[3 * j + 1] = d1;
                 d[3 * j + 2] = d2;
+                int ca = (int)((a + 1.0f) * (0.5f * kCellsPerSide));
+                int cb = (int)((b + 1.0f) * (0.5f * kCellsPerSide));
+                ca = ca < 0 ? 0 : (ca >= kCellsPerSide ? kCellsPerSide - 1 : ca);
+                cb = cb < 0 ? 0 : (cb >= kCellsPerSide ? kCellsPerSide - 1 : cb);
+                cell[k] = (f * kCellsPerSide + ca) * kCellsPerSide + cb;
+                rank[k] = atomicAdd(&s_cell[cell[k]], 1u);
             }
         }
-        mask[k] = __ballot(is_live);
-        if (lane == 0) s_off[k][wave] = (unsigned)__popcll(mask[k]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {                   // cell counts -> offsets in the block's part of the list
         unsigned tot = 0;
-        for (int k = 0; k < kSamplesPerThread; ++k)
-            for (int v = 0; v < kShadeWaves; ++v) {
-                const unsigned c = s_off[k][v];
-                s_off[k][v] = tot;
-                tot += c;
-            }
+        for (int c = 0; c < kAimCells; ++c) {
+            const unsigned n = s_cell[c];
+            s_cell[c] = tot;
+            tot += n;
+        }
         s_base = tot ? atomicAdd(n_live, (unsigned long long)tot) : 0ull;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSamplesPerThread; ++k)
-        if (mask[k] & (1ull << lane))
-            live[s_base + s_off[k][wave] + __popcll(mask[k] & below)] = j0 + (int64_t)k * kShadeBlock;
+        if (cell[k] >= 0) live[s_base + s_cell[cell[k]] + rank[k]] = j0 + (int64_t)k * kShadeBlock;
 }
 
 // Blend and per-point sums.  Block b takes points [b P, b P + P) with
