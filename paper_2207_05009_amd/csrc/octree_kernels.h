@@ -39,8 +39,8 @@ namespace lq {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRefillBelow = 32;     // refill when fewer lanes of a wave are busy
-constexpr int kStepsPerCheck = 16;   // steps between refill checks
+constexpr int kRefillBelow = 40;     // refill when fewer lanes of a wave are busy
+constexpr int kStepsPerCheck = 10;   // steps between refill checks
 // the same for camera batches in tile order, whose rays in a wave (one
 // pixel tile) end at similar steps: fewer checks pay more than early refills
 constexpr int kTileRefillBelow = 16;
