@@ -60,6 +60,9 @@ def lib():
             L.orc_query.restype = C.c_int
             L.orc_query.argtypes = [C.POINTER(_Tree), C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
                                     C.c_uint32] + [C.c_void_p] * 15 + [C.c_int32, C.c_int]
+            L.orc_candidates.restype = C.c_int
+            L.orc_candidates.argtypes = [C.POINTER(_Tree), C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                         C.c_uint32, C.c_int] + [C.c_void_p] * 8 + [C.c_int]
             L.orc_sh_eval.restype = None
             L.orc_sh_eval.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
             L.orc_max_threads.restype = C.c_int
@@ -100,6 +103,45 @@ def sh_eval(deg: int, w) -> np.ndarray:
     Y = np.zeros(25, dtype=np.float64)
     lib().orc_sh_eval(int(deg), w.ctypes.data, Y.ctypes.data)
     return Y[: (deg + 1) ** 2].copy()
+
+
+# ---------------------------------------------------------------- pruning
+def pruned_tree(tree, storage: str = "f32"):
+    """The tree without the data leaves that the sigma_min skip never
+    composites (Sec. 6.2: stored density below sigma_min, compared at the
+    stored precision) and without the internal nodes left with no child.
+    Leaf indices (and so the density and SH arrays) are unchanged; the root
+    stays node 0.  Marching it with the skip off visits exactly the
+    composited leaves of the original tree, over the same segments."""
+    import dataclasses
+    child = np.asarray(tree.child, dtype=np.int64)
+    keep = dequantize(tree.sigma, storage) >= float(np.float32(tree.sigma_min))
+    levels = [np.array([0])]
+    while True:
+        kids = child[levels[-1]]
+        nxt = kids[kids > 0]
+        if nxt.size == 0:
+            break
+        levels.append(nxt)
+    alive = np.zeros(child.shape[0], bool)
+    for nodes in reversed(levels):
+        kids = child[nodes]
+        sub = np.zeros(kids.shape, bool)
+        sub[kids > 0] = alive[kids[kids > 0]]
+        sub[kids < 0] = keep[-kids[kids < 0] - 1]
+        alive[nodes] = sub.any(1)
+    order = np.concatenate(levels)
+    order = order[(order == 0) | alive[order]]
+    new_index = np.zeros(child.shape[0], np.int64)
+    new_index[order] = np.arange(order.size)
+    kids = child[order]
+    out = np.zeros(kids.shape, np.int32)
+    node_kept = (kids > 0) & alive[np.maximum(kids, 0)]
+    out[node_kept] = new_index[kids[node_kept]]
+    leaf_kept = kids < 0
+    leaf_kept[leaf_kept] = keep[-kids[leaf_kept] - 1]
+    out[leaf_kept] = kids[leaf_kept]
+    return dataclasses.replace(tree, child=out)
 
 
 # ---------------------------------------------------------------- query
@@ -158,6 +200,55 @@ def query(tree, o, d, model: int = LINEAR, opts: int = 0, storage: str = "f32",
     if exact_fallback:
         for i in flagged.tolist():
             _exact_ray(P, o[i], d[i], model, opts, out, i, ids, max_ids)
+    return out
+
+
+def candidates(tree, o, d, model: int = LINEAR, opts: int = 0, storage: str = "f32",
+               max_cand: int = 8, prepared: PreparedTree | None = None, force_exact: bool = False) -> dict:
+    """Every valid outcome of each ray's alpha_max stop (Sec. 6.2, reading
+    R3 for rays with several stop tests within eta of the threshold: each of
+    those may go either way, so the march may stop at any of them or
+    continue through all of them; the other tests keep their decision).
+    Candidate 0 continues at every ambiguous test; candidate c >= 1 stops at
+    the c-th ambiguous test.  Returns arrays [n, max_cand]: L [n, max_cand,
+    3], alpha, count, hash, term_idx, n_comp, n_nodes and valid (unused
+    slots 0).  Rays whose FP64 decisions were within the filter are re-run
+    exactly, as in query()."""
+    P = prepared if prepared is not None else PreparedTree(tree, storage)
+    o = np.ascontiguousarray(o, dtype=np.float32).reshape(-1, 3)
+    d = np.ascontiguousarray(d, dtype=np.float32).reshape(-1, 3)
+    n, m = o.shape[0], int(max_cand)
+    out = {"L": np.zeros((n, m, 3)), "alpha": np.zeros((n, m)), "count": np.zeros((n, m), np.int32),
+           "hash": np.zeros((n, m), np.uint64), "term_idx": np.zeros((n, m), np.int32),
+           "n_comp": np.zeros((n, m), np.int32), "n_nodes": np.zeros((n, m), np.int32),
+           "valid": np.zeros((n, m), np.uint8)}
+    lib().orc_candidates(C.byref(P.c), o.ctypes.data, d.ctypes.data, n, int(model), int(opts), m,
+                         _ptr(out["L"]), _ptr(out["alpha"]), _ptr(out["count"]), _ptr(out["hash"]),
+                         _ptr(out["term_idx"]), _ptr(out["n_comp"]), _ptr(out["n_nodes"]),
+                         _ptr(out["valid"]), 0)
+    # rays the FP64 march could not decide: the exact path
+    flags = query(None, o, d, model=model, opts=opts, prepared=P, exact_fallback=False)["flags"]
+    redo = np.arange(n) if force_exact else np.nonzero(flags & NEED_EXACT)[0]
+    for i in redo.tolist():
+        tr = P.tree
+        segs, visited, ordinals = exact.march_octree(tr, o[i], d[i], with_ordinals=True)
+        df = np.asarray(d[i], dtype=np.float64)
+        dl = np.sqrt((df * df).sum())
+        Y = sh_eval(tr.sh_degree, -df / dl) if dl > 0 else np.zeros(25)
+        kw = dict(no_stop=bool(opts & NO_STOP), no_skip=bool(opts & NO_SKIP), sigma=P.sigma, sh=P.sh)
+        first = exact.composite(tr, segs, d[i], Y, model, force_stop=exact.FORCE_CONTINUE, **kw)
+        forces = [exact.FORCE_CONTINUE] + first["amb_tests"][: m - 1]
+        out["valid"][i] = 0
+        for c, f in enumerate(forces):
+            r = exact.composite(tr, segs, d[i], Y, model, force_stop=f, **kw)
+            out["L"][i, c] = r["L"]
+            out["alpha"][i, c] = r["alpha"]
+            out["count"][i, c] = r["count"]
+            out["hash"][i, c] = r["hash"]
+            out["term_idx"][i, c] = r["term_idx"]
+            out["n_comp"][i, c] = r["n_comp"]
+            out["n_nodes"][i, c] = ordinals[r["term_idx"]] if r["term_idx"] >= 0 else visited
+            out["valid"][i, c] = 1
     return out
 
 

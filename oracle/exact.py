@@ -211,10 +211,17 @@ def dense_dda(tree, o, d, leaf_cells):
     return out
 
 
+FORCE_CONTINUE = 1 << 30
+
+
 def composite(tree, segs, d, Y, model, no_stop=False, no_skip=False, flip_test=-1,
-              sigma=None, sh=None, eta=1e-4):
+              sigma=None, sh=None, eta=1e-4, force_stop=None):
     """FP64 compositing of an exact leaf sequence.  Returns a dict with L,
-    alpha, count, hash, term_idx, n_comp, first_amb_test."""
+    alpha, count, hash, term_idx, n_comp, first_amb_test, amb_tests (the
+    stop tests within eta of the threshold).  flip_test inverts one stop
+    test; force_stop takes another valid outcome of a threshold-ambiguous
+    ray: continue at every ambiguous test before test force_stop and stop
+    there (FORCE_CONTINUE: continue at every ambiguous test)."""
     sigma = tree.sigma.astype(np.float64) if sigma is None else sigma
     sh = tree.sh.astype(np.float64) if sh is None else sh
     df = [float(v) for v in d]
@@ -230,6 +237,7 @@ def composite(tree, segs, d, Y, model, no_stop=False, no_skip=False, flip_test=-
     tests = 0
     first_amb = -1
     weights, alphas = [], []
+    amb_tests = []
     for (leaf, mid, t0, t1) in segs:
         ids.append(mid)
         sig = float(sigma[leaf])
@@ -253,14 +261,22 @@ def composite(tree, segs, d, Y, model, no_stop=False, no_skip=False, flip_test=-
             if not no_stop:
                 alpha = 1.0 - Tr
                 stop = alpha >= amax
-                if abs(alpha - amax) <= eta and first_amb < 0:
-                    first_amb = tests
+                amb = abs(alpha - amax) <= eta
+                if amb:
+                    amb_tests.append(tests)
+                    if first_amb < 0:
+                        first_amb = tests
                 if tests == flip_test:
                     stop = not stop
+                if force_stop is not None:
+                    if tests == force_stop:
+                        stop = True
+                    elif amb:
+                        stop = False
                 tests += 1
                 if stop:
                     term = len(ids) - 1
                     break
     return {"L": L, "alpha": 1.0 - Tr, "count": len(ids), "hash": fnv(ids), "ids": ids,
-            "term_idx": term, "n_comp": n_comp, "first_amb_test": first_amb,
+            "term_idx": term, "n_comp": n_comp, "first_amb_test": first_amb, "amb_tests": amb_tests,
             "weights": weights, "alphas": alphas}

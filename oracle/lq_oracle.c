@@ -163,13 +163,36 @@ static uint32_t morton(uint32_t x, uint32_t y, uint32_t z) {
 }
 
 /* ------------------------------------------------------------ march */
+/* force_stop values besides a test index */
+#define ORC_FORCE_NONE (-1)          /* every stop test decided in FP64          */
+#define ORC_FORCE_CONTINUE 0x7fffffff /* continue at every ambiguous test       */
+
 /*
  * One ray.  flip_test >= 0 inverts the outcome of that (0-based) alpha_max
  * test: the second candidate for rays whose test is within eta of the
- * threshold.  leaf_out/max_ids optionally receive the Morton ids in order.
+ * threshold.  force_stop (when not ORC_FORCE_NONE) takes another valid
+ * outcome of a threshold-ambiguous ray: continue at every ambiguous test
+ * before test force_stop and stop at that test (ORC_FORCE_CONTINUE: continue
+ * at every ambiguous test); tests that are not ambiguous keep their FP64
+ * decision.  *forced_ok (if given) is cleared when that outcome is not a
+ * valid one: the march ended or stopped (at a test that is not ambiguous)
+ * before test force_stop, or 1 - T at that test is below alpha_max - eta.
+ * leaf_out/max_ids optionally receive the Morton ids in order.
  */
+static void march_forced(const orc_tree *T, const float *of, const float *df, int model, uint32_t opts,
+                         int flip_test, int force_stop, int *forced_ok, int *amb_list, int amb_cap,
+                         int *n_amb, orc_result *res, uint32_t *leaf_out, int max_ids);
+
 static void march(const orc_tree *T, const float *of, const float *df, int model, uint32_t opts,
                   int flip_test, orc_result *res, uint32_t *leaf_out, int max_ids) {
+    march_forced(T, of, df, model, opts, flip_test, ORC_FORCE_NONE, NULL, NULL, 0, NULL, res, leaf_out, max_ids);
+}
+
+static void march_forced(const orc_tree *T, const float *of, const float *df, int model, uint32_t opts,
+                         int flip_test, int force_stop, int *forced_ok, int *amb_list, int amb_cap,
+                         int *n_amb, orc_result *res, uint32_t *leaf_out, int max_ids) {
+    if (forced_ok) *forced_ok = 1;
+    if (n_amb) *n_amb = 0;
     memset(res, 0, sizeof(*res));
     res->term_idx = -1;
     res->first_amb_test = -1;
@@ -280,11 +303,26 @@ static void march(const orc_tree *T, const float *of, const float *df, int model
                 if (!(opts & ORC_NO_STOP)) {
                     double alpha = 1.0 - Tr;
                     int stop = alpha >= T->alpha_max;
-                    if (fabs(alpha - T->alpha_max) <= T->eta) {
+                    int amb = fabs(alpha - T->alpha_max) <= T->eta;
+                    if (amb) {
                         res->flags |= ORC_AMBIGUOUS;
                         if (res->first_amb_test < 0) res->first_amb_test = tests;
+                        if (n_amb) {
+                            if (*n_amb < amb_cap) amb_list[*n_amb] = tests;
+                            ++*n_amb;
+                        }
                     }
                     if (tests == flip_test) stop = !stop;
+                    if (force_stop != ORC_FORCE_NONE) {
+                        if (tests == force_stop) {
+                            if (!(stop || amb) && forced_ok) *forced_ok = 0;
+                            stop = 1;
+                        } else if (amb) {
+                            stop = 0;
+                        } else if (stop && tests < force_stop && force_stop != ORC_FORCE_CONTINUE && forced_ok) {
+                            *forced_ok = 0;   /* a clear stop before the forced test */
+                        }
+                    }
                     ++tests;
                     if (stop) { res->term_idx = res->count - 1; break; }
                 }
@@ -293,6 +331,9 @@ static void march(const orc_tree *T, const float *of, const float *df, int model
         t = t_next;
         ev.t = t_next; ev.ev_a = nx_a; ev.ev_k = nx_k;
     }
+    /* the march ended before the forced stop test */
+    if (force_stop != ORC_FORCE_NONE && force_stop != ORC_FORCE_CONTINUE && res->term_idx < 0 && forced_ok)
+        *forced_ok = 0;
     res->L[0] = L[0]; res->L[1] = L[1]; res->L[2] = L[2];
     res->alpha = 1.0 - Tr;
 }
@@ -336,6 +377,51 @@ int orc_query(const orc_tree *T, const float *o, const float *d, int64_t n, int 
             if (alt_hash) alt_hash[i] = A.hash;
             if (alt_term) alt_term[i] = A.term_idx;
             if (alt_valid) alt_valid[i] = 1;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Every valid outcome of a ray's alpha_max stop (the reading for rays with
+ * several stop tests within eta of the threshold: each of them may go
+ * either way, so the march may stop at any of them, or continue through all
+ * of them; tests outside eta keep their FP64 decision).  Since 1 - T never
+ * decreases, the ambiguous tests all come before the first clear stop, and
+ * the outcomes are: candidate 0, continue at every ambiguous test; candidate
+ * c = 1, 2, ..., stop at the c-th ambiguous test.  Outputs [n][max_cand]
+ * (any may be NULL except valid): L [..][3], alpha, count, hash, term_idx,
+ * n_comp, n_nodes, valid (1 for a candidate, 0 for unused slots).  A ray
+ * with no ambiguous test has one candidate, the canonical outcome; a ray
+ * with more than max_cand - 1 ambiguous tests gets the first ones.
+ */
+int orc_candidates(const orc_tree *T, const float *o, const float *d, int64_t n, int model, uint32_t opts,
+                   int max_cand, double *L, double *alpha, int32_t *count, uint64_t *hash,
+                   int32_t *term_idx, int32_t *n_comp, int32_t *n_nodes, uint8_t *valid, int n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int amb[64];
+        int n_amb = 0;
+        for (int c = 0; c < max_cand; ++c) valid[(size_t)i * max_cand + c] = 0;
+        for (int c = 0; c < max_cand; ++c) {
+            if (c > 0 && c > (n_amb < 64 ? n_amb : 64)) break;
+            orc_result A;
+            int ok = 1;
+            const int force = c == 0 ? ORC_FORCE_CONTINUE : amb[c - 1];
+            march_forced(T, o + 3 * i, d + 3 * i, model, opts, -1, force, &ok, c == 0 ? amb : NULL,
+                         c == 0 ? 64 : 0, c == 0 ? &n_amb : NULL, &A, NULL, 0);
+            const size_t j = (size_t)i * max_cand + c;
+            if (L) { L[3 * j] = A.L[0]; L[3 * j + 1] = A.L[1]; L[3 * j + 2] = A.L[2]; }
+            if (alpha) alpha[j] = A.alpha;
+            if (count) count[j] = A.count;
+            if (hash) hash[j] = A.hash;
+            if (term_idx) term_idx[j] = A.term_idx;
+            if (n_comp) n_comp[j] = A.n_comp;
+            if (n_nodes) n_nodes[j] = A.n_nodes_visited;
+            valid[j] = (uint8_t)ok;
         }
     }
     return 0;

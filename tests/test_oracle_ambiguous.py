@@ -160,3 +160,52 @@ def test_no_stop_has_no_second_candidate():
     sig, _ = _densities(core.LINEAR, 1, 4e-5)
     r = core.query(_tree(sig), O, D, model=core.LINEAR, opts=core.NO_STOP)
     assert r["alt_valid"][0] == 0 and r["term_idx"][0] == -1 and r["count"][0] == 4
+
+
+def _densities_two(model, first_offset, second_offset):
+    """Densities putting 1 - T at AMAX + first_offset after leaf 0 and at
+    AMAX + second_offset after leaf 1 (two ambiguous tests in a row), then a
+    saturating leaf."""
+    dlt = _deltas()
+    a0, a1 = AMAX + first_offset, AMAX + second_offset
+    if model == core.LINEAR:
+        s0, s1 = a0 / dlt[0], (a1 - a0) / dlt[1]
+    else:
+        s0 = -math.log(1.0 - a0) / dlt[0]
+        s1 = (-math.log(1.0 - a1) + math.log(1.0 - a0)) / dlt[1]
+    sig = [s0, s1, 40.0, 1.0]
+    return [float(np.float32(s)) for s in sig], dlt
+
+
+@pytest.mark.parametrize("exact_path", [False, True])
+@pytest.mark.parametrize("model", [core.LINEAR, core.EXP])
+@pytest.mark.parametrize("offsets", [(-6e-5, 3e-5), (-8e-5, -2e-5), (2e-5, 7e-5)])
+def test_every_outcome_of_two_ambiguous_tests(exact_path, model, offsets):
+    """Two stop tests in a row within eta of the threshold: each may go
+    either way, so the valid outcomes are stop at the first, stop at the
+    second, or continue through both (and stop at the saturating third
+    leaf).  candidates() lists exactly these, in that order after the
+    continue-through one, each equal to its closed form; the canonical
+    outcome of query() is one of them.  (The second leaf adds under 1e-4 to
+    1 - T, so its density is below sigma_min: the skip is off here.)"""
+    sig, dlt = _densities_two(model, *offsets)
+    a0, a1 = _closed(sig, dlt, model, 0)[1], _closed(sig, dlt, model, 1)[1]
+    assert abs(a0 - AMAX) <= core.ETA and abs(a1 - AMAX) <= core.ETA
+    assert _closed(sig, dlt, model, 2)[1] >= AMAX + core.ETA
+    tree = _tree(sig)
+    c = core.candidates(tree, O, D, model=model, opts=core.NO_SKIP, force_exact=exact_path)
+    assert list(c["valid"][0]) == [1, 1, 1, 0, 0, 0, 0, 0]
+    ids = [_morton(*cell) for cell in CELLS]
+    for slot, stop_at in ((0, 2), (1, 0), (2, 1)):
+        L, a = _closed(sig, dlt, model, stop_at)
+        assert c["L"][0, slot, 0] == pytest.approx(L, rel=1e-12)
+        assert c["alpha"][0, slot] == pytest.approx(a, rel=1e-12)
+        assert c["count"][0, slot] == stop_at + 1 and c["term_idx"][0, slot] == stop_at
+        assert int(c["hash"][0, slot]) == _fnv(ids[:stop_at + 1])
+    r = core.query(tree, O, D, model=model, opts=core.NO_SKIP)
+    canon = 0 if offsets[0] >= 0 else (1 if offsets[1] >= 0 else 2)
+    assert r["term_idx"][0] == canon
+    # one clear test: a single candidate, the canonical outcome
+    sig1, _ = _densities(model, 1, 3e-4)
+    c1 = core.candidates(_tree(sig1), O, D, model=model, force_exact=exact_path)
+    assert list(c1["valid"][0]) == [1, 0, 0, 0, 0, 0, 0, 0] and c1["term_idx"][0, 0] == 1

@@ -151,3 +151,33 @@ def test_exact_path_records_match_fp64_path(c0_tree):
         for key in ("count", "hash", "term_idx", "n_comp", "n_nodes", "leaf_ids"):
             assert np.array_equal(a[key], b[key]), key
         np.testing.assert_allclose(a["L"], b["L"], rtol=1e-8, atol=1e-300)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_pruned_tree_structure_and_march(c0_tree, storage):
+    """The pruned tree (the table the production query marches) holds
+    exactly the leaves whose stored density is >= sigma_min, every internal
+    node has a child, and marching it with the skip off composites the same
+    leaves over the same segments as marching the whole tree with the skip
+    on (Sec. 6.2): identical FP64 radiance, alpha, stop, and the leaf count
+    of the pruned march equals the composited count of the full one."""
+    for tree in (c0_tree, inputs.random_tree(4, 0.5, seed=7, sigma_range=(0.02, 50.0))):
+        p = core.pruned_tree(tree, storage)
+        kept = core.dequantize(tree.sigma, storage) >= float(np.float32(0.1))
+        leaves = -p.child[p.child < 0] - 1
+        assert np.array_equal(np.sort(leaves), np.nonzero(kept)[0])
+        assert np.all((p.child != 0).any(1)) or p.n_nodes == 1
+        # every node below the root is referenced exactly once
+        refs = p.child[p.child > 0]
+        assert np.array_equal(np.sort(refs), np.arange(1, p.n_nodes))
+        assert p.n_nodes <= tree.n_nodes
+        o, d = inputs.rays.sphere_to_cube(3000, 17)
+        for model in (core.LINEAR, core.EXP):
+            a = core.query(tree, o, d, model=model, storage=storage)
+            b = core.query(p, o, d, model=model, opts=core.NO_SKIP, storage=storage)
+            assert np.array_equal(a["L"], b["L"]) and np.array_equal(a["alpha"], b["alpha"])
+            assert np.array_equal(a["n_comp"], b["count"]) and np.array_equal(b["count"], b["n_comp"])
+            stopped = a["term_idx"] >= 0
+            assert np.array_equal(stopped, b["term_idx"] >= 0)
+            assert np.all(b["term_idx"][stopped] == b["count"][stopped] - 1)
+            assert np.all(b["n_nodes"] <= a["n_nodes"])
