@@ -9,10 +9,17 @@ with a 40 degree field of view; linear transmittance, sigma_min = 0.1,
 alpha_max = 0.9.
 
 Prints one JSON line (rays/s) with the dominant kernel's roofline fraction
-(algorithmic bytes per launch / measured launch time vs 8 TB/s) and the
-CPU oracle's throughput on a bounded sample of the same rays.  Extra
-variants (float16/bfloat16 storage, exponential transmittance, incoherent
-room queries) are reported under "variants".
+(algorithmic bytes per launch / measured launch time vs 8 TB/s; the bytes
+are counted on the table the timed kernel marches) and the CPU oracle's
+throughput on a bounded sample of the same rays.  Extra variants
+(float16/bfloat16 storage, exponential transmittance, incoherent room
+queries, the learned surrogate with octree fallback, the consumer side, the
+uneven 16-luminaire batch) are reported under "variants".
+
+The CPU leg is the only part that runs the oracle: it times it, and it
+compares the GPU outputs of every variant, on a seeded sample of its rays,
+with it (the "error" records), and states the bias of the render
+heuristics (sigma_min skip and alpha_max stop) on the camera and room rays.
 """
 from __future__ import annotations
 
@@ -63,9 +70,22 @@ def time_launches(fn, steps, warmup):
 
 
 def alg_bytes(trace, K, elem_bytes):
-    """Bytes the method must move per launch: rays in (24 B), RGB + alpha out
-    (16 B), a density per data leaf visited, 3K SH coefficients per leaf
-    composited, one 4-byte child slot per octree node visited."""
+    """Bytes the method must move per launch, counted on the table the
+    production query marches (a trace with LQ_TRACE_PRUNED: only the leaves
+    it composites, the nodes of that table it visits): rays in (24 B), RGB +
+    alpha out (16 B), per composited leaf its density and 3K SH coefficients,
+    one 4-byte child slot per octree node visited."""
+    n = trace["count"].numel()
+    comp = int(trace["n_comp"].sum())
+    steps = int(trace["n_steps"].sum())
+    return 40 * n + comp * (1 + 3 * K) * elem_bytes + steps * 4, {
+        "rays": n, "mean_composited": comp / n, "mean_nodes": steps / n}
+
+
+def alg_bytes_full_table(trace, K, elem_bytes):
+    """The same formula on the full table (the validation trace): a density
+    per data leaf visited, including those below sigma_min that the
+    production query never reads, and the nodes of the full table."""
     n = trace["count"].numel()
     occ = int(trace["count"].sum())
     comp = int(trace["n_comp"].sum())
@@ -74,12 +94,13 @@ def alg_bytes(trace, K, elem_bytes):
         "rays": n, "mean_leaves": occ / n, "mean_composited": comp / n, "mean_nodes": steps / n}
 
 
-def variant_record(oc, o, d, model, K, elem_bytes, vms, traffic_tag=None):
+def variant_record(lumiq, oc, o, d, model, K, elem_bytes, vms, traffic_tag=None):
     """rays/s of a timed query launch and its algorithmic bytes against the
-    HBM peak (per-ray counts from a trace launch over the same rays), plus the
-    measured HBM bytes per launch where a counter summary exists."""
+    HBM peak (per-ray counts from a trace of the pruned table over the same
+    rays), plus the measured HBM bytes per launch where a counter summary
+    exists."""
     n = o.shape[0]
-    nbytes, counts = alg_bytes(oc.trace(o, d, model=model), K, elem_bytes)
+    nbytes, counts = alg_bytes(oc.trace(o, d, model=model, flags=lumiq.LQ_TRACE_PRUNED), K, elem_bytes)
     achieved = nbytes / (vms * 1e-3) / 1e9
     rec = {"rays_per_s": n / (vms * 1e-3), "ms_per_step": vms, "alg_bytes_per_launch": nbytes,
            "achieved_gbs": round(achieved, 1), "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -109,13 +130,44 @@ def traffic_from_profiles(kernel_tag):
         return None
 
 
+def host_info():
+    """The host the CPU leg runs on: logical CPUs, the CPUs this process may
+    run on (affinity and cgroup quota), OMP_NUM_THREADS and the CPU model."""
+    info = {"nproc": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except Exception:
+        info["affinity"] = os.cpu_count()
+    info["cgroup_cpu_quota"] = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            info["cgroup_cpu_quota"] = float(q) / float(per)
+    except Exception:
+        pass
+    info["cpu_model"] = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    usable = info["affinity"] or 1
+    if info["cgroup_cpu_quota"]:
+        usable = min(usable, max(1, int(info["cgroup_cpu_quota"])))
+    info["usable_cores"] = usable
+    return info
+
+
 def cpu_baseline(tree, o, d, budget_s):
-    """The FP64 oracle on the host cores, on a seeded sample of the rays,
-    chunk by chunk until the time budget is spent; then the same oracle on
-    one thread for a fifth of the budget."""
+    """The FP64 oracle on every core this process may use, on a seeded
+    sample of the rays, chunk by chunk until the time budget is spent; then
+    the same oracle on one thread for a fifth of the budget."""
     import numpy as np
     from oracle import core
-    threads = max(1, min(16, os.cpu_count() or 1))
+    host = host_info()
+    threads = host["usable_cores"]
     P = core.PreparedTree(tree, "f32")
     rng = np.random.default_rng(123)
     order = rng.permutation(len(o))
@@ -142,13 +194,137 @@ def cpu_baseline(tree, o, d, budget_s):
     t_mlp = time.perf_counter() - t0
     return {"value": done / t_total, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} of the {len(o)} camera rays (seeded random subset), FP64 oracle "
-                      f"with its OpenMP loop over rays, {t_total:.1f} s",
+                      f"with its OpenMP loop over rays on {threads} threads, {t_total:.1f} s",
+            "host": host,
             "one_thread": {"value": done1 / t1, "unit": "rays/s", "sample": f"{done1} rays, {t1:.1f} s"},
             "surrogate_oracle": {"value": len(ro) / t_mlp, "unit": "rays/s",
                                  "sample": f"{len(ro)} room rays, numpy FP64 forward, {t_mlp:.2f} s"}}
 
 
-def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
+ERROR_SAMPLE = 20000
+
+
+def sample_index(n, seed):
+    import numpy as np
+    m = min(n, ERROR_SAMPLE)
+    return np.sort(np.random.default_rng(seed).choice(n, m, replace=False))
+
+
+def keep_sample(samples, name, rgb, alpha, idx, **meta):
+    """Keep the GPU outputs of a variant on a seeded sample of its rays for
+    the CPU leg's error records."""
+    import torch
+    it = torch.from_numpy(idx).to(rgb.device)
+    samples[name] = {"idx": idx, "rgb": rgb[it].cpu().numpy(),
+                     "alpha": None if alpha is None else alpha[it].cpu().numpy(), **meta}
+
+
+def error_records(samples, trees, rays):
+    """Error of every sampled variant against the FP64 oracle (each ray
+    against the nearer of its candidates when its alpha_max test is within
+    1e-4 of the threshold), on the tree as stored; for float16 / bfloat16
+    storage also the storage error against the float32 tree; for the
+    surrogate against the oracle on the float32 tree.  Per ray and channel
+    the error is |L - L_ref| / max(|L_ref|, 1e-6 L_max)."""
+    import numpy as np
+    from oracle import core
+    out, cache = {}, {}
+
+    def oracle(tree_key, storage, model, ray_key, idx):
+        key = (tree_key, storage, model, ray_key)
+        if key not in cache:
+            o, d = rays[ray_key]
+            cache[key] = core.query(trees[tree_key], o[idx], d[idx], model=model, storage=storage)
+        return cache[key]
+
+    def stats(rgb, alpha, orc, lmax):
+        g = np.asarray(rgb, np.float64)
+        fl = 1e-6 * lmax
+        e_main = (np.abs(g - orc["L"]) / np.maximum(np.abs(orc["L"]), fl)).max(1)
+        e_alt = (np.abs(g - orc["alt_L"]) / np.maximum(np.abs(orc["alt_L"]), fl)).max(1)
+        alt = orc["alt_valid"].astype(bool) & (e_alt < e_main)
+        err = np.where(alt, e_alt, e_main)
+        ref = np.where(alt[:, None], orc["alt_L"], orc["L"])
+        rec = {"rays": int(len(err)), "max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
+               "median_rel": float(np.median(err)),
+               "rel_l2": float(np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-300)),
+               "n_ambiguous": int(orc["alt_valid"].sum())}
+        if alpha is not None:
+            ra = np.where(alt, orc["alt_alpha"], orc["alpha"])
+            rec["max_alpha_err"] = float(np.abs(np.asarray(alpha, np.float64) - ra).max())
+        return rec
+
+    for name, smp in samples.items():
+        idx, kind = smp["idx"], smp.get("kind", "octree")
+        if kind == "uneven":
+            recs = []
+            tk = smp["tree_of"]
+            for k in np.unique(tk):
+                sel = tk == k
+                o, d = rays["uneven"]
+                orc = core.query(trees[("uneven", int(k))], o[idx[sel]], d[idx[sel]], model=core.LINEAR,
+                                 storage="f16")
+                recs.append((sel, orc))
+            L = np.zeros((len(idx), 3))
+            A = np.zeros(len(idx))
+            merged = {"L": L, "alt_L": np.zeros_like(L), "alpha": A, "alt_alpha": np.zeros_like(A),
+                      "alt_valid": np.zeros(len(idx), np.uint8)}
+            for sel, orc in recs:
+                for key in merged:
+                    merged[key][sel] = orc[key]
+            rec = stats(smp["rgb"], smp["alpha"], merged, 2048.0)
+            rec["vs"] = "FP64 oracle on each luminaire's float16 tree"
+            out[name] = rec
+            continue
+        model = core.EXP if smp.get("model") == "exp" else core.LINEAR
+        tree_key, storage, ray_key = smp["tree"], smp.get("storage", "f32"), smp["rays"]
+        lmax = trees[tree_key].l_max
+        if kind == "surrogate":
+            ref = oracle(tree_key, "f32", core.LINEAR, ray_key, idx)
+            g = np.asarray(smp["rgb"], np.float64)
+            err = (np.abs(g - ref["L"]) / np.maximum(np.abs(ref["L"]), 1e-6 * lmax)).max(1)
+            out[name] = {"rays": int(len(g)), "vs": "FP64 oracle on the float32 tree",
+                         "rel_l2": float(np.linalg.norm(g - ref["L"]) / np.linalg.norm(ref["L"])),
+                         "p99_rel": float(np.quantile(err, 0.99)), "median_rel": float(np.median(err))}
+            continue
+        rec = stats(smp["rgb"], smp["alpha"], oracle(tree_key, storage, model, ray_key, idx), lmax)
+        rec["vs"] = f"FP64 oracle on the tree as stored ({storage})"
+        if storage != "f32":
+            ref = oracle(tree_key, "f32", model, ray_key, idx)
+            g = np.asarray(smp["rgb"], np.float64)
+            e = (np.abs(g - ref["L"]) / np.maximum(np.abs(ref["L"]), 1e-6 * lmax)).max(1)
+            rec["storage_error_vs_f32_tree"] = {
+                "max_rel": float(e.max()), "p99_rel": float(np.quantile(e, 0.99)),
+                "median_rel": float(np.median(e)),
+                "rel_l2": float(np.linalg.norm(g - ref["L"]) / np.linalg.norm(ref["L"]))}
+        out[name] = rec
+    return out
+
+
+def heuristic_bias(tree, rays):
+    """Bias of the render heuristics (Sec. 6.2: sigma_min skip, alpha_max
+    stop) on a seeded sample of each ray set: the oracle with them (L)
+    against the oracle without them (L*, the exact integral of the
+    piecewise-constant field)."""
+    import numpy as np
+    from oracle import core
+    out = {}
+    for key, (o, d) in rays.items():
+        idx = sample_index(len(o), 17)
+        L = core.query(tree, o[idx], d[idx], model=core.LINEAR)
+        F = core.query(tree, o[idx], d[idx], model=core.LINEAR, opts=core.NO_SKIP | core.NO_STOP)
+        fl = 1e-6 * tree.l_max
+        e = (np.abs(L["L"] - F["L"]) / np.maximum(np.abs(F["L"]), fl)).max(1)
+        out[key] = {"rays": int(len(idx)),
+                    "rel_l2": float(np.linalg.norm(L["L"] - F["L"]) / np.linalg.norm(F["L"])),
+                    "median_rel": float(np.median(e)), "p99_rel": float(np.quantile(e, 0.99)),
+                    "max_rel": float(e.max()),
+                    "mean_alpha": float(L["alpha"].mean()), "mean_alpha_exact": float(F["alpha"].mean()),
+                    "mean_composited": float(L["n_comp"].mean()), "mean_composited_exact": float(F["n_comp"].mean())}
+    return out
+
+
+def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf, samples=None, sample_idx=None):
     """Learned surrogate: trained on (ray, radiance) pairs that the float32
     octree renders for incoherent room rays, trust map from held-out pairs
     at 1% relative error (30,000,000 held-out rays), then inference with
@@ -191,6 +367,10 @@ def surrogate_variant(args, lumiq, tree, oct32, qo, qd, qref_buf):
     def rel_l2(a, b):
         return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
 
+    if samples is not None:
+        keep_sample(samples, "surrogate_only", pred, None, sample_idx, kind="surrogate", tree="c1", rays="room")
+        keep_sample(samples, "surrogate_with_fallback", out, None, sample_idx, kind="surrogate", tree="c1",
+                    rays="room")
     res = {
         "train_steps": args.surrogate_steps, "train_pairs": args.surrogate_pairs, "batch": 65536,
         "lr": [lr0, lr0 / 100], "train_s": round(t_train, 2),
@@ -257,7 +437,7 @@ def floor_variant(inputs, oct32, steps):
     return rec
 
 
-def uneven_variant(lumiq):
+def uneven_variant(lumiq, samples=None, trees_out=None, rays_out=None):
     """The uneven multi-luminaire batch (16 trees of depth 6 to 10, SH degree
     3, float16, log-uniform ray counts): one persistent launch over all rays
     against one launch per luminaire; load balance = sum of the isolated
@@ -275,6 +455,14 @@ def uneven_variant(lumiq):
     rgb = torch.empty((n, 3), device="cuda")
     alpha = torch.empty((n,), device="cuda")
     ms_one, _ = time_launches(lambda: lumiq.query_multi(octs, offs, ot, dt, rgb=rgb, alpha=alpha), 10, 3)
+    if samples is not None:
+        import numpy as np
+        idx = sample_index(n, 29)
+        keep_sample(samples, "uneven_batch", rgb, alpha, idx, kind="uneven",
+                    tree_of=np.searchsorted(offs, idx, side="right") - 1)
+        for k, t in enumerate(trees):
+            trees_out[("uneven", k)] = t
+        rays_out["uneven"] = (o, d)
     iso = []
     for k, oc in enumerate(octs):
         a, b = int(offs[k]), int(offs[k + 1])
@@ -349,8 +537,9 @@ def main():
     ap.add_argument("--sh-sweep", action="store_true",
                     help="also time SH degrees 0..4 x linear/exponential on the depth-9 geometry "
                          "(generates a degree-4 tree: a minute of CPU)")
-    ap.add_argument("--uneven", action="store_true",
-                    help="also run the uneven 16-luminaire batch (generates depth-10 trees: minutes of CPU)")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven 16-luminaire batch (it generates three depth-10 trees: a minute "
+                         "or more of CPU)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -400,36 +589,55 @@ def main():
         log("copy probe: 1 GiB read + 1 GiB written")
         del src, dst
 
+    samples = {}
+    keep_sample(samples, "headline", rgb, alpha, sample_index(n, 11), tree="c1", rays="camera")
+    trp = oct32.trace(o, d, model="linear", flags=lumiq.LQ_TRACE_PRUNED)
     tr = oct32.trace(o, d, model="linear")
     torch.cuda.synchronize()
-    nbytes, counts = alg_bytes(tr, tree.K, 4)
+    nbytes, counts = alg_bytes(trp, tree.K, 4)
+    full_bytes, full_counts = alg_bytes_full_table(tr, tree.K, 4)
+    del trp, tr
     achieved = nbytes / (ms * 1e-3) / 1e9
     traffic = traffic_from_profiles("query_f32_camera")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": nbytes, "per_ray": counts,
+                "full_table": {"alg_bytes_per_launch": full_bytes, "per_ray": full_counts,
+                               "frac": round(full_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "note": "counts of the validation trace over the full table (densities of "
+                                       "leaves below sigma_min and nodes the timed kernel never visits)"},
                 "kernel": "k_query_plain<F32, SH deg 2, sigma_min-pruned table, linear, 8x8 pixel tiles>",
                 "kernel_sources": kernel_sources_hash()}
 
     variants = {}
+    trees = {"c1": tree}
+    rays = {"camera": (o_np, d_np)}
     if not args.no_variants:
         for storage in ("f16", "bf16"):
             oc = lumiq.Octree(tree, storage)
             vms, _ = time_launches(lambda: oc.query_image(o, d, 2048, 2048, model="linear", rgb=rgb, alpha=alpha),
                                    max(5, args.steps // 2), 2)
-            variants[f"camera_{storage}_linear"] = variant_record(oc, o, d, "linear", tree.K, 2, vms)
+            keep_sample(samples, f"camera_{storage}_linear", rgb, alpha, sample_index(n, 11), tree="c1",
+                        rays="camera", storage=storage)
+            variants[f"camera_{storage}_linear"] = variant_record(lumiq, oc, o, d, "linear", tree.K, 2, vms)
             log(f"{storage}: {vms:.3f} ms/step")
             oc.free()
         vms, _ = time_launches(lambda: oct32.query_image(o, d, 2048, 2048, model="exp", rgb=rgb, alpha=alpha),
                                max(5, args.steps // 2), 2)
-        variants["camera_f32_exp"] = variant_record(oct32, o, d, "exp", tree.K, 4, vms)
+        keep_sample(samples, "camera_f32_exp", rgb, alpha, sample_index(n, 11), tree="c1", rays="camera",
+                    model="exp")
+        variants["camera_f32_exp"] = variant_record(lumiq, oct32, o, d, "exp", tree.K, 4, vms)
         # the same camera batch through the batch-order entry point (row by row)
         vms, _ = time_launches(lambda: oct32.query(o, d, model="linear", rgb=rgb, alpha=alpha),
                                max(5, args.steps // 2), 2)
-        variants["camera_f32_linear_row_order"] = variant_record(oct32, o, d, "linear", tree.K, 4, vms)
+        keep_sample(samples, "camera_f32_linear_row_order", rgb, alpha, sample_index(n, 11), tree="c1",
+                    rays="camera")
+        variants["camera_f32_linear_row_order"] = variant_record(lumiq, oct32, o, d, "linear", tree.K, 4, vms)
         log(f"f32 linear, row order: {vms:.3f} ms/step")
         # incoherent shading queries from a room around the luminaire
         ro, rd = inputs.rays.room_to_proxy(1 << 24, 20)
+        rays["room"] = (ro, rd)
+        ridx = sample_index(len(ro), 13)
         ro_t, rd_t = torch.from_numpy(ro).cuda(), torch.from_numpy(rd).cuda()
         rrgb = torch.empty((1 << 24, 3), device="cuda")
         ralpha = torch.empty((1 << 24,), device="cuda")
@@ -437,14 +645,17 @@ def main():
             oc = oct32 if storage == "f32" else lumiq.Octree(tree, storage)
             vms, _ = time_launches(lambda: oc.query(ro_t, rd_t, model="linear", rgb=rrgb, alpha=ralpha),
                                    max(3, args.steps // 4), 1)
+            keep_sample(samples, f"room16M_{storage}_linear", rrgb, ralpha, ridx, tree="c1", rays="room",
+                        storage=storage)
             variants[f"room16M_{storage}_linear"] = variant_record(
-                oc, ro_t, rd_t, "linear", tree.K, 4 if storage == "f32" else 2, vms,
+                lumiq, oc, ro_t, rd_t, "linear", tree.K, 4 if storage == "f32" else 2, vms,
                 traffic_tag=f"query_{storage}_room")
             log(f"room {storage}: {vms:.3f} ms/step")
             if storage != "f32":
                 oc.free()
         if args.surrogate_steps > 0:
-            variants["surrogate"] = surrogate_variant(args, lumiq, tree, oct32, ro_t, rd_t, rrgb)
+            variants["surrogate"] = surrogate_variant(args, lumiq, tree, oct32, ro_t, rd_t, rrgb,
+                                                      samples=samples, sample_idx=ridx)
         del ro_t, rd_t, rrgb, ralpha
 
     if not args.no_variants:
@@ -453,14 +664,25 @@ def main():
     if args.sh_sweep:
         variants["sh_sweep_camera"] = sh_sweep_variant(lumiq, o, d, max(5, args.steps // 2))
 
-    if args.uneven:
-        variants["uneven_batch"] = uneven_variant(lumiq)
+    if not args.no_variants and not args.no_uneven:
+        variants["uneven_batch"] = uneven_variant(lumiq, samples=samples, trees_out=trees, rays_out=rays)
 
     cpu = None
+    error = None
     if not args.no_cpu:
         log("timing the CPU oracle")
         cpu = cpu_baseline(tree, o_np, d_np, args.cpu_budget)
         log(f"cpu oracle: {cpu['value']:.0f} rays/s on {cpu['cores']} threads")
+        t0 = time.perf_counter()
+        errs = error_records(samples, trees, rays)
+        error = errs.pop("headline")
+        for name, rec in errs.items():
+            if name in ("surrogate_only", "surrogate_with_fallback"):
+                variants["surrogate"][name]["error"] = rec
+            else:
+                variants[name]["error"] = rec
+        cpu["heuristic_bias"] = heuristic_bias(tree, {k: rays[k] for k in ("camera", "room") if k in rays})
+        log(f"error records and heuristic bias: {time.perf_counter() - t0:.1f} s")
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "rays/s", "n_gpus": 1,
@@ -473,7 +695,7 @@ def main():
                    "rays": n, "n_leaves": tree.n_leaves, "n_nodes": tree.n_nodes,
                    "sh_degree": tree.sh_degree, "storage": "f32", "transmittance": "linear",
                    "sigma_min": 0.1, "alpha_max": 0.9},
-        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "error": error, "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

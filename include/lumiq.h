@@ -60,7 +60,8 @@ enum { LQ_LINEAR = 0, LQ_EXP = 1 };
 enum {
     LQ_NO_EARLY_TERM = 1,   /* march to the far proxy hit (no alpha_max stop)    */
     LQ_FP64_ACCUM = 2,      /* validation: accumulate T, weights and L in FP64   */
-    LQ_NO_SIGMA_SKIP = 4    /* composite every data leaf (no sigma_min skip)     */
+    LQ_NO_SIGMA_SKIP = 4,   /* composite every data leaf (no sigma_min skip)     */
+    LQ_TRACE_PRUNED = 8     /* lq_query_trace only: see there                    */
 };
 
 typedef struct lq_octree lq_octree;   /* opaque, library-owned */
@@ -156,6 +157,13 @@ lq_status lq_query_radiance_image(const lq_octree *tree, const float *origins, c
  *                nodes, each reached by one descent), up to the stop;
  *   leaf_ids     optional [n][max_ids]: the first max_ids leaf ids.
  * rgb/alpha may be NULL.  All arrays are device pointers.
+ * With LQ_TRACE_PRUNED the trace marches the table that lq_query_radiance
+ * marches: the tree without the data leaves whose stored density is below
+ * sigma_min and without the nodes they leave empty (Sec. 6.2: those leaves
+ * are never composited).  Radiance and alpha are those the production
+ * query computes; the records then list only the composited leaves (count
+ * = n_comp) and n_steps counts the nodes of that table visited -- the work
+ * of the production query.  It combines with LQ_NO_EARLY_TERM only.
  */
 lq_status lq_query_trace(const lq_octree *tree, const float *origins, const float *dirs,
                          int64_t n, float *rgb, float *alpha, int model, uint32_t flags,
@@ -169,7 +177,11 @@ lq_status lq_query_trace(const lq_octree *tree, const float *origins, const floa
  * n_trees + 1 non-decreasing values starting at 0; origins/dirs/rgb/alpha
  * are device arrays of ray_offsets[n_trees] rays.  Every tree must live on
  * the same device and share its storage and SH degree, which must be 2 or 3
- * (else LQ_ERR_UNSUPPORTED).  Same per-ray semantics as lq_query_radiance.
+ * (else LQ_ERR_UNSUPPORTED); ray_offsets[n_trees] must not exceed 2^40.
+ * Same per-ray semantics as lq_query_radiance.  The trees' device
+ * descriptors and the offsets are staged from host memory through
+ * stream-ordered scratch: the call synchronises hip_stream once, before
+ * the launch, so that the host copies are complete when it returns.
  */
 lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees,
                                   const int64_t *ray_offsets, const float *origins,
@@ -286,8 +298,12 @@ lq_status lq_mlp_trust_map(const lq_mlp *mlp, uint8_t *host_map, int32_t *n_bins
 
 /*
  * Surrogate with octree fallback.  A classification pass splits the batch on
- * the device: rays whose line misses the bounding sphere get radiance 0,
- * rays in trusted bins go to a surrogate list, the rest to an octree list.
+ * the device.  The network models the radiance of a whole line, which a ray
+ * sees only when the bounding sphere lies wholly ahead of its origin: rays
+ * whose line misses the sphere, or whose sphere lies wholly behind them, get
+ * radiance 0; rays that start inside the sphere go to the octree list; the
+ * others go to a surrogate list when their trust bin is trusted, else to
+ * the octree list.
  * The surrogate then answers only its list and lq_query_radiance on
  * `fallback` (linear model, default flags) only the other;
  * used_fallback[n] (device, nullable) marks the rays the octree answered.

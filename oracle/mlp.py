@@ -73,6 +73,28 @@ def sphere_param(o, d):
     return x6, hit
 
 
+ROUTE_NET, ROUTE_OCTREE, ROUTE_ZERO = 0, 1, 2
+
+
+def route(o, d):
+    """Which path answers a ray of the hybrid query.  The network models the
+    radiance of a whole line (the proxy chord the line crosses); a ray sees
+    that whole chord only when the bounding sphere, and so the box inside it,
+    lies wholly ahead of its origin.  ROUTE_ZERO: the line misses the sphere
+    or the sphere lies wholly behind (radiance 0); ROUTE_OCTREE: the origin
+    is inside the sphere; ROUTE_NET: the sphere lies ahead (then both
+    crossing parameters, whose product is |o|^2 - 3 > 0, are positive)."""
+    o = np.asarray(o, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    _, hit = sphere_param(o, d)
+    c = (o * o).sum(1) - R2
+    ahead = (o * d).sum(1) < 0.0
+    out = np.full(o.shape[0], ROUTE_ZERO, np.int32)
+    out[hit & (c > 0) & ahead] = ROUTE_NET
+    out[hit & ~(c > 0)] = ROUTE_OCTREE
+    return out
+
+
 def features(x6):
     x6 = np.asarray(x6, dtype=np.float64)
     n = x6.shape[0]

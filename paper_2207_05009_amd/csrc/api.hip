@@ -411,8 +411,10 @@ static lq_status query_common(const lq_octree *t, const QueryArgs &a, bool trace
     if (!t) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");
     if (a.n < 0) return fail(LQ_ERR_INVALID_ARG, "n must be >= 0");
     if (a.model != LQ_LINEAR && a.model != LQ_EXP) return fail(LQ_ERR_INVALID_ARG, "model must be LQ_LINEAR or LQ_EXP");
-    if (a.flags & ~(uint32_t)(LQ_NO_EARLY_TERM | LQ_FP64_ACCUM | LQ_NO_SIGMA_SKIP))
-        return fail(LQ_ERR_INVALID_ARG, "unknown flag bits");
+    const uint32_t known = LQ_NO_EARLY_TERM | LQ_FP64_ACCUM | LQ_NO_SIGMA_SKIP | (trace ? LQ_TRACE_PRUNED : 0u);
+    if (a.flags & ~known) return fail(LQ_ERR_INVALID_ARG, "unknown flag bits");
+    if ((a.flags & LQ_TRACE_PRUNED) && (a.flags & (LQ_FP64_ACCUM | LQ_NO_SIGMA_SKIP)))
+        return fail(LQ_ERR_INVALID_ARG, "LQ_TRACE_PRUNED combines with LQ_NO_EARLY_TERM only");
     if (a.n > ((int64_t)1 << 40)) return fail(LQ_ERR_INVALID_ARG, "n too large");
     if (a.n == 0) return LQ_OK;
     hipError_t e = hipSetDevice(t->device);
@@ -524,6 +526,7 @@ lq_status lq_query_radiance_multi(const lq_octree *const *trees, int32_t n_trees
     if (trees[0]->t.sh_degree != 2 && trees[0]->t.sh_degree != 3)
         return fail(LQ_ERR_UNSUPPORTED, "the multi-tree query is built for SH degrees 2 and 3");
     const int64_t n = ray_offsets[n_trees];
+    if (n > ((int64_t)1 << 40)) return fail(LQ_ERR_INVALID_ARG, "ray_offsets[n_trees] too large");
     QueryArgs a{};
     a.o = origins;
     a.d = dirs;

@@ -805,15 +805,19 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
                 if (act) {
                     const float p6[6] = {e0, e1, e2, e3, e4, e5};
                     const int bin = trust_bin(p6);
-                    double se = 0.0, sr = 0.0;
+                    // float32 sums of three squares (relative error under
+                    // 8 u each); the error side is inflated by 2^-20 = 16 u,
+                    // so a pair at the bound counts as outside (conservative)
+                    float se = 0.0f, sr = 0.0f;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const double rc = ref[3 * ray + c];
-                        se += ((double)L[c] - rc) * ((double)L[c] - rc);
-                        sr += rc * rc;
+                        const float rc = ref[3 * ray + c];
+                        const float ec = L[c] - rc;
+                        se = fmaf(ec, ec, se);
+                        sr = fmaf(rc, rc, sr);
                     }
                     atomicAdd(tcnt + bin, 1u);
-                    if (se > (double)max_rel2 * sr + (double)abs_floor2) atomicAdd(tbad + bin, 1u);
+                    if (se * (1.0f + 0x1p-20f) > fmaf(max_rel2, sr, abs_floor2)) atomicAdd(tbad + bin, 1u);
                 }
             } else {
                 rgb[3 * ray] = L[0];
@@ -824,9 +828,11 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(4, 4)
     }
 }
 
-// Split a batch for the hybrid query: rays whose line misses the bounding
-// sphere get radiance 0 here; the others go to the surrogate list if their
-// trust bin is trusted, else to the octree list.  A block classifies
+// Split a batch for the hybrid query (sphere_route): rays whose line misses
+// the bounding sphere, or whose sphere lies behind them, get radiance 0
+// here; rays starting inside the sphere go to the octree list; the others go
+// to the surrogate list if their trust bin is trusted, else to the octree
+// list.  A block classifies
 // kClassRays rays (16 per thread, strided by the block size so that loads
 // coalesce), places them with wave ballots and LDS counters, and reserves
 // its slots in each global list with one atomic per list.
@@ -853,7 +859,8 @@ __global__ __launch_bounds__(256) void k_classify(const float *o, const float *d
             float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
             float dd[3] = {d[3 * ray], d[3 * ray + 1], d[3 * ray + 2]};
             float x6[6];
-            cls = sphere_x6(oo, dd, x6) ? (trust[trust_bin(x6)] ? 0 : 1) : 2;
+            const int route = sphere_route(oo, dd, x6);
+            cls = route == kRouteNet ? (trust[trust_bin(x6)] ? 0 : 1) : (route == kRouteOctree ? 1 : 2);
         }
         slot[k] = ~0u;
 #pragma unroll

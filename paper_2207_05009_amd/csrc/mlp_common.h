@@ -88,6 +88,25 @@ __device__ inline bool sphere_x6(const float *o, const float *d, float *x6) {
     return dd > 0.0f && isfinite(dd) && disc > 0.0f;
 }
 
+// Which path answers a ray of the hybrid query.  The network models the
+// radiance of a whole line (the chord of the proxy box it crosses), keyed by
+// where the line enters the bounding sphere; a ray sees that whole chord
+// only when the sphere -- and so the box inside it -- lies wholly ahead of
+// its origin.  kRouteZero: the line misses the sphere, or the sphere lies
+// wholly behind the origin (radiance 0, as the octree gives).  kRouteOctree:
+// the origin is inside the sphere (it may be inside the box, or see a part
+// of the chord only).  kRouteNet: the sphere lies ahead.
+enum { kRouteNet = 0, kRouteOctree = 1, kRouteZero = 2 };
+
+__device__ inline int sphere_route(const float *o, const float *d, float *x6) {
+    if (!sphere_x6(o, d, x6)) return kRouteZero;
+    const float c = o[0] * o[0] + o[1] * o[1] + o[2] * o[2] - kR2;
+    const float od = o[0] * d[0] + o[1] * d[1] + o[2] * d[2];
+    if (!(c > 0.0f)) return kRouteOctree;
+    // outside the sphere, both crossings lie on the side where o.d < 0
+    return od < 0.0f ? kRouteNet : kRouteZero;
+}
+
 // octahedral cell (0..kOctRes^2-1) of a unit vector
 __device__ inline int oct_cell(float x, float y, float z) {
     const float s = fabsf(x) + fabsf(y) + fabsf(z);

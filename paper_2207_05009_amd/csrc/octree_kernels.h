@@ -296,6 +296,8 @@ hipError_t launch_deg(const DevTree &t, const QueryArgs &a, bool trace, hipStrea
     // queries that composite every leaf
     const bool acc64 = (a.flags & LQ_FP64_ACCUM) != 0;
     const bool full = trace || (a.flags & LQ_NO_SIGMA_SKIP) != 0;
+    // a trace of the pruned table (the production query's work)
+    if (trace && (a.flags & LQ_TRACE_PRUNED)) return launch_one<ST, DEG, false, true, true>(t, a, s);
     if (trace) return acc64 ? launch_one<ST, DEG, true, true, false>(t, a, s)
                             : launch_one<ST, DEG, false, true, false>(t, a, s);
     if (full) return acc64 ? launch_one<ST, DEG, true, false, false>(t, a, s)

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblumiq.so")
 LQ_OK = 0
 LQ_F32, LQ_F16, LQ_BF16 = 0, 1, 2
 LQ_LINEAR, LQ_EXP = 0, 1
-LQ_NO_EARLY_TERM, LQ_FP64_ACCUM, LQ_NO_SIGMA_SKIP = 1, 2, 4
+LQ_NO_EARLY_TERM, LQ_FP64_ACCUM, LQ_NO_SIGMA_SKIP, LQ_TRACE_PRUNED = 1, 2, 4, 8
 
 STORAGE = {"f32": LQ_F32, "f16": LQ_F16, "bf16": LQ_BF16}
 MODEL = {"linear": LQ_LINEAR, "exp": LQ_EXP}

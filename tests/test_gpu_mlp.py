@@ -8,6 +8,7 @@ import pytest
 
 import inputs
 from oracle import core, mlp as omlp
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +42,34 @@ def _theta(seed, scale=1.0):
     return th.astype(np.float32)
 
 
+def _rounded_inputs(th, F):
+    """The network with its weights and its input features rounded to
+    bfloat16 (what a bfloat16 kernel is given), everything after in FP64."""
+    return omlp.bf16(th), omlp.bf16(F)
+
+
+def _forward_rounded_inputs(th, o, d):
+    x6, hit = omlp.sphere_param(o, d)
+    thr, Fr = _rounded_inputs(th.astype(np.float64), omlp.features(x6))
+    y, _ = omlp.forward(thr, Fr)
+    L = np.maximum(np.exp(y) - omlp.EPS_OUT, 0.0)
+    L[~hit] = 0.0
+    return L, hit
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-2)
+
+
 def test_forward_matches_oracle(lq):
+    """Surrogate radiance against the FP64 network given the same bfloat16
+    weights and input features: relative L2 over the batch <= 1e-2 (the
+    survey's bound, read in aggregate like the surrogate's accuracy), 99% of
+    the rays and channels within 1e-2 and every one within 3e-2 (the
+    kernel also rounds each layer's activations to bfloat16, 2^-9 relative
+    per rounding).  Against the exact FP64 network (nothing rounded) and
+    against an oracle that rounds where the kernel does: rel-L2 <= 1e-2,
+    p99 <= 2e-2 and 1e-2, max <= 3e-2."""
     import torch
     o, d = _rays(4096, 1)
     sur = lq.Surrogate(seed=1)
@@ -51,28 +79,36 @@ def test_forward_matches_oracle(lq):
     g = sur.forward(_dev(o), _dev(d))
     torch.cuda.synchronize()
     g = g.cpu().numpy().astype(np.float64)
-    # same bfloat16 rounding of weights and GEMM inputs as the kernel
-    ref, hit = omlp.predict(th.astype(np.float64), o, d, round_bf16=omlp.bf16)
-    # compare the network output y = log(L + 0.01): a one-ulp bfloat16
-    # difference early in the network moves y by ~1e-2 at most
-    y_g = np.log(g[hit] + omlp.EPS_OUT)
-    y_r = np.log(ref[hit] + omlp.EPS_OUT)
-    dy = np.abs(y_g - y_r)
-    _say(f"|dy| median {np.median(dy):.2e} p99 {np.quantile(dy, 0.99):.2e} max {dy.max():.2e}")
-    assert dy.max() < 3e-2 and np.median(dy) < 2e-3
-    # against the exact (unrounded) network: the stated bfloat16 error
+    ref, hit = _forward_rounded_inputs(th, o, d)
     exact, _ = omlp.predict(th.astype(np.float64), o, d)
-    rel_x = np.abs(g - exact) / np.maximum(np.abs(exact), 1e-2)
-    _say(f"bf16 network vs fp64 network: median {np.median(rel_x):.2e} max {rel_x.max():.2e}")
+    mirror, _ = omlp.predict(th.astype(np.float64), o, d, round_bf16=omlp.bf16)
     assert np.all(g[~hit] == 0)
+    stats = {}
+    for name, r in (("rounded weights and inputs", ref), ("exact", exact), ("rounding mirror", mirror)):
+        e = _rel(g[hit], r[hit])
+        rl2 = float(np.linalg.norm(g[hit] - r[hit]) / np.linalg.norm(r[hit]))
+        stats[name] = (rl2, float(np.quantile(e, 0.99)), float(e.max()))
+        _say(f"forward vs {name} network: rel-L2 {rl2:.2e} median {np.median(e):.2e} "
+             f"p99 {np.quantile(e, 0.99):.2e} max {e.max():.2e}")
+    # bounds: (rel-L2, p99, max); the exact network also differs by the
+    # rounding of the weights and inputs themselves
+    bounds = {"rounded weights and inputs": (1e-2, 1e-2, 3e-2), "exact": (1e-2, 2e-2, 3e-2),
+              "rounding mirror": (1e-2, 1e-2, 3e-2)}
+    for name, (rl2, p99, mx) in stats.items():
+        b = bounds[name]
+        assert rl2 <= b[0] and p99 <= b[1] and mx <= b[2], (name, stats[name])
 
 
 # 37: one partial tile; 2048: whole tiles, one per workgroup; 70,001: several
-# tiles per workgroup and a ragged last tile.  The oracle mirrors the kernel's
-# bfloat16 GEMM inputs (weights, activations, output gradients); the
-# comparison with the exact FP64 gradient states the bfloat16 error.
+# tiles per workgroup and a ragged last tile.
 @pytest.mark.parametrize("n", [37, 2048, 70001])
 def test_gradient_matches_oracle(lq, n):
+    """The batch gradient against the FP64 gradient of the network given the
+    same bfloat16 weights and input features (and against the exact one):
+    cosine >= 0.999, and relative L2 <= 1e-2 from a batch of whole tiles on;
+    against an oracle that rounds every GEMM input where the kernel does
+    (activations and output gradients too): cosine > 0.9999, relative L2
+    < 1e-2 and cosine > 0.999 layer by layer."""
     o, d = _rays(n, 3)
     tgt = np.exp(np.random.default_rng(4).uniform(-4, 5, size=(n, 3))).astype(np.float32)
     sur = lq.Surrogate(seed=1)
@@ -83,25 +119,38 @@ def test_gradient_matches_oracle(lq, n):
     g = g.cpu().numpy().astype(np.float64)
     x6, hit = omlp.sphere_param(o, d)
     F = omlp.features(x6)
-    rl, rg = omlp.loss_and_grad(th.astype(np.float64), F, tgt.astype(np.float64), hit,
-                                round_bf16=omlp.bf16)
-    _, xg = omlp.loss_and_grad(th.astype(np.float64), F, tgt.astype(np.float64), hit)
+    t64 = tgt.astype(np.float64)
+    thr, Fr = _rounded_inputs(th, F)
+    rl, rg = omlp.loss_and_grad(thr, Fr, t64, hit)
+    _, xg = omlp.loss_and_grad(th.astype(np.float64), F, t64, hit)
+    _, mg = omlp.loss_and_grad(th.astype(np.float64), F, t64, hit, round_bf16=omlp.bf16)
     assert loss == pytest.approx(rl, rel=2e-2)
-    cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
-    rel_l2 = float(np.linalg.norm(g - rg) / np.linalg.norm(rg))
-    xcos = float(g @ xg / (np.linalg.norm(g) * np.linalg.norm(xg)))
-    xrel = float(np.linalg.norm(g - xg) / np.linalg.norm(xg))
-    _say(f"vs bf16-mirroring oracle: cosine {cos:.7f} rel-L2 {rel_l2:.3e}; "
-         f"vs exact FP64: cosine {xcos:.6f} rel-L2 {xrel:.3e}")
-    assert cos > 0.999 and rel_l2 < 1e-2
-    assert xcos > 0.99
-    # layer by layer
-    off = 0
-    for i, o_ in omlp.LAYERS:
-        sl = slice(off, off + i * o_ + o_)
-        c = g[sl] @ rg[sl] / (np.linalg.norm(g[sl]) * np.linalg.norm(rg[sl]))
-        assert c > 0.999, (i, o_, c)
-        off += i * o_ + o_
+
+    def cmp(a, b):
+        return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b))), float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    res = {}
+    for name, ref in (("rounded weights and inputs", rg), ("exact", xg), ("rounding mirror", mg)):
+        res[name] = cmp(g, ref)
+        layers, off = [], 0
+        for i, o_ in omlp.LAYERS:
+            sl = slice(off, off + i * o_ + o_)
+            layers.append(cmp(g[sl], ref[sl]))
+            off += i * o_ + o_
+        _say(f"gradient vs {name}: cosine {res[name][0]:.7f} rel-L2 {res[name][1]:.3e}; per layer "
+             + ", ".join(f"{c:.5f}/{r:.1e}" for c, r in layers))
+        if name == "rounding mirror":
+            assert min(c for c, _ in layers) > 0.999, (name, layers)
+    # the kernel against its rounding mirror at every size; against the
+    # network given rounded weights and inputs (and the exact one) from a
+    # batch of whole tiles on: 37 samples leave the activation roundings
+    # unaveraged (rel-L2 ~3e-2 there, cosine still > 0.999)
+    assert res["rounding mirror"][0] > 0.9999 and res["rounding mirror"][1] < 1e-2, res
+    for name in ("rounded weights and inputs", "exact"):
+        cos, rel = res[name]
+        assert cos >= 0.999, (name, cos)
+        if n >= 2048:
+            assert rel <= 1e-2, (name, rel)
 
 
 @pytest.mark.parametrize("n", [32, 37])
@@ -129,28 +178,38 @@ def test_gradient_ignores_padding(lq, n):
 
 
 def test_adam_steps_match_oracle(lq):
+    """Three training steps against Adam's formula (Kingma & Ba; Sec. 4.4
+    exponential learning-rate decay), parameter by parameter, with the
+    GPU's own batch gradient at each step's parameters: the updated weights
+    agree to float32 rounding (the kernel keeps m, v and the weights in
+    float32, the formula is evaluated in FP64 from the same gradient)."""
+    import torch
     o, d = _rays(1024, 6)
     tgt = np.exp(np.random.default_rng(7).uniform(-3, 4, size=(1024, 3))).astype(np.float32)
+    O, D, Tg = _dev(o), _dev(d), _dev(tgt)
     sur = lq.Surrogate(seed=1)
-    th0 = _theta(8, 0.7)
-    sur.set_params(th0)
+    th = _theta(8, 0.7).astype(np.float64)
+    sur.set_params(th.astype(np.float32))
     _say("three Adam steps")
-    sur.train(_dev(o), _dev(d), _dev(tgt), steps=3, total_steps=10, batch=1024, lr0=1e-3, lr1=1e-4)
-    th_gpu = sur.get_params().astype(np.float64)
-    x6, hit = omlp.sphere_param(o, d)
-    F = omlp.features(x6)
-    th = th0.astype(np.float64)
     m = np.zeros_like(th)
     v = np.zeros_like(th)
+    lr0, lr1, total = 1e-3, 1e-4, 10
+    worst = 0.0
     for k in range(3):
-        _, gr = omlp.loss_and_grad(th, F, tgt.astype(np.float64), hit, round_bf16=omlp.bf16)
-        th, m, v = omlp.adam_step(th, gr, m, v, k + 1, omlp.lr_at(k, 10, 1e-3, 1e-4))
-    du_gpu, du_ref = th_gpu - th0, th - th0
-    cos = du_gpu @ du_ref / (np.linalg.norm(du_gpu) * np.linalg.norm(du_ref))
-    _say(f"update cosine {cos:.5f}")
-    assert cos > 0.99
-    # Adam moves every parameter by about lr per step
-    assert np.median(np.abs(du_gpu)) == pytest.approx(np.median(np.abs(du_ref)), rel=0.1)
+        _, gk = sur.grad(O, D, Tg)           # at the current parameters, no update
+        gk = gk.cpu().numpy().astype(np.float64)
+        ref, m, v = omlp.adam_step(th, gk, m, v, k + 1, omlp.lr_at(k, total, lr0, lr1))
+        sur.train(O, D, Tg, steps=1, total_steps=total, batch=1024, lr0=lr0, lr1=lr1)
+        torch.cuda.synchronize()
+        got = sur.get_params().astype(np.float64)
+        # float32: the weight's own rounding plus a few ulp of the update
+        tol = 2.0 ** -22 * np.abs(ref) + 2.0 ** -16 * lr0
+        dev = np.abs(got - ref)
+        worst = max(worst, float((dev / tol).max()))
+        assert np.all(dev <= tol), (k, int(np.argmax(dev / tol)), float(dev.max()))
+        assert np.count_nonzero(got != th) > 0.9 * th.size
+        th = got
+    _say(f"Adam: largest deviation {worst:.3f} of the float32 tolerance")
 
 
 def _training_set(lq, tree_oct, n, seed):
@@ -224,6 +283,45 @@ def test_trust_map_and_fallback(lq, c0_tree):
     assert float(u.float().mean()) < 0.97
 
 
+def test_hybrid_routes_rays_behind_and_inside(lq, c0_tree):
+    """Rays the network cannot answer, with every trust bin trusted: room
+    rays turned away from the luminaire (the proxy behind them), origins
+    inside the box, and origins inside the bounding sphere but outside the
+    box.  The hybrid must return what the octree returns on each of them:
+    0 for the first, the octree's own march for the others."""
+    import torch
+    oct_ = lq.Octree(c0_tree, "f32")
+    sur = lq.Surrogate(seed=5)
+    ho, hd, hrgb = _training_set(lq, oct_, 1 << 24, 42)
+    sur.build_trust(ho, hd, hrgb, max_rel_err=1e9)
+    assert sur.trust_map().sum() > 0
+    del ho, hd, hrgb
+    rng = np.random.default_rng(77)
+    ro, rd = inputs.rays.room_to_proxy(1 << 15, 78)
+    bo = rng.uniform(-0.95, 0.95, size=(1 << 14, 3))
+    bd = rng.normal(size=(1 << 14, 3))
+    so = rng.normal(size=(1 << 15, 3))
+    so = so / np.linalg.norm(so, axis=1, keepdims=True) * rng.uniform(1.0, 1.7, size=(len(so), 1))
+    so = so[np.abs(so).max(1) > 1.0]
+    sd = rng.uniform(-1, 1, size=so.shape) - so
+    o = np.concatenate([ro, bo, so]).astype(np.float32)
+    d = np.concatenate([-rd, bd, sd]).astype(np.float32)
+    _say(f"hybrid routing: {len(ro)} reversed room rays, {len(bo)} from inside the box, "
+         f"{len(so)} from inside the sphere")
+    O, D = _dev(o), _dev(d)
+    out, used = sur.infer(O, D, oct_)
+    ref, _ = oct_.query(O, D)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    route = omlp.route(o, d)
+    u = used.cpu().numpy().astype(bool)
+    # the proxy is behind every reversed room ray: radiance 0, and only
+    # those starting inside the sphere were handed to the octree
+    assert float(ref[: len(ro)].abs().max()) == 0.0
+    assert int((u[: len(ro)] != (route[: len(ro)] == omlp.ROUTE_OCTREE)).sum()) <= 2
+    assert u[len(ro):].all()
+
+
 def test_multi_tree_query_matches_single(lq):
     import torch
     trees = [inputs.random_tree(dep, 0.3, seed=70 + dep, sh_degree=3) for dep in (2, 3, 4, 5)]
@@ -246,10 +344,9 @@ def test_multi_tree_query_matches_single(lq):
     k = 2
     s = slice(offs[k], offs[k + 1])
     orc = core.query(trees[k], o[s], d[s], model=0, storage="f16")
-    rgb, _ = lq.query_multi(octs, offs, _dev(o), _dev(d))
-    err = np.abs(rgb.cpu().numpy()[s] - orc["L"]) / np.maximum(np.abs(orc["L"]), 1e-6 * 2048)
-    amb = orc["alt_valid"].astype(bool)
-    assert err[~amb].max() < 1e-4
+    rgb, alpha = lq.query_multi(octs, offs, _dev(o), _dev(d))
+    rep = parity.match_plain(rgb.cpu().numpy()[s], alpha.cpu().numpy()[s], orc, trees[k].l_max)
+    assert rep["n_bad"] == 0, rep
 
 
 def test_trained_surrogate_serves_rays_the_untrained_cannot(lq, c0_tree):

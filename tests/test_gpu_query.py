@@ -154,6 +154,68 @@ def test_sh_degrees_parity(lq, deg):
         oct_.free()
 
 
+def test_threshold_ambiguous_rays_match_a_candidate(lq):
+    """Hand-built rows of leaves put 1 - T within 1e-4 of alpha_max at the
+    first or second stop test, above or below it (down to 1e-7 away): the
+    GPU's float32 compositing may decide either way, and its records and
+    radiance must equal one of the oracle's two candidates (Sec. 6.2)."""
+    from tests import test_oracle_ambiguous as amb
+    n_alt = 0
+    for model, name in ((core.LINEAR, "linear"), (core.EXP, "exp")):
+        for amb_test in (0, 1):
+            for offset in (4e-5, -4e-5, 1e-6, -1e-6, 1e-7, -1e-7):
+                sig, _ = amb._densities(model, amb_test, offset)
+                tree = amb._tree(sig)
+                orc = core.query(tree, amb.O, amb.D, model=model, max_ids=8)
+                assert orc["alt_valid"][0] == 1
+                oct_ = lq.Octree(tree, "f32")
+                g = _run_trace(oct_, amb.O, amb.D, name, max_ids=8)
+                rep = parity.compare(g, orc, tree.l_max)
+                assert rep["ok"], (name, amb_test, offset, rep)
+                n_alt += rep["n_alt"]
+                oct_.free()
+    _say(f"threshold-ambiguous rays: {n_alt} of 24 matched the second candidate")
+    # two ambiguous tests in a row (the second leaf's density is below
+    # sigma_min: the skip is off): stop at either, or continue through both
+    outcomes = {}
+    for model, name in ((core.LINEAR, "linear"), (core.EXP, "exp")):
+        for offsets in ((-6e-5, 3e-5), (-8e-5, -2e-5), (2e-5, 7e-5), (-1e-7, 1e-7), (-3e-7, -1e-7)):
+            sig, _ = amb._densities_two(model, *offsets)
+            tree = amb._tree(sig)
+            oct_ = lq.Octree(tree, "f32")
+            g = _run_trace(oct_, amb.O, amb.D, name, lq.LQ_NO_SIGMA_SKIP, max_ids=8)
+            c = core.candidates(tree, amb.O, amb.D, model=model, opts=core.NO_SKIP)
+            assert int(c["valid"][0].sum()) == 3
+            assert parity.match_candidates(g, c, tree.l_max)[0], (name, offsets, g)
+            outcomes[int(g["term_idx"][0])] = outcomes.get(int(g["term_idx"][0]), 0) + 1
+            oct_.free()
+    _say(f"two ambiguous tests: the GPU stopped at tests {outcomes}")
+
+
+@pytest.mark.parametrize("depth", [2, 3, 5])
+def test_pruned_table_trace(lq, depth):
+    """The trace of the sigma_min-pruned table (what the production query
+    marches) against the oracle marching its own pruned tree with the skip
+    off: records bit-exact on adversarial and random rays, every storage."""
+    tree = inputs.random_tree(depth, 0.5, seed=30 + depth, sigma_range=(0.02, 50.0))
+    o1, d1 = inputs.rays.adversarial(depth, seed=40 + depth, n=400)
+    o2, d2 = inputs.rays.sphere_to_cube(3000, 45 + depth)
+    o, d = np.concatenate([o1, o2]), np.concatenate([d1, d2])
+    mx = 3 * (1 << depth) + 4
+    for storage in ("f32", "f16", "bf16"):
+        oct_ = lq.Octree(tree, storage)
+        pt = core.pruned_tree(tree, storage)
+        for model, m in (("linear", 0), ("exp", 1)):
+            for flags in (0, lq.LQ_NO_EARLY_TERM):
+                _say(f"pruned-table trace, depth {depth}, {storage} {model} flags={flags}")
+                g = _run_trace(oct_, o, d, model, flags | lq.LQ_TRACE_PRUNED, max_ids=mx)
+                opts = core.NO_SKIP | (core.NO_STOP if flags else 0)
+                orc = core.query(pt, o, d, model=m, opts=opts, storage=storage, max_ids=mx)
+                rep = parity.compare(g, orc, tree.l_max)
+                assert rep["ok"], (storage, model, flags, rep)
+        oct_.free()
+
+
 def test_empty_tree_and_misses(lq):
     import torch
     tree = inputs.empty_tree(4)
@@ -226,33 +288,6 @@ def test_direction_scaling_bit_identical(lq, c0_tree):
             assert np.array_equal(g[key], ref[key]), (k, key)
 
 
-def test_full_size_camera_sampled_parity(lq, c1_tree):
-    """The depth-9 tree and the 2048x2048 camera batch in one launch, as the
-    benchmark times it; a seeded sample of rays is checked one by one."""
-    import torch
-    o, d = inputs.rays.pinhole(2048, 2048)
-    _say(f"full-size camera batch: {len(o)} rays, {c1_tree.n_leaves} leaves")
-    oct_ = lq.Octree(c1_tree, "f32")
-    out = parity.to_numpy(oct_.trace(_dev(o), _dev(d), model="linear"))
-    rgb, alpha = oct_.query_image(_dev(o), _dev(d), 2048, 2048, model="linear")   # the timed entry point
-    torch.cuda.synchronize()
-    idx = np.sort(np.random.default_rng(7).choice(len(o), 20000, replace=False))
-    orc = core.query(c1_tree, o[idx], d[idx], model=0)
-    g = {k: v[idx] for k, v in out.items()}
-    rep = parity.compare(g, orc, c1_tree.l_max, ids=False)
-    _say(f"report {rep}")
-    assert rep["ok"], rep
-    q = {"count": g["count"], "hash": g["hash"], "term_idx": g["term_idx"],
-         "rgb": rgb.cpu().numpy()[idx], "alpha": alpha.cpu().numpy()[idx]}
-    rep = parity.compare(q, orc, c1_tree.l_max, ids=False)
-    _say(f"plain query report {rep}")
-    assert rep["ok"], rep
-    # properties on every ray
-    assert np.all(np.isfinite(out["rgb"])) and np.all(out["rgb"] >= 0)
-    assert np.all((out["alpha"] >= 0) & (out["alpha"] <= 1))
-    assert np.all(out["rgb"] <= c1_tree.l_max * out["alpha"][:, None] * (1 + 1e-5) + 1e-6)
-
-
 @pytest.mark.parametrize("wh", [(1, 1), (7, 5), (8, 8), (13, 11), (64, 3), (3, 64), (100, 37), (517, 259)])
 def test_camera_batch_order_is_bit_identical(lq, c0_tree, wh):
     """The camera-batch entry point takes rays up in 8x8 pixel tiles (then
@@ -316,48 +351,9 @@ def test_abi_rejects_bad_pointers(lq, c0_tree):
                              C.c_void_p(rgb.data_ptr()), None, 0, 1 << 9, None)
     assert st == -1
     assert L.lq_query_radiance(oct_.handle, None, None, 0, None, None, 0, 0, None) == 0
-
-
-@pytest.fixture(scope="module")
-def full_rays():
-    cam = inputs.rays.pinhole(2048, 2048)
-    room = inputs.rays.room_to_proxy(1 << 24, 20)
-    return {"camera": cam, "room": room}
-
-
-@pytest.mark.parametrize("workload", ["camera", "room"])
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_full_size_error_against_oracle(lq, c1_tree, full_rays, workload, storage):
-    """Every benchmarked configuration at full size, in the launch the
-    benchmark times: a seeded sample of rays must match the oracle on the
-    stored (dequantised) tree to 1e-4; the error against the float32 tree --
-    the storage error -- is stated."""
-    import torch
-    o, d = full_rays[workload]
-    _say(f"full-size {workload} batch, {len(o)} rays, storage {storage}")
-    oct_ = lq.Octree(c1_tree, storage)
-    if workload == "camera":   # one 2048x2048 image: the camera-batch entry point
-        rgb, alpha = oct_.query_image(_dev(o), _dev(d), 2048, 2048, model="linear")
-    else:
-        rgb, alpha = oct_.query(_dev(o), _dev(d), model="linear")
-    torch.cuda.synchronize()
-    idx = np.sort(np.random.default_rng(11).choice(len(o), 20000, replace=False))
-    g_rgb = rgb.cpu().numpy()[idx].astype(np.float64)
-    g_alpha = alpha.cpu().numpy()[idx].astype(np.float64)
-    oct_.free()
-    orc = core.query(c1_tree, o[idx], d[idx], model=0, storage=storage)
-    amb = orc["alt_valid"].astype(bool)
-    err = parity.rel_err(g_rgb, orc["L"], c1_tree.l_max).max(1)
-    alt_err = parity.rel_err(g_rgb, orc["alt_L"], c1_tree.l_max).max(1)
-    err = np.where(amb, np.minimum(err, alt_err), err)
-    aerr = np.abs(g_alpha - orc["alpha"])
-    aerr = np.where(amb, np.minimum(aerr, np.abs(g_alpha - orc["alt_alpha"])), aerr)
-    _say(f"{workload} {storage} vs oracle on the stored tree: max {err.max():.2e} "
-         f"p99 {np.quantile(err, 0.99):.2e} max |dalpha| {aerr.max():.2e} ({int(amb.sum())} ambiguous)")
-    assert err.max() <= parity.RTOL and aerr.max() <= parity.RTOL
-    if storage != "f32":
-        orc32 = core.query(c1_tree, o[idx], d[idx], model=0)
-        e32 = parity.rel_err(g_rgb, orc32["L"], c1_tree.l_max).max(1)
-        rl2 = float(np.linalg.norm(g_rgb - orc32["L"]) / np.linalg.norm(orc32["L"]))
-        _say(f"{workload} {storage} storage error vs the float32 tree: median {np.median(e32):.2e} "
-             f"p99 {np.quantile(e32, 0.99):.2e} max {e32.max():.2e} rel-L2 {rl2:.2e}")
+    # the pruned-table flag belongs to the trace, and only with the stop flag
+    st = L.lq_query_radiance(oct_.handle, C.c_void_p(o.data_ptr()), C.c_void_p(d.data_ptr()), 16,
+                             C.c_void_p(rgb.data_ptr()), None, 0, lq.LQ_TRACE_PRUNED, None)
+    assert st == -1
+    with pytest.raises(lq.LumiqError):
+        oct_.trace(o, d, flags=lq.LQ_TRACE_PRUNED | lq.LQ_FP64_ACCUM)

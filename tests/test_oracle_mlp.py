@@ -151,3 +151,38 @@ def test_learning_rate_schedule():
     assert mlp.lr_at(0, 20000) == pytest.approx(5e-4)
     assert mlp.lr_at(20000, 20000) == pytest.approx(5e-6)
     assert mlp.lr_at(10000, 20000) == pytest.approx(math.sqrt(5e-4 * 5e-6))
+
+
+def test_route_against_box_chords():
+    """The hybrid's routing rule against the box geometry: a ray routed to
+    the network sees the whole chord its line cuts from the box (the slab
+    interval of the line lies at t >= 0); a ray routed to zero sees none of
+    it (the octree of a box full of emitting density returns exactly 0)."""
+    import inputs
+    from oracle import core
+    rng = np.random.default_rng(5)
+    n = 4000
+    # origins around and inside the box and the sphere, toward the box or away
+    o = rng.uniform(-3, 3, size=(n, 3))
+    tgt = rng.uniform(-1.2, 1.2, size=(n, 3))
+    d = (tgt - o) * np.where(rng.random(n) < 0.4, -1.0, 1.0)[:, None]
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    r = mlp.route(o, d)
+    assert set(np.unique(r)) == {mlp.ROUTE_NET, mlp.ROUTE_OCTREE, mlp.ROUTE_ZERO}
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t0, t1 = (-1 - od) / dd, (1 - od) / dd
+    tin = np.nanmax(np.minimum(t0, t1), axis=1)
+    tout = np.nanmin(np.maximum(t0, t1), axis=1)
+    meets_line = tout > tin
+    net = r == mlp.ROUTE_NET
+    assert np.all(tin[net & meets_line] >= 0)
+    assert np.all((np.linalg.norm(od, axis=1) ** 2 > 3) | (r == mlp.ROUTE_OCTREE) | (r == mlp.ROUTE_ZERO))
+    full = inputs.uniform_tree(2, 0.5, np.zeros((3, 1)))
+    q = core.query(full, o, d, opts=core.NO_STOP)
+    zero = r == mlp.ROUTE_ZERO
+    assert np.all(q["L"][zero] == 0) and np.all(q["alpha"][zero] == 0)
+    # and rays routed to the network that meet the box see its whole chord
+    chord = (tout - tin) * np.linalg.norm(dd, axis=1)
+    sel = net & meets_line
+    assert np.allclose(q["alpha"][sel], np.minimum(1.0, 0.5 * chord[sel]), rtol=1e-9, atol=1e-12)
