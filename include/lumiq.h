@@ -127,6 +127,22 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
                             void *hip_stream);
 
 /*
+ * lq_query_radiance without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results (bit for bit), flags and
+ * errors as lq_query_radiance.  The launch's only scratch -- 16 ray
+ * counters, 128 bytes, whatever n -- lives in a static device array of the
+ * library (one copy per GPU, held until the process ends), cleared by a
+ * kernel at the start of every call.  Every call on one GPU shares that
+ * array: calls that overlap in time on one GPU (concurrent streams, or
+ * threads) race on it and give wrong results; serialise them.  Its address
+ * is looked up on the first call on each device.
+ */
+lq_status lq_query_radiance_noalloc(const lq_octree *tree, const float *origins, const float *dirs,
+                                    int64_t n, float *rgb, float *alpha, int model, uint32_t flags,
+                                    void *hip_stream);
+
+/*
  * Camera batch: the query of lq_query_radiance over the width * height rays
  * of an image stored row-major (ray y * width + x belongs to pixel (x, y)),
  * e.g. the primary rays of a rendered frame.  The results are those of

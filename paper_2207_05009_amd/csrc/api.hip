@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -488,6 +489,54 @@ lq_status lq_query_radiance(const lq_octree *tree, const float *origins, const f
     a.alpha = alpha;
     a.model = model;
     a.flags = flags;
+    return query_common(tree, a, false, hip_stream);
+}
+
+}  // extern "C"
+
+namespace lq {
+
+// Ray counters of lq_query_radiance_noalloc: a file-scope device array (one
+// copy on every GPU the library runs on, held until the process ends).  In
+// host code its name is not a device address; the address is looked up once
+// per device, with that device current, and only that pointer is used.
+static __device__ __align__(256) unsigned long long scratch[kQueryCounters];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+
+static lq_status scratch_counters(int device, unsigned long long **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(LQ_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress of the counter array");
+        g_scratch_ptr[device] = static_cast<unsigned long long *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return LQ_OK;
+}
+
+}  // namespace lq
+
+extern "C" {
+
+lq_status lq_query_radiance_noalloc(const lq_octree *tree, const float *origins, const float *dirs, int64_t n,
+                                    float *rgb, float *alpha, int model, uint32_t flags, void *hip_stream) {
+    if (!tree) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");
+    QueryArgs a{};
+    a.o = origins;
+    a.d = dirs;
+    a.n = n;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.model = model;
+    a.flags = flags;
+    lq_status st = scratch_counters(tree->device, &a.counters);
+    if (st != LQ_OK) return st;
     return query_common(tree, a, false, hip_stream);
 }
 

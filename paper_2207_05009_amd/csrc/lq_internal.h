@@ -40,6 +40,10 @@ struct DevTree {
     float l_max, sigma_min, alpha_max, pad2;
 };
 
+// Ray counters of one query launch (two contiguous ranges of the batch per
+// accelerator die, see octree_kernels.h).
+constexpr int kQueryCounters = 16;
+
 struct QueryArgs {
     const float *o, *d;
     int64_t n;
@@ -62,6 +66,9 @@ struct QueryArgs {
     // of a row-major image and the waves take them up in 8 x 8 pixel tiles
     // (tile_order_pixel); excludes index
     uint32_t img_w, img_h;
+    // kQueryCounters device counters for the launch, or null: the launcher
+    // then allocates them stream-ordered
+    unsigned long long *counters;
 };
 
 // Pixel taken up at position v (< w h) of a camera batch's tile order, a

@@ -48,6 +48,7 @@ constexpr int kTileStepsPerCheck = 32;
 constexpr int kXcds = 8;             // accelerator dies (XCDs) of an MI355X
 constexpr int kRangesPerXcd = 2;     // ray counters (contiguous ranges) per die
 constexpr int kRanges = kXcds * kRangesPerXcd;
+static_assert(kRanges == kQueryCounters, "one counter per range");
 static_assert(kRanges >= 1 && kRanges <= 64, "one bit per range in a 64-bit mask");
 constexpr uint64_t kAllRanges = kRanges == 64 ? ~0ull : (1ull << kRanges) - 1ull;   // every range used up
 constexpr int kMaxTries = 8;         // refill attempts per check
@@ -280,13 +281,15 @@ hipError_t launch_one(const DevTree &t, const QueryArgs &a, hipStream_t s) {
     auto kern = query_kernel<ST, DEG, ACC64, TRACE, SKIP, MODEL, TILES>();
     const int64_t need_blocks = (a.n + kBlock - 1) / kBlock;
     const int64_t nb = std::min<int64_t>(need_blocks, resident_blocks(kern));
-    unsigned long long *queue = nullptr;
-    hipError_t e = hipMallocAsync((void **)&queue, kRanges * sizeof(unsigned long long), s);
-    if (e != hipSuccess) return e;
+    unsigned long long *queue = a.counters;
+    hipError_t e = hipSuccess;
+    if (!queue && (e = hipMallocAsync((void **)&queue, kRanges * sizeof(unsigned long long), s)) != hipSuccess)
+        return e;
+    // cleared by a kernel (not a memset node), so the launch can be captured
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kRanges), 0, s, queue);
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, t, a, queue);
     e = hipGetLastError();
-    hipError_t f = hipFreeAsync(queue, s);
+    hipError_t f = a.counters ? hipSuccess : hipFreeAsync(queue, s);
     return e != hipSuccess ? e : f;
 }
 
