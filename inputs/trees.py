@@ -239,6 +239,23 @@ def _solve_scale(spec: TreeSpec, p: _Params) -> float:
     return math.sqrt(lo * hi)
 
 
+def field_params(spec: TreeSpec) -> dict:
+    """Parameters of the continuous field the tree of `spec` samples (the
+    stand-in for a trained radiance field that a plenoctree is distilled
+    from): blob centres, radii (with the solved scale), log-density
+    amplitudes, per-blob emission (magnitude times tint) and higher SH
+    coefficients, shells (centre, radius) of half-width one finest voxel at
+    the spec's depth, base log-density, density clamp, L_max, SH degree."""
+    p = _draw_params(spec)
+    s = _solve_scale(spec, p) if spec.n_blobs else 1.0
+    K = (spec.sh_degree + 1) ** 2
+    return {"centres": p.centres.copy(), "radii": s * p.u, "amps": p.amp.copy(),
+            "emission": p.mag[:, None] * p.tint, "hi": p.hi.reshape(spec.n_blobs, 3, K - 1).copy(),
+            "shells": p.shells.copy(), "shell_half_width": 2.0 / (1 << spec.depth),
+            "log_base": LOG_BASE, "sigma_max": SIGMA_CLAMP, "l_max": float(spec.l_max),
+            "sh_degree": spec.sh_degree}
+
+
 def make_tree(spec: TreeSpec) -> Tree:
     """Generate the seeded synthetic plenoctree described by spec."""
     depth = spec.depth
