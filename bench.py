@@ -437,6 +437,52 @@ def floor_variant(inputs, oct32, steps):
     return rec
 
 
+DISTILL_SAMPLES = 256
+
+
+def distill_variant(lumiq, steps):
+    """Plenoctree distillation (Sec. 5): the continuous field behind the
+    depth-9 luminaire (16 blobs + 4 shells, SH degree 2) distilled at 512^3
+    with 256 samples per kept voxel, one lq_distill_leaves call per step
+    (centre test, compaction, sampling and averaging; the call reads the
+    kept count back to size the launch).  The sampling kernel is bound by
+    its arithmetic: per sample 24 + 23 n_blobs float32 operations (an FMA
+    counts 2, a transcendental 1) against the chip's float32 vector peak."""
+    import torch
+    import inputs
+    from inputs.trees import field_params
+    p = field_params(inputs.C1_TREE)
+    codes, sig, sh = lumiq.distill_leaves(p, 9, 0.01, DISTILL_SAMPLES, 2022)
+    n = codes.shape[0]
+    desc, keep = lumiq.field_desc(p)
+    cnt = lumiq.C.c_int64()
+    L = lumiq.lib()
+
+    def call():
+        lumiq.check(L.lq_distill_leaves(lumiq.C.byref(desc), 9, 0.01, DISTILL_SAMPLES, 2022, 0, n,
+                                        lumiq._ptr(codes), lumiq._ptr(sig), lumiq._ptr(sh), lumiq.C.byref(cnt),
+                                        lumiq._stream(None)))
+
+    ms, _ = time_launches(call, steps, 2)
+    nb = len(p["radii"])
+    flop = n * DISTILL_SAMPLES * (24 + 23 * nb)
+    t0 = time.perf_counter()
+    tree = lumiq.octree_from_leaves(9, 2, codes, sig, sh, l_max=p["l_max"])
+    torch.cuda.synchronize()
+    t_tree = time.perf_counter() - t0
+    info = tree.info()
+    tree.free()
+    rec = {"depth": 9, "voxels": 1 << 27, "kept": int(n), "samples_per_voxel": DISTILL_SAMPLES, "ms": ms,
+           "samples_per_s": n * DISTILL_SAMPLES / (ms * 1e-3),
+           "roofline": {"bound": "alu", "achieved": round(flop / (ms * 1e-3) / 1e12, 2), "peak": 157.3,
+                        "unit": "TFLOP/s", "frac": round(flop / (ms * 1e-3) / 157.3e12, 4),
+                        "flop_per_sample": 24 + 23 * nb},
+           "octree_build_and_load_s": round(t_tree, 3), "n_nodes": info["n_nodes"]}
+    log(f"distillation: {ms:.3f} ms for {n} voxels x {DISTILL_SAMPLES} samples")
+    del keep
+    return rec
+
+
 def uneven_variant(lumiq, samples=None, trees_out=None, rays_out=None):
     """The uneven multi-luminaire batch (16 trees of depth 6 to 10, SH degree
     3, float16, log-uniform ray counts): one persistent launch over all rays
@@ -660,6 +706,7 @@ def main():
 
     if not args.no_variants:
         variants["floor_irradiance"] = floor_variant(inputs, oct32, max(5, args.steps // 4))
+        variants["distillation"] = distill_variant(lumiq, 5)
 
     if args.sh_sweep:
         variants["sh_sweep_camera"] = sh_sweep_variant(lumiq, o, d, max(5, args.steps // 2))

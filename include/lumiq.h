@@ -239,6 +239,81 @@ lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const 
                               float *sample_terms, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Plenoctree distillation (Sec. 5, "Creating the plenoctree"): a density
+ * sample at the centre of every voxel of the finest grid (2^max_depth per
+ * axis over [-1,1]^3), pruning of the voxels whose centre density is below
+ * prune_sigma (0.01 in the paper), and for every voxel kept the mean density
+ * and mean SH coefficients of n_samples uniformly random positions inside
+ * it (256 in the paper, against aliasing at discontinuities); the octree
+ * over the kept voxels collapses empty octants bottom-up.
+ *
+ * The continuous field stands in for a trained radiance field:
+ *   density(x) = sigma_max inside a shell (| |x - s_j| - R_j | < shell_half_width),
+ *              = min(exp(log_density_base + sum_k a_k g_k(x)), sigma_max) elsewhere,
+ *   g_k(x) = exp(-|x - c_k|^2 / (2 r_k^2));
+ * its emission coefficients are blended by w_k(x) = g_k(x) / sum_j g_j(x):
+ *   coefficient 0 of channel c = logit(E_c(x) / l_max) / Y_00, E_c = sum_k w_k e_kc
+ *     (so that Eq. 6's l_max sigmoid(...) returns E_c for that band alone),
+ *   coefficient j >= 1 of channel c = sum_k w_k h_kcj (index j = l^2 + l + m).
+ * The random positions come from Philox4x32-10 (Salmon et al., SC 2011):
+ * counter (Morton code of the voxel, sample index, 0, 0), key (low and high
+ * 32 bits of seed); the first three output words u give the offsets
+ * (u >> 8) 2^-24 along x, y, z in units of the voxel edge.  Decisions (the
+ * centre test, shell membership) are taken in FP64, the samples' blob terms
+ * and the sums in float32.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_blobs;          /* 1..32                                           */
+    int32_t n_shells;         /* 0..8                                            */
+    int32_t sh_degree;        /* 0..4                                            */
+    int32_t reserved;
+    const double *blobs;      /* host [n_blobs][8]: centre x, y, z, radius r > 0,
+                                 log-density amplitude a, radiance e_r, e_g, e_b
+                                 (each in (0, l_max))                            */
+    const double *blob_sh;    /* host [n_blobs][3][(sh_degree+1)^2 - 1]: h_kcj for
+                                 j >= 1 (NULL for degree 0)                      */
+    const double *shells;     /* host [n_shells][4]: centre x, y, z, radius      */
+    double shell_half_width, log_density_base, sigma_max, l_max;
+} lq_field_desc;
+
+/*
+ * Distil the leaves: codes[i] (ascending Morton codes of the kept voxels,
+ * x bit b -> bit 3b, y -> 3b+1, z -> 3b+2), sigma[i] and sh[i][3][K] (the
+ * means), device arrays of `capacity` entries on `device`.  *n_leaves (host)
+ * receives the number of voxels kept.  capacity = 0 only counts them (the
+ * arrays may then be NULL); a count above capacity is LQ_ERR_INVALID_ARG
+ * with *n_leaves set and nothing written.  The call synchronises hip_stream
+ * (the count decides the launch size).  Errors: LQ_ERR_INVALID_ARG,
+ * LQ_ERR_UNSUPPORTED (more than 32 blobs or 8 shells), LQ_ERR_OOM,
+ * LQ_ERR_HIP.
+ */
+lq_status lq_distill_leaves(const lq_field_desc *field, int32_t max_depth, float prune_sigma,
+                            int32_t n_samples, uint64_t seed, int device, int64_t capacity,
+                            uint32_t *codes, float *sigma, float *sh, int64_t *n_leaves,
+                            void *hip_stream);
+
+/*
+ * An octree from leaves at max depth: codes (device, strictly ascending
+ * Morton codes below 8^max_depth, else LQ_ERR_FORMAT), sigma [n] and
+ * sh [n][3][K] (device, float32).  The child table is built on the device
+ * by collapsing empty octants bottom-up (nodes breadth-first, Morton order
+ * within a level; leaf i is codes[i]) and the tree is then loaded as by
+ * lq_load_octree_desc (its storage conversion and tables); synchronous.
+ */
+lq_status lq_octree_from_leaves(int32_t max_depth, int32_t sh_degree, const uint32_t *codes,
+                                const float *sigma, const float *sh, int64_t n_leaves, float l_max,
+                                float sigma_min, float alpha_max, int storage, int device,
+                                lq_octree **out);
+
+/*
+ * Copy a tree's tables to host memory: child [n_nodes][8], sigma [n_leaves]
+ * and sh [n_leaves][3][K] (any may be NULL), with the sizes lq_octree_info
+ * reports; values as stored (float16 / bfloat16 widened exactly to
+ * float32).  Synchronous.
+ */
+lq_status lq_octree_download(const lq_octree *tree, int32_t *child, float *sigma, float *sh);
+
+/* ------------------------------------------------------------------------
  * Learned surrogate.  A ray is reduced to the point where its line enters
  * the sphere of radius sqrt(3) bounding the proxy box and its unit direction
  * (the 5D light-field coordinates of Sec. 3, Eq. 1), encoded with 10

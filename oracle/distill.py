@@ -168,27 +168,35 @@ def morton_encode(x, y, z):
 
 
 # ---------------------------------------------------------------- steps
-def centre_occupancy(f: Field, depth: int, prune_sigma: float = 0.01, chunk: int = 1 << 21):
+def _centre_chunk(args):
+    f, depth, thr, a, b = args
+    h = 2.0 / (1 << depth)
+    codes = np.arange(a, b, dtype=np.uint64)
+    q = morton_decode(codes)
+    x = -1.0 + (q + 0.5) * h
+    S = log_density_sum(f, x)
+    inside, margin = _in_shell(f, x)
+    keep = inside | (S >= thr)
+    near = (np.abs(S - thr) <= AMBIGUOUS_REL * max(1.0, abs(thr))) & ~inside
+    near |= margin <= AMBIGUOUS_REL * (1.0 + f.shell_half_width)
+    return codes[keep], codes[near]
+
+
+def centre_occupancy(f: Field, depth: int, prune_sigma: float = 0.01, chunk: int = 1 << 21, workers: int = 1):
     """Step (1)-(2): Morton codes (ascending) of the voxels whose centre
     density is >= prune_sigma, and the codes of the ambiguous voxels (either
-    decision valid)."""
-    n = 1 << depth
-    h = 2.0 / n
+    decision valid).  workers > 1 spreads the chunks of voxels over
+    processes (the same computation per voxel)."""
     thr = math.log(prune_sigma) - f.log_base
-    kept, amb = [], []
-    total = n ** 3
-    for a in range(0, total, chunk):
-        codes = np.arange(a, min(total, a + chunk), dtype=np.uint64)
-        q = morton_decode(codes)
-        x = -1.0 + (q + 0.5) * h
-        S = log_density_sum(f, x)
-        inside, margin = _in_shell(f, x)
-        keep = inside | (S >= thr)
-        near = (np.abs(S - thr) <= AMBIGUOUS_REL * max(1.0, abs(thr))) & ~inside
-        near |= margin <= AMBIGUOUS_REL * (1.0 + f.shell_half_width)
-        kept.append(codes[keep])
-        amb.append(codes[near])
-    return np.concatenate(kept), np.concatenate(amb)
+    total = (1 << depth) ** 3
+    jobs = [(f, depth, thr, a, min(total, a + chunk)) for a in range(0, total, chunk)]
+    if workers > 1 and len(jobs) > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(workers) as ex:
+            parts = list(ex.map(_centre_chunk, jobs))
+    else:
+        parts = [_centre_chunk(j) for j in jobs]
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
 
 def average_samples(f: Field, depth: int, codes, n_samples: int = 256, seed: int = 0,

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblumiq.so")
 SOURCES = ["api.hip", "proxy_shade.hip", "octree_query.hip", "octree_query_f32.hip", "octree_query_f16.hip",
-           "octree_query_bf16.hip", "mlp.hip"]
+           "octree_query_bf16.hip", "mlp.hip", "distill.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

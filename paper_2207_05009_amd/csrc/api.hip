@@ -361,6 +361,44 @@ void lq_free_octree(lq_octree *t) {
     delete t;
 }
 
+lq_status lq_octree_download(const lq_octree *t, int32_t *child, float *sigma, float *sh) {
+    if (!t) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");
+    hipError_t e = hipSetDevice(t->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const DevTree &dt = t->t;
+    if (child && (e = hipMemcpy(child, t->d_child, (size_t)dt.n_nodes * 32, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "reading the child table");
+    if (!sigma && !sh) return LQ_OK;
+    const int esz = dt.storage == LQ_F32 ? 4 : 2;
+    const size_t rb = (size_t)dt.row_elems * esz;
+    std::vector<uint8_t> rows((size_t)dt.n_leaves * rb);
+    if (!rows.empty() && (e = hipMemcpy(rows.data(), t->d_rows, rows.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "reading the leaf rows");
+    auto value = [&](const uint8_t *row, int j) -> float {
+        if (dt.storage == LQ_F32) {
+            float f;
+            memcpy(&f, row + 4 * j, 4);
+            return f;
+        }
+        uint16_t b;
+        memcpy(&b, row + 2 * j, 2);
+        if (dt.storage == LQ_BF16) {
+            const uint32_t u = (uint32_t)b << 16;
+            float f;
+            memcpy(&f, &u, 4);
+            return f;
+        }
+        return (float)__builtin_bit_cast(_Float16, b);
+    };
+    for (int64_t i = 0; i < dt.n_leaves; ++i) {
+        const uint8_t *row = rows.data() + (size_t)i * rb;
+        if (sigma) sigma[i] = value(row, 0);
+        if (sh)
+            for (int j = 0; j < 3 * dt.K; ++j) sh[(size_t)i * 3 * dt.K + j] = value(row, 1 + j);
+    }
+    return LQ_OK;
+}
+
 lq_status lq_octree_info(const lq_octree *t, int64_t *device_bytes, int32_t *n_nodes, int32_t *n_leaves,
                          int32_t *max_depth, int32_t *sh_degree, int32_t *storage) {
     if (!t) return fail(LQ_ERR_INVALID_ARG, "tree is NULL");

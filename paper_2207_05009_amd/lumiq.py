@@ -39,6 +39,13 @@ class OctreeDesc(C.Structure):
                 ("sh", C.c_void_p)]
 
 
+class FieldDesc(C.Structure):
+    _fields_ = [("n_blobs", C.c_int32), ("n_shells", C.c_int32), ("sh_degree", C.c_int32),
+                ("reserved", C.c_int32), ("blobs", C.c_void_p), ("blob_sh", C.c_void_p),
+                ("shells", C.c_void_p), ("shell_half_width", C.c_double),
+                ("log_density_base", C.c_double), ("sigma_max", C.c_double), ("l_max", C.c_double)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -64,9 +71,15 @@ def lib():
                                          vp, vp, vp, vp, vp, vp, i32, vp]
             L.lq_query_radiance_image.argtypes = [vp, vp, vp, i32, i32, vp, vp, C.c_int, u32, vp]
             L.lq_proxy_irradiance.argtypes = [vp, vp, vp, i64, vp, i32, vp, C.c_int, vp, vp, vp]
+            L.lq_distill_leaves.argtypes = [C.POINTER(FieldDesc), i32, C.c_float, i32, C.c_uint64, C.c_int,
+                                            i64, vp, vp, vp, C.POINTER(i64), vp]
+            L.lq_octree_from_leaves.argtypes = [i32, i32, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
+                                                C.c_int, C.c_int, C.POINTER(vp)]
+            L.lq_octree_download.argtypes = [vp, vp, vp, vp]
             for name in ("lq_load_octree_desc", "lq_load_octree", "lq_octree_info",
                          "lq_query_radiance", "lq_query_trace", "lq_query_radiance_image",
-                         "lq_proxy_irradiance"):
+                         "lq_proxy_irradiance", "lq_distill_leaves", "lq_octree_from_leaves",
+                         "lq_octree_download"):
                 getattr(L, name).restype = C.c_int
             _lib = L
     return _lib
@@ -111,6 +124,26 @@ class Octree:
                               child.ctypes.data, sigma.ctypes.data if sigma.size else None,
                               sh.ctypes.data if sh.size else None)
             check(lib().lq_load_octree_desc(C.byref(desc), st, device, C.byref(self.handle)))
+
+    @classmethod
+    def _adopt(cls, handle, storage: str, device: int) -> "Octree":
+        self = cls.__new__(cls)
+        self.handle = handle
+        self.device = device
+        self.storage = storage
+        return self
+
+    def download(self) -> dict:
+        """The tree's tables as stored: child [n_nodes, 8] int32, sigma
+        [n_leaves] and sh [n_leaves, 3, K] float32 (numpy)."""
+        inf = self.info()
+        K = (inf["sh_degree"] + 1) ** 2
+        child = np.zeros((inf["n_nodes"], 8), np.int32)
+        sigma = np.zeros(inf["n_leaves"], np.float32)
+        sh = np.zeros((inf["n_leaves"], 3, K), np.float32)
+        check(lib().lq_octree_download(self.handle, child.ctypes.data, sigma.ctypes.data if sigma.size else None,
+                                       sh.ctypes.data if sh.size else None))
+        return {"child": child, "sigma": sigma, "sh": sh}
 
     def info(self) -> dict:
         v = [C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()]
@@ -203,6 +236,58 @@ class Octree:
         if ids is not None:
             out["leaf_ids"] = ids
         return out
+
+
+def field_desc(p: dict):
+    """lq_field_desc from field parameters (centres [nb, 3], radii, amps,
+    emission [nb, 3], hi [nb, 3, K-1], shells [ns, 4], shell_half_width,
+    log_base, sigma_max, l_max, sh_degree).  Returns (desc, arrays kept
+    alive)."""
+    nb = len(p["radii"])
+    blobs = np.ascontiguousarray(np.concatenate([np.asarray(p["centres"], np.float64).reshape(nb, 3),
+                                                 np.asarray(p["radii"], np.float64).reshape(nb, 1),
+                                                 np.asarray(p["amps"], np.float64).reshape(nb, 1),
+                                                 np.asarray(p["emission"], np.float64).reshape(nb, 3)], axis=1))
+    hi = np.ascontiguousarray(np.asarray(p["hi"], np.float64).reshape(-1))
+    shells = np.ascontiguousarray(np.asarray(p["shells"], np.float64).reshape(-1, 4))
+    desc = FieldDesc(nb, shells.shape[0], int(p["sh_degree"]), 0, blobs.ctypes.data,
+                     hi.ctypes.data if hi.size else None, shells.ctypes.data if shells.size else None,
+                     float(p["shell_half_width"]), float(p["log_base"]), float(p["sigma_max"]), float(p["l_max"]))
+    return desc, (blobs, hi, shells)
+
+
+def distill_leaves(params: dict, depth: int, prune_sigma: float = 0.01, n_samples: int = 256, seed: int = 0,
+                   device: int = 0, stream=None):
+    """Plenoctree distillation of a continuous field (Sec. 5): returns the
+    kept voxels' Morton codes (int32 view of the uint32 codes, ascending),
+    mean densities and mean SH coefficients as CUDA tensors."""
+    import torch
+    L = lib()
+    desc, keep = field_desc(params)
+    n = C.c_int64()
+    check(L.lq_distill_leaves(C.byref(desc), depth, prune_sigma, n_samples, seed, device, 0, None, None, None,
+                              C.byref(n), _stream(stream)))
+    K = (int(params["sh_degree"]) + 1) ** 2
+    dev = torch.device("cuda", device)
+    codes = torch.empty((max(n.value, 1),), dtype=torch.int32, device=dev)
+    sigma = torch.empty((max(n.value, 1),), dtype=torch.float32, device=dev)
+    sh = torch.empty((max(n.value, 1), 3, K), dtype=torch.float32, device=dev)
+    check(L.lq_distill_leaves(C.byref(desc), depth, prune_sigma, n_samples, seed, device, n.value, _ptr(codes),
+                              _ptr(sigma), _ptr(sh), C.byref(n), _stream(stream)))
+    del keep
+    return codes[: n.value], sigma[: n.value], sh[: n.value]
+
+
+def octree_from_leaves(depth: int, sh_degree: int, codes, sigma, sh, l_max: float = 2048.0,
+                       sigma_min: float = 0.1, alpha_max: float = 0.9, storage: str = "f32",
+                       device: int = 0) -> Octree:
+    """An Octree (device-built child table) from leaves at max depth."""
+    h = C.c_void_p()
+    n = codes.shape[0]
+    check(lib().lq_octree_from_leaves(depth, sh_degree, _ptr(codes) if n else None, _ptr(sigma) if n else None,
+                                      _ptr(sh) if n else None, n, l_max, sigma_min, alpha_max, STORAGE[storage],
+                                      device, C.byref(h)))
+    return Octree._adopt(h, storage, device)
 
 
 def version() -> str:

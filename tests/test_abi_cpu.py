@@ -131,3 +131,29 @@ def test_image_query_argument_errors(L):
 def test_proxy_irradiance_argument_errors(L):
     assert L.lq_proxy_irradiance(None, None, None, 4, None, 8, None, 0, None, None, None) == -1
     assert b"tree" in L.lq_last_error()
+
+
+def test_distillation_rejects_bad_fields(L):
+    """lq_distill_leaves checks its field before touching a device."""
+    from paper_2207_05009_amd import lumiq
+    from inputs.trees import field_params
+    p = field_params(inputs.TreeSpec(depth=3, n_blobs=4, n_shells=1, sh_degree=2, seed=1, occupancy=0.3))
+    n = C.c_int64()
+    assert L.lq_distill_leaves(None, 3, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -1
+    desc, keep = lumiq.field_desc(p)
+    assert L.lq_distill_leaves(C.byref(desc), 11, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -1
+    assert L.lq_distill_leaves(C.byref(desc), 3, 0.0, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -1
+    assert L.lq_distill_leaves(C.byref(desc), 3, 0.01, 0, 0, 0, 0, None, None, None, C.byref(n), None) == -1
+    desc.n_blobs = 33
+    assert L.lq_distill_leaves(C.byref(desc), 3, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -5
+    desc.n_blobs = 4
+    desc.sh_degree = 5
+    assert L.lq_distill_leaves(C.byref(desc), 3, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -5
+    bad = dict(p)
+    bad["emission"] = np.asarray(p["emission"]) * 0.0
+    d2, keep2 = lumiq.field_desc(bad)
+    assert L.lq_distill_leaves(C.byref(d2), 3, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -1
+    assert b"radiance" in L.lq_last_error()
+    h = C.c_void_p()
+    assert L.lq_octree_from_leaves(11, 2, None, None, None, 0, 2048.0, 0.1, 0.9, 0, 0, C.byref(h)) == -1
+    assert L.lq_octree_download(None, None, None, None) == -1
