@@ -189,3 +189,10 @@ def sample_numbers(n: int, samples: int, seed: int):
     """Uniform numbers in [0, 1) for the proxy samples, [n, samples, 3] float32."""
     rng = np.random.default_rng(seed)
     return rng.random((n, samples, 3), dtype=np.float32)
+
+
+def probe_numbers(n_cells: int, probes: int, seed: int):
+    """Uniform numbers in [0, 1) for the guide's probe rays, [n_cells,
+    probes, 5] float32 (a point of the cell, a target in the box)."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n_cells, probes, 5), dtype=np.float32)

@@ -87,3 +87,136 @@ def proxy_irradiance(tree, points, normals, u, background=(0.0, 0.0, 0.0), model
     terms_alt = (w[:, None] * lo_alt).reshape(n, S, 3)
     return {"E": terms.mean(axis=1), "terms": terms, "terms_alt": terms_alt,
             "alt_valid": q["alt_valid"].reshape(n, S).astype(bool), "w": w.reshape(n, S)}
+
+
+# ---------------------------------------------------------------- guided sampling
+# Importance sampling of the proxy according to the radiance field (the
+# paper's stated future work, Sec. 6 "Sampling" and Sec. 7 "Limitations --
+# Sampling"; the design below is this project's).  The proxy surface is cut
+# into 6 G^2 cells (face f, then G x G cells on it along the face's next two
+# axes in cyclic order).  The guide weight of a cell is the mean luminance
+# (channel mean) of the emission the query returns for probe rays that start
+# at uniform points of the cell and aim at uniform points inside the box.
+# A sample picks cell k with probability
+#     p_k = (1 - beta) w_k / sum_i w_i + beta / (6 G^2)
+# (the defensive share beta keeps every cell reachable: the light behind
+# the luminaire also passes where it emits nothing) and a uniform point in
+# it, so its area density is p_k / A_cell with A_cell = (2 / G)^2.
+
+def guide_cells(G):
+    return 6 * G * G
+
+
+def _cell_point(cell, ua, ub, G):
+    """Face point of (cell, ua, ub) in float32 with the operations the
+    definition lists; returns (y [m, 3] float32, face, axis, sign)."""
+    cell = np.asarray(cell, np.int64)
+    face = cell // (G * G)
+    ca = (cell // G) % G
+    cb = cell % G
+    axis = face >> 1
+    sgn = np.where(face & 1, np.float32(1.0), np.float32(-1.0)).astype(np.float32)
+    step = np.float32(2.0 / G)
+    a = (ca.astype(np.float32) + ua.astype(np.float32)) * step - np.float32(1.0)
+    b = (cb.astype(np.float32) + ub.astype(np.float32)) * step - np.float32(1.0)
+    y = np.empty((cell.size, 3), np.float32)
+    rows = np.arange(cell.size)
+    y[rows, axis] = sgn
+    y[rows, (axis + 1) % 3] = a
+    y[rows, (axis + 2) % 3] = b
+    return y, face, axis, sgn
+
+
+def guide_probe_rays(G, u_probe):
+    """Probe rays of the guide: u_probe [6 G^2, R, 5] in [0, 1): a point of
+    the cell (two numbers) and a target inside the box (three); the ray
+    starts on the face and points at the target (float32, d = t - y)."""
+    u = np.ascontiguousarray(u_probe, np.float32)
+    n_cells, R = u.shape[0], u.shape[1]
+    cell = np.repeat(np.arange(n_cells), R)
+    uu = u.reshape(-1, 5)
+    y, _, _, _ = _cell_point(cell, uu[:, 0], uu[:, 1], G)
+    t = uu[:, 2:5] * np.float32(2.0) - np.float32(1.0)
+    d = (t - y).astype(np.float32)
+    return y, d
+
+
+def guide_weights(tree, G, u_probe, model: int = core.LINEAR, storage: str = "f32"):
+    """Mean probe luminance per cell (float64), and the oracle's query
+    output on the probes (for candidate checks)."""
+    o, d = guide_probe_rays(G, u_probe)
+    q = core.query(tree, o, d, model=model, storage=storage)
+    R = np.asarray(u_probe).shape[1]
+    lum = q["L"].mean(1).reshape(-1, R)
+    return lum.mean(1), q
+
+
+def guide_cdf(weights, beta):
+    """Cell probabilities and their cumulative sums in FP64, summed in cell
+    order: W = w_0 + w_1 + ..., p_k = (1 - beta) (w_k / W) + beta / n (all
+    1 / n when W = 0), cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k."""
+    w = [float(v) for v in np.asarray(weights, np.float32)]
+    n = len(w)
+    W = 0.0
+    for v in w:
+        W += v
+    if W > 0.0:
+        p = [(1.0 - beta) * (v / W) + beta / n for v in w]
+    else:
+        p = [1.0 / n] * n
+    cdf = [0.0] * (n + 1)
+    for k in range(n):
+        cdf[k + 1] = cdf[k] + p[k]
+    return np.array(p), np.array(cdf)
+
+
+def guided_proxy_rays(points, normals, u, weights, G, beta):
+    """Rays and weights of guided samples: u [n, S, 3]: u0 picks the cell
+    (the largest k < 6 G^2 whose cdf[k] <= u0), u1, u2 the point in it.  The
+    Monte Carlo weight is cos(theta_x) cos(theta_y) / (|y - x|^2 p_A) with
+    p_A = p_k / A_cell; zero for back faces and below the horizon."""
+    x = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
+    nrm = np.asarray(normals, np.float64).reshape(-1, 3)
+    u = np.ascontiguousarray(u, np.float32)
+    n, S = u.shape[0], u.shape[1]
+    u = u.reshape(n * S, 3)
+    p, cdf = guide_cdf(weights, beta)
+    n_cells = p.size
+    cell = np.searchsorted(cdf[:n_cells], u[:, 0].astype(np.float64), side="right") - 1
+    cell = np.clip(cell, 0, n_cells - 1)
+    y, face, axis, sgn = _cell_point(cell, u[:, 1], u[:, 2], G)
+    rows = np.arange(n * S)
+    xs = np.repeat(x, S, axis=0)
+    d = (y - xs).astype(np.float32)
+    d64 = d.astype(np.float64)
+    dist2 = np.einsum("ij,ij->i", d64, d64)
+    dist = np.sqrt(dist2)
+    ns = np.repeat(nrm, S, axis=0)
+    nlen = np.linalg.norm(ns, axis=1)
+    cos_x = np.einsum("ij,ij->i", ns, d64) / np.where(nlen * dist > 0, nlen * dist, 1.0)
+    h = sgn.astype(np.float64) * xs.astype(np.float64)[rows, axis] - 1.0
+    cos_y = h / np.where(dist > 0, dist, 1.0)
+    area = (2.0 / G) ** 2
+    pa = p[cell] / area
+    ok = (h > 0) & (cos_x > 0) & (dist2 > 0) & (nlen > 0) & (pa > 0)
+    w = np.where(ok, cos_x * cos_y / np.where(dist2 > 0, dist2, 1.0) / np.where(pa > 0, pa, 1.0), 0.0)
+    d[~ok] = 0.0
+    return xs, d, w, cell
+
+
+def proxy_irradiance_guided(tree, points, normals, u, weights, G, beta, background=(0.0, 0.0, 0.0),
+                            model: int = core.LINEAR, storage: str = "f32") -> dict:
+    """The guided estimate per point (E [n, 3]) and its terms, as
+    proxy_irradiance does for uniform sampling."""
+    u = np.asarray(u, np.float32)
+    n, S = u.shape[0], u.shape[1]
+    o, d, w, cell = guided_proxy_rays(points, normals, u, weights, G, beta)
+    q = core.query(tree, o, d, model=model, storage=storage)
+    B = np.asarray(background, np.float64)[None, :]
+    lo = q["L"] + (1.0 - q["alpha"])[:, None] * B
+    lo_alt = q["alt_L"] + (1.0 - q["alt_alpha"])[:, None] * B
+    terms = (w[:, None] * lo).reshape(n, S, 3)
+    terms_alt = (w[:, None] * lo_alt).reshape(n, S, 3)
+    return {"E": terms.mean(axis=1), "terms": terms, "terms_alt": terms_alt,
+            "alt_valid": q["alt_valid"].reshape(n, S).astype(bool), "w": w.reshape(n, S),
+            "cell": cell.reshape(n, S)}

@@ -139,3 +139,105 @@ def test_only_front_faces_carry_weight():
     face = np.minimum((u[0, :, 0] * np.float32(6.0)).astype(np.int32), 5)
     assert np.all(w[face != 4] == 0.0) and np.all(w[face == 4] > 0.0)
     assert abs(np.mean(face == 4) - 1 / 6) < 0.03
+
+
+# ---------------------------------------------------------------- guided sampling
+G = 8
+
+
+def _random_guide(seed, zeros=0.3):
+    rng = np.random.default_rng(seed)
+    w = rng.exponential(1.0, shade.guide_cells(G)).astype(np.float32)
+    w[rng.random(w.size) < zeros] = 0.0
+    return w
+
+
+def test_uniform_guide_is_area_uniform():
+    """With equal cell weights the guided density is the uniform one: every
+    live sample's weight is cos cos / r^2 times 24 (the box's area)."""
+    x = np.array([[0.4, -0.3, -2.7]], np.float32)
+    n = np.array([[0.1, 0.2, 1.0]], np.float32)
+    u = inputs.rays.sample_numbers(1, 4096, 21)
+    for beta in (0.0, 0.3, 1.0):
+        o, d, w, cell = shade.guided_proxy_rays(x, n, u, np.ones(shade.guide_cells(G), np.float32), G, beta)
+        live = w > 0
+        d64 = d[live].astype(np.float64)
+        r2 = (d64 ** 2).sum(1)
+        nn = n[0].astype(np.float64)
+        cos_x = d64 @ (nn / np.linalg.norm(nn)) / np.sqrt(r2)
+        cos_y = (-x[0, 2].astype(np.float64) - 1.0) / np.sqrt(r2)     # bottom face (z = -1)
+        assert np.allclose(w[live] * r2 / (cos_x * cos_y), 24.0, rtol=1e-9)
+
+
+def test_cell_frequencies_follow_the_guide():
+    """Cells are picked with probability p_k = (1 - beta) w_k / W + beta / n:
+    counts within 5 standard deviations; with beta = 0 a cell of weight 0
+    is never picked."""
+    w = _random_guide(3)
+    S = 400_000
+    u = inputs.rays.sample_numbers(1, S, 22)
+    x = np.array([[0.0, 0.0, -3.0]], np.float32)
+    n = np.array([[0.0, 0.0, 1.0]], np.float32)
+    for beta in (0.0, 0.25):
+        _, _, _, cell = shade.guided_proxy_rays(x, n, u, w, G, beta)
+        p, cdf = shade.guide_cdf(w, beta)
+        assert cdf[-1] == pytest.approx(1.0, abs=1e-12)
+        cnt = np.bincount(cell, minlength=p.size)
+        sd = np.sqrt(S * p * (1 - p))
+        assert np.all(np.abs(cnt - S * p) <= 5 * sd + 1e-9)
+        if beta == 0.0:
+            assert np.all(cnt[w == 0] == 0)
+
+
+@pytest.mark.parametrize("pose", range(len(POSES)))
+def test_guided_estimate_is_unbiased(pose):
+    """The guided estimator against Lambert's closed form: an opaque uniform
+    luminaire (E = Phi times the projected solid angle) and an empty one
+    passing the background (E = L_b times it), with a guide that favours
+    some cells and ignores others (defensive share 0.2), within 5 standard
+    errors."""
+    x, n = POSES[pose]
+    ref = _box_projected_solid_angle(x, n)
+    w = _random_guide(10 + pose)
+    S = 100_000
+    u = inputs.rays.sample_numbers(1, S, 60 + pose)
+    c = np.array([[-1.0], [0.5], [2.0]])
+    tree = inputs.uniform_tree(2, 1e6, c)
+    phi = inputs.L_MAX / (1.0 + np.exp(-c[:, 0].astype(np.float32).astype(np.float64) * Y00))
+    r = shade.proxy_irradiance_guided(tree, np.array([x], np.float32), np.array([n], np.float32), u, w, G, 0.2)
+    se = r["terms"][0].std(axis=0) / math.sqrt(S)
+    assert np.all(np.abs(r["E"][0] - phi * ref) < 5 * se + 1e-9), (r["E"][0], phi * ref, se)
+    B = np.array([0.5, 1.25, 2.0])
+    r = shade.proxy_irradiance_guided(inputs.empty_tree(3), np.array([x], np.float32), np.array([n], np.float32),
+                                      u, w, G, 0.2, background=B)
+    se = r["terms"][0].std(axis=0) / math.sqrt(S)
+    assert np.all(np.abs(r["E"][0] - B * ref) < 5 * se + 1e-12), (r["E"][0], B * ref, se)
+
+
+def test_guide_of_an_opaque_uniform_luminaire():
+    """Every probe of an opaque uniform luminaire sees its emission Phi, so
+    every cell's guide weight is Phi's luminance (channel mean)."""
+    c = np.array([[-1.0], [0.5], [2.0]])
+    tree = inputs.uniform_tree(2, 1e6, c)
+    phi = inputs.L_MAX / (1.0 + np.exp(-c[:, 0].astype(np.float32).astype(np.float64) * Y00))
+    u = inputs.rays.probe_numbers(shade.guide_cells(4), 8, 23)
+    wts, _ = shade.guide_weights(tree, 4, u)
+    assert np.allclose(wts, phi.mean(), rtol=1e-9)
+    # and of an empty one: all zero, so the guided density falls back to uniform
+    wts, _ = shade.guide_weights(inputs.empty_tree(3), 4, u)
+    p, _ = shade.guide_cdf(wts, 0.0)
+    assert np.all(wts == 0.0) and np.allclose(p, 1.0 / p.size)
+
+
+def test_guide_probes_start_on_their_cell():
+    u = inputs.rays.probe_numbers(shade.guide_cells(2), 3, 24)
+    o, d = shade.guide_probe_rays(2, u)
+    for c in range(shade.guide_cells(2)):
+        face, ca, cb = c // 4, (c // 2) % 2, c % 2
+        axis, sgn = face >> 1, (1.0 if face & 1 else -1.0)
+        pts = o[3 * c: 3 * c + 3]
+        assert np.all(pts[:, axis] == sgn)
+        a, b = pts[:, (axis + 1) % 3], pts[:, (axis + 2) % 3]
+        assert np.all((a >= -1 + ca) & (a <= ca)) and np.all((b >= -1 + cb) & (b <= cb))
+        # the probes aim into the box
+        assert np.all(d[3 * c: 3 * c + 3, axis] * sgn < 0)
