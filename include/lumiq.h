@@ -238,6 +238,50 @@ lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const 
                               const float *background_rgb, int model, float *irradiance,
                               float *sample_terms, void *hip_stream);
 
+/*
+ * Radiance-field-guided sampling of the proxy: the importance sampling that
+ * the paper leaves as future work (Sec. 6, Sampling; Sec. 7, Limitations --
+ * Sampling), in a form of this library's.  The proxy's surface is cut into
+ * 6 grid^2 cells: face f (as in lq_proxy_irradiance), then grid x grid
+ * cells on it along the face's next two axes in cyclic order, cell
+ * k = (f grid + i) grid + j.
+ *
+ * lq_proxy_guide: the guide weight of every cell, the mean luminance (mean
+ * of R, G, B) of the emission that lq_query_radiance returns for n_probes
+ * probe rays per cell.  Probe r of cell k reads u_probe[k][r][0..4] in
+ * [0, 1): it starts at the cell's point with coordinates
+ * -1 + (i + u0) 2 / grid and -1 + (j + u1) 2 / grid (float32) and aims at
+ * the point 2 (u2, u3, u4) - 1 inside the box.  weights [6 grid^2] float32,
+ * u_probe [6 grid^2][n_probes][5] float32: device arrays.  The probe
+ * luminances are summed in FP64 in probe order.
+ *
+ * lq_proxy_irradiance_guided: lq_proxy_irradiance with the sample's cell
+ * drawn from the guide.  With W the sum of the weights (any non-negative
+ * finite values), cell k has probability
+ *     p_k = (1 - defensive) w_k / W + defensive / (6 grid^2)
+ * (1 / (6 grid^2) each when W = 0), summed in cell order in FP64 into
+ * cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.  A point receives light only
+ * through the faces it sees from the front (side * x_axis > 1), so its
+ * samples pick among those faces' cells: with P_f = cdf[(f + 1) grid^2] -
+ * cdf[f grid^2] and P_vis the sum of P_f over the visible faces, sample s
+ * of point i walks the visible faces in order with t = u[i][s][0] P_vis;
+ * in the face where t < P_f (the last visible face takes any remainder) it
+ * picks the largest cell k of the face with cdf[k] <= cdf[f grid^2] + t,
+ * and the point of that cell at u[i][s][1], u[i][s][2] as above.  Its area
+ * density is p_k / (P_vis (2 / grid)^2), and its term L_o cos(theta_x)
+ * cos(theta_y) / (|y - x|^2 p_A) (zero as in lq_proxy_irradiance, for a
+ * point that sees no face, and for a cell of p_k = 0).  The estimate stays
+ * unbiased for any guide with defensive > 0; defensive in [0, 1], grid in
+ * 1..256.  Scratch: as lq_proxy_irradiance plus 8 (12 grid^2 + 1) bytes.
+ */
+lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t n_probes, const float *u_probe,
+                         int model, float *weights, void *hip_stream);
+lq_status lq_proxy_irradiance_guided(const lq_octree *tree, const float *points, const float *normals,
+                                     int64_t n_points, const float *u, int32_t n_samples,
+                                     const float *weights, int32_t grid, float defensive,
+                                     const float *background_rgb, int model, float *irradiance,
+                                     float *sample_terms, void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Plenoctree distillation (Sec. 5, "Creating the plenoctree"): a density
  * sample at the centre of every voxel of the finest grid (2^max_depth per

@@ -196,3 +196,12 @@ def probe_numbers(n_cells: int, probes: int, seed: int):
     probes, 5] float32 (a point of the cell, a target in the box)."""
     rng = np.random.default_rng(seed)
     return rng.random((n_cells, probes, 5), dtype=np.float32)
+
+
+def guide_weights(n_cells: int, seed: int, zero_fraction: float = 0.3):
+    """Synthetic guide weights for the proxy's cells: exponential values with
+    a share of exact zeros, float32."""
+    rng = np.random.default_rng(seed)
+    w = rng.exponential(1.0, n_cells).astype(np.float32)
+    w[rng.random(n_cells) < zero_fraction] = 0.0
+    return w

@@ -97,11 +97,16 @@ def proxy_irradiance(tree, points, normals, u, background=(0.0, 0.0, 0.0), model
 # axes in cyclic order).  The guide weight of a cell is the mean luminance
 # (channel mean) of the emission the query returns for probe rays that start
 # at uniform points of the cell and aim at uniform points inside the box.
-# A sample picks cell k with probability
+# The cells have the probabilities
 #     p_k = (1 - beta) w_k / sum_i w_i + beta / (6 G^2)
 # (the defensive share beta keeps every cell reachable: the light behind
-# the luminaire also passes where it emits nothing) and a uniform point in
-# it, so its area density is p_k / A_cell with A_cell = (2 / G)^2.
+# the luminaire also passes where it emits nothing).  A shading point x only
+# receives light through the faces it sees from the front (sgn x_axis > 1);
+# the others contribute exactly zero, so a sample of x picks among the cells
+# of those faces only, with probability p_k / P_vis(x) (P_vis the sum of
+# p over them), and a uniform point in the cell: its area density is
+# p_k / (P_vis A_cell) with A_cell = (2 / G)^2.  The estimate is unbiased
+# whenever every cell of a visible face has p_k > 0 (beta > 0 ensures it).
 
 def guide_cells(G):
     return 6 * G * G
@@ -170,20 +175,71 @@ def guide_cdf(weights, beta):
     return np.array(p), np.array(cdf)
 
 
+def visible_faces(x):
+    """[n, 6] bool: the faces x sees from the front (face f: axis f >> 1,
+    side -1 for even f, +1 for odd; visible iff side * x_axis > 1)."""
+    x = np.asarray(x, np.float32).reshape(-1, 3)
+    out = np.zeros((x.shape[0], 6), bool)
+    for f in range(6):
+        sgn = np.float32(1.0) if f & 1 else np.float32(-1.0)
+        out[:, f] = sgn * x[:, f >> 1] > np.float32(1.0)
+    return out
+
+
+def guided_cell(cdf, G, vis, u0):
+    """The cell a sample picks: t = u0 P_vis walks the visible faces in
+    order (face f holds cells [f G^2, (f + 1) G^2) and probability
+    P_f = cdf[(f + 1) G^2] - cdf[f G^2]): in the face where t < P_f (the
+    last visible face takes any remainder) the cell is the largest k of the
+    face with cdf[k] <= cdf[f G^2] + t.  Returns (cell, P_vis); cell -1 when
+    no face is visible or P_vis = 0."""
+    gg = G * G
+    P = [cdf[(f + 1) * gg] - cdf[f * gg] for f in range(6)]
+    pv = 0.0
+    for f in range(6):
+        if vis[f]:
+            pv += P[f]
+    if not pv > 0.0:
+        return -1, 0.0
+    t = float(u0) * pv
+    last = max(f for f in range(6) if vis[f])
+    for f in range(6):
+        if not vis[f]:
+            continue
+        if t < P[f] or f == last:
+            target = cdf[f * gg] + t
+            lo, hi = f * gg, f * gg + gg - 1
+            while lo < hi:
+                mid = (lo + hi + 1) // 2
+                if cdf[mid] <= target:
+                    lo = mid
+                else:
+                    hi = mid - 1
+            return lo, pv
+        t -= P[f]
+    return -1, 0.0
+
+
 def guided_proxy_rays(points, normals, u, weights, G, beta):
     """Rays and weights of guided samples: u [n, S, 3]: u0 picks the cell
-    (the largest k < 6 G^2 whose cdf[k] <= u0), u1, u2 the point in it.  The
-    Monte Carlo weight is cos(theta_x) cos(theta_y) / (|y - x|^2 p_A) with
-    p_A = p_k / A_cell; zero for back faces and below the horizon."""
+    among the faces the point sees (guided_cell), u1, u2 the point in it.
+    The Monte Carlo weight is cos(theta_x) cos(theta_y) / (|y - x|^2 p_A)
+    with p_A = p_k / (P_vis A_cell); zero below the horizon, and for a point
+    that sees no face."""
     x = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
     nrm = np.asarray(normals, np.float64).reshape(-1, 3)
     u = np.ascontiguousarray(u, np.float32)
     n, S = u.shape[0], u.shape[1]
     u = u.reshape(n * S, 3)
     p, cdf = guide_cdf(weights, beta)
-    n_cells = p.size
-    cell = np.searchsorted(cdf[:n_cells], u[:, 0].astype(np.float64), side="right") - 1
-    cell = np.clip(cell, 0, n_cells - 1)
+    vis = visible_faces(x)
+    cell = np.empty(n * S, np.int64)
+    pvis = np.zeros(n * S)
+    for i in range(n):
+        for j in range(S):
+            cell[i * S + j], pvis[i * S + j] = guided_cell(cdf, G, vis[i], u[i * S + j, 0])
+    dead = cell < 0
+    cell = np.where(dead, 0, cell)
     y, face, axis, sgn = _cell_point(cell, u[:, 1], u[:, 2], G)
     rows = np.arange(n * S)
     xs = np.repeat(x, S, axis=0)
@@ -197,7 +253,7 @@ def guided_proxy_rays(points, normals, u, weights, G, beta):
     h = sgn.astype(np.float64) * xs.astype(np.float64)[rows, axis] - 1.0
     cos_y = h / np.where(dist > 0, dist, 1.0)
     area = (2.0 / G) ** 2
-    pa = p[cell] / area
+    pa = np.where(dead, 0.0, p[cell] / np.where(dead, 1.0, pvis) / area)
     ok = (h > 0) & (cos_x > 0) & (dist2 > 0) & (nlen > 0) & (pa > 0)
     w = np.where(ok, cos_x * cos_y / np.where(dist2 > 0, dist2, 1.0) / np.where(pa > 0, pa, 1.0), 0.0)
     d[~ok] = 0.0

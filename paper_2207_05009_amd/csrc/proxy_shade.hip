@@ -46,9 +46,63 @@ __global__ void k_proxy_zero(unsigned long long *p) { p[0] = 0ull; }
 // on it.
 constexpr int kCellsPerSide = 4;
 constexpr int kAimCells = 6 * kCellsPerSide * kCellsPerSide;
+// Guided sampling (cdf != null): the sample picks a cell of the faces its
+// point sees from the front (the others contribute nothing): with P_f the
+// probability of face f's cells (cdf[(f + 1) G^2] - cdf[f G^2]) and P_vis
+// their sum over the visible faces, t = u0 P_vis walks the visible faces in
+// order, and in the face where t < P_f (the last visible one takes any
+// remainder) the cell is the largest k of the face with cdf[k] <=
+// cdf[f G^2] + t (FP64, in the order the table was summed); u1, u2 give
+// the point in the cell, and the area density is p_k / (P_vis A_cell).
+struct Guide {
+    const double *cdf;    // [n_cells + 1], or null: uniform sampling
+    const double *prob;   // [n_cells]
+    int G, n_cells;
+    float step;           // 2 / G (float32)
+    double area;          // (2 / G)^2
+};
+
+// returns the cell (or -1 when the point sees no face, or P_vis = 0) and P_vis
+__device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, float u0, double &pvis) {
+    const int gg = g.G * g.G;
+    bool vis[6];
+    double P[6];
+    double pv = 0.0;
+    int last = -1;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const float xa = (f >> 1) == 0 ? x0 : ((f >> 1) == 1 ? x1 : x2);
+        vis[f] = ((f & 1) ? xa : -xa) > 1.0f;
+        P[f] = g.cdf[(f + 1) * gg] - g.cdf[f * gg];
+        if (vis[f]) {
+            pv += P[f];
+            last = f;
+        }
+    }
+    pvis = pv;
+    if (!(pv > 0.0)) return -1;
+    double t = (double)u0 * pv;
+    for (int f = 0; f < 6; ++f) {
+        if (!vis[f]) continue;
+        if (t < P[f] || f == last) {
+            const double target = g.cdf[f * gg] + t;
+            int lo = f * gg, hi = f * gg + gg - 1;   // cdf[lo] <= target holds for lo = f gg
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (g.cdf[mid] <= target) lo = mid;
+                else hi = mid - 1;
+            }
+            return lo;
+        }
+        t -= P[f];
+    }
+    return -1;
+}
+
 __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points, const float *normals, int64_t m,
                                                             int S, const float *u, float *o, float *d, float *w,
-                                                            int64_t *live, unsigned long long *n_live) {
+                                                            int64_t *live, unsigned long long *n_live,
+                                                            const Guide g) {
     __shared__ unsigned s_cell[kAimCells];
     __shared__ unsigned long long s_base;
     for (int c = threadIdx.x; c < kAimCells; c += kShadeBlock) s_cell[c] = 0;
@@ -66,11 +120,27 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
             const float x0 = points[3 * i], x1 = points[3 * i + 1], x2 = points[3 * i + 2];
             const float n0 = normals[3 * i], n1 = normals[3 * i + 1], n2 = normals[3 * i + 2];
             const float u0 = u[3 * j], u1 = u[3 * j + 1], u2 = u[3 * j + 2];
-            int f = (int)(u0 * 6.0f);
-            f = f < 0 ? 0 : (f > 5 ? 5 : f);
+            int f;
+            float a, b, inv_density = kInvAreaDensity;
+            if (g.cdf) {
+                double pvis = 0.0;
+                int k = guide_cell(g, x0, x1, x2, u0, pvis);
+                const double pk = k >= 0 ? g.prob[k] : 0.0;
+                inv_density = pk > 0.0 ? (float)(pvis * g.area / pk) : 0.0f;
+                k = k < 0 ? 0 : k;                    // a dead sample: any cell, weight 0
+                const int gg = g.G * g.G;
+                f = k / gg;
+                const int ca = (k / g.G) % g.G, cb = k % g.G;
+                a = ((float)ca + u1) * g.step - 1.0f;
+                b = ((float)cb + u2) * g.step - 1.0f;
+            } else {
+                f = (int)(u0 * 6.0f);
+                f = f < 0 ? 0 : (f > 5 ? 5 : f);
+                a = u1 * 2.0f - 1.0f;
+                b = u2 * 2.0f - 1.0f;
+            }
             const int axis = f >> 1;
             const float sgn = (f & 1) ? 1.0f : -1.0f;
-            const float a = u1 * 2.0f - 1.0f, b = u2 * 2.0f - 1.0f;
             // the face point: sgn on `axis`, then a and b on the next two axes (cyclic)
             const float y0 = axis == 0 ? sgn : (axis == 1 ? b : a);
             const float y1 = axis == 1 ? sgn : (axis == 2 ? b : a);
@@ -82,10 +152,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
             const float nlen = sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
             const float ndot = n0 * d0 + n1 * d1 + n2 * d2;
             float wt = 0.0f;
-            if (h > 0.0f && ndot > 0.0f && dist2 > 0.0f && nlen > 0.0f) {
+            if (h > 0.0f && ndot > 0.0f && dist2 > 0.0f && nlen > 0.0f && inv_density > 0.0f) {
                 const float dist = sqrtf(dist2);
                 const float cos_x = ndot / (nlen * dist), cos_y = h / dist;
-                wt = cos_x * cos_y / dist2 * kInvAreaDensity;
+                wt = cos_x * cos_y / dist2 * inv_density;
             }
             w[j] = wt;
             if (wt > 0.0f) {
@@ -118,6 +188,61 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
 #pragma unroll
     for (int k = 0; k < kSamplesPerThread; ++k)
         if (cell[k] >= 0) live[s_base + s_cell[cell[k]] + rank[k]] = j0 + (int64_t)k * kShadeBlock;
+}
+
+// Probe rays of the guide: probe j of cell c = j / R starts at a uniform
+// point of the cell (u0, u1) and aims at a uniform point of the box (u2..u4).
+__global__ void k_guide_rays(int G, int R, int64_t n, const float *u, float step, float *o, float *d) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int c = (int)(j / R);
+    const int gg = G * G;
+    const int f = c / gg, ca = (c / G) % G, cb = c % G;
+    const int axis = f >> 1;
+    const float sgn = (f & 1) ? 1.0f : -1.0f;
+    const float *uj = u + 5 * j;
+    const float a = ((float)ca + uj[0]) * step - 1.0f;
+    const float b = ((float)cb + uj[1]) * step - 1.0f;
+    const float y0 = axis == 0 ? sgn : (axis == 1 ? b : a);
+    const float y1 = axis == 1 ? sgn : (axis == 2 ? b : a);
+    const float y2 = axis == 2 ? sgn : (axis == 0 ? b : a);
+    const float t0 = uj[2] * 2.0f - 1.0f, t1 = uj[3] * 2.0f - 1.0f, t2 = uj[4] * 2.0f - 1.0f;
+    o[3 * j] = y0;
+    o[3 * j + 1] = y1;
+    o[3 * j + 2] = y2;
+    d[3 * j] = t0 - y0;
+    d[3 * j + 1] = t1 - y1;
+    d[3 * j + 2] = t2 - y2;
+}
+
+// Mean luminance (channel mean) of each cell's R probes, summed in FP64 in
+// probe order.
+__global__ void k_guide_reduce(const float *rgb, int R, int n_cells, float *weights) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) {
+        const float *q = rgb + 3 * ((int64_t)c * R + r);
+        s += ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
+    }
+    weights[c] = (float)(s / R);
+}
+
+// The cell probabilities and their running sums, in cell order, by one
+// thread (FP64): W = sum w, p_k = (1 - beta) (w_k / W) + beta / n (1 / n
+// each when W = 0), cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.
+__global__ void k_guide_cdf(const float *weights, int n, double beta, double *prob, double *cdf) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double W = 0.0;
+    for (int k = 0; k < n; ++k) W += (double)weights[k];
+    double run = 0.0;
+    cdf[0] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double p = W > 0.0 ? (1.0 - beta) * ((double)weights[k] / W) + beta / n : 1.0 / n;
+        prob[k] = p;
+        run += p;
+        cdf[k + 1] = run;
+    }
 }
 
 // Blend and per-point sums.  Block b takes points [b P, b P + P) with
@@ -195,15 +320,22 @@ lq_status shade_fail(lq_status st, const std::string &msg) {
 
 using namespace lq;
 
-extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const float *normals,
-                                         int64_t n_points, const float *u, int32_t n_samples,
-                                         const float *background_rgb, int model, float *irradiance,
-                                         float *sample_terms, void *hip_stream) {
+namespace lq {
+namespace {
+
+lq_status proxy_common(const lq_octree *tree, const float *points, const float *normals, int64_t n_points,
+                       const float *u, int32_t n_samples, const float *weights, int32_t grid, float defensive,
+                       const float *background_rgb, int model, float *irradiance, float *sample_terms,
+                       void *hip_stream) {
     if (!tree) return shade_fail(LQ_ERR_INVALID_ARG, "tree is NULL");
     if (n_points < 0) return shade_fail(LQ_ERR_INVALID_ARG, "n_points must be >= 0");
     if (n_samples < 1 || n_samples > 65536) return shade_fail(LQ_ERR_INVALID_ARG, "n_samples must be in 1..65536");
     if (model != LQ_LINEAR && model != LQ_EXP) return shade_fail(LQ_ERR_INVALID_ARG, "model must be LQ_LINEAR or LQ_EXP");
     if (n_points > ((int64_t)1 << 36) / n_samples) return shade_fail(LQ_ERR_INVALID_ARG, "n_points * n_samples too large");
+    const bool guided = weights != nullptr;
+    if (guided && (grid < 1 || grid > 256)) return shade_fail(LQ_ERR_INVALID_ARG, "grid must be in 1..256");
+    if (guided && !(defensive >= 0.0f && defensive <= 1.0f))
+        return shade_fail(LQ_ERR_INVALID_ARG, "defensive must be in [0, 1]");
     if (n_points == 0) return LQ_OK;
     const float b0 = background_rgb ? background_rgb[0] : 0.0f;
     const float b1 = background_rgb ? background_rgb[1] : 0.0f;
@@ -212,6 +344,7 @@ extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *poi
     hipError_t e = hipSetDevice(dev);
     if (e != hipSuccess) return shade_fail(LQ_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
     const int64_t m = n_points * n_samples;
+    const int n_cells = guided ? 6 * grid * grid : 0;
     lq_status st;
     if ((st = check_device_array(points, (size_t)n_points * 12, dev, "points")) != LQ_OK) return st;
     if ((st = check_device_array(normals, (size_t)n_points * 12, dev, "normals")) != LQ_OK) return st;
@@ -219,19 +352,34 @@ extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *poi
     if ((st = check_device_array(irradiance, (size_t)n_points * 12, dev, "irradiance")) != LQ_OK) return st;
     if (sample_terms && (st = check_device_array(sample_terms, (size_t)m * 12, dev, "sample_terms")) != LQ_OK)
         return st;
+    if (guided && (st = check_device_array(weights, (size_t)n_cells * 4, dev, "weights")) != LQ_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     // stream-ordered scratch: the live-ray counter (256 B), then per sample a
-    // list slot (8 B), a ray (24 B), its weight (4 B), its radiance and opacity (16 B)
+    // list slot (8 B), a ray (24 B), its weight (4 B), its radiance and
+    // opacity (16 B); guided, the cell probabilities and running sums
+    const size_t guide_bytes = guided ? (size_t)(2 * n_cells + 1) * 8 : 0;
     unsigned char *buf = nullptr;
-    if ((e = hipMallocAsync((void **)&buf, 256 + (size_t)m * 52, s)) != hipSuccess)
+    if ((e = hipMallocAsync((void **)&buf, 256 + (size_t)m * 52 + guide_bytes, s)) != hipSuccess)
         return shade_fail(LQ_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     unsigned long long *n_live = reinterpret_cast<unsigned long long *>(buf);
     int64_t *live = reinterpret_cast<int64_t *>(buf + 256);
     float *o = reinterpret_cast<float *>(buf + 256 + (size_t)m * 8);
     float *d = o + 3 * m, *w = o + 6 * m, *rgb = o + 7 * m, *alpha = o + 10 * m;
+    Guide g{};
+    if (guided) {
+        double *gd = reinterpret_cast<double *>(buf + 256 + (size_t)m * 52);
+        g.prob = gd;
+        g.cdf = gd + n_cells;
+        g.G = grid;
+        g.n_cells = n_cells;
+        g.step = (float)(2.0 / grid);
+        g.area = (2.0 / grid) * (2.0 / grid);
+        hipLaunchKernelGGL(k_guide_cdf, dim3(1), dim3(64), 0, s, weights, n_cells, (double)defensive,
+                           const_cast<double *>(g.prob), const_cast<double *>(g.cdf));
+    }
     hipLaunchKernelGGL(k_proxy_zero, dim3(1), dim3(1), 0, s, n_live);
     hipLaunchKernelGGL(k_proxy_rays, dim3((unsigned)((m + kSamplesPerBlock - 1) / kSamplesPerBlock)),
-                       dim3(kShadeBlock), 0, s, points, normals, m, (int)n_samples, u, o, d, w, live, n_live);
+                       dim3(kShadeBlock), 0, s, points, normals, m, (int)n_samples, u, o, d, w, live, n_live, g);
     e = hipGetLastError();
     st = LQ_OK;
     if (e != hipSuccess) {
@@ -244,6 +392,65 @@ extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *poi
                                rgb, alpha, w, n_points, (int)n_samples, P, b0, b1, b2, irradiance, sample_terms);
             if ((e = hipGetLastError()) != hipSuccess)
                 st = shade_fail(LQ_ERR_HIP, std::string("launching the proxy reduction: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t f = hipFreeAsync(buf, s);
+    if (st == LQ_OK && f != hipSuccess) st = shade_fail(LQ_ERR_HIP, std::string("hipFreeAsync: ") + hipGetErrorString(f));
+    return st;
+}
+
+}  // namespace
+}  // namespace lq
+
+extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const float *normals,
+                                         int64_t n_points, const float *u, int32_t n_samples,
+                                         const float *background_rgb, int model, float *irradiance,
+                                         float *sample_terms, void *hip_stream) {
+    return proxy_common(tree, points, normals, n_points, u, n_samples, nullptr, 0, 0.0f, background_rgb, model,
+                        irradiance, sample_terms, hip_stream);
+}
+
+extern "C" lq_status lq_proxy_irradiance_guided(const lq_octree *tree, const float *points, const float *normals,
+                                                int64_t n_points, const float *u, int32_t n_samples,
+                                                const float *weights, int32_t grid, float defensive,
+                                                const float *background_rgb, int model, float *irradiance,
+                                                float *sample_terms, void *hip_stream) {
+    if (!weights) return shade_fail(LQ_ERR_INVALID_ARG, "weights is NULL");
+    return proxy_common(tree, points, normals, n_points, u, n_samples, weights, grid, defensive, background_rgb,
+                        model, irradiance, sample_terms, hip_stream);
+}
+
+extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t n_probes, const float *u_probe,
+                                    int model, float *weights, void *hip_stream) {
+    if (!tree) return shade_fail(LQ_ERR_INVALID_ARG, "tree is NULL");
+    if (grid < 1 || grid > 256) return shade_fail(LQ_ERR_INVALID_ARG, "grid must be in 1..256");
+    if (n_probes < 1 || n_probes > 65536) return shade_fail(LQ_ERR_INVALID_ARG, "n_probes must be in 1..65536");
+    if (model != LQ_LINEAR && model != LQ_EXP) return shade_fail(LQ_ERR_INVALID_ARG, "model must be LQ_LINEAR or LQ_EXP");
+    const int dev = octree_device(tree);
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return shade_fail(LQ_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    const int n_cells = 6 * grid * grid;
+    const int64_t n = (int64_t)n_cells * n_probes;
+    lq_status st;
+    if ((st = check_device_array(u_probe, (size_t)n * 20, dev, "u_probe")) != LQ_OK) return st;
+    if ((st = check_device_array(weights, (size_t)n_cells * 4, dev, "weights")) != LQ_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    float *buf = nullptr;    // probe rays (24 B) and their radiance (12 B)
+    if ((e = hipMallocAsync((void **)&buf, (size_t)n * 36, s)) != hipSuccess)
+        return shade_fail(LQ_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    float *o = buf, *d = buf + 3 * n, *rgb = buf + 6 * n;
+    hipLaunchKernelGGL(k_guide_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, grid, n_probes, n, u_probe,
+                       (float)(2.0 / grid), o, d);
+    st = LQ_OK;
+    if ((e = hipGetLastError()) != hipSuccess) {
+        st = shade_fail(LQ_ERR_HIP, std::string("launching the guide probes: ") + hipGetErrorString(e));
+    } else {
+        st = query_scratch(tree, o, d, n, nullptr, nullptr, rgb, nullptr, model, s);
+        if (st == LQ_OK) {
+            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s, rgb,
+                               n_probes, n_cells, weights);
+            if ((e = hipGetLastError()) != hipSuccess)
+                st = shade_fail(LQ_ERR_HIP, std::string("launching the guide reduction: ") + hipGetErrorString(e));
         }
     }
     hipError_t f = hipFreeAsync(buf, s);

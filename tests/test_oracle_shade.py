@@ -153,8 +153,9 @@ def _random_guide(seed, zeros=0.3):
 
 
 def test_uniform_guide_is_area_uniform():
-    """With equal cell weights the guided density is the uniform one: every
-    live sample's weight is cos cos / r^2 times 24 (the box's area)."""
+    """With equal cell weights the guided density is uniform over the faces
+    the point sees: from below, only the bottom face (area 4), so every
+    sample's weight is cos cos / r^2 times 4, and no sample is dead."""
     x = np.array([[0.4, -0.3, -2.7]], np.float32)
     n = np.array([[0.1, 0.2, 1.0]], np.float32)
     u = inputs.rays.sample_numbers(1, 4096, 21)
@@ -166,25 +167,33 @@ def test_uniform_guide_is_area_uniform():
         nn = n[0].astype(np.float64)
         cos_x = d64 @ (nn / np.linalg.norm(nn)) / np.sqrt(r2)
         cos_y = (-x[0, 2].astype(np.float64) - 1.0) / np.sqrt(r2)     # bottom face (z = -1)
-        assert np.allclose(w[live] * r2 / (cos_x * cos_y), 24.0, rtol=1e-9)
+        assert live.all()
+        assert np.allclose(w[live] * r2 / (cos_x * cos_y), 4.0, rtol=1e-9)
 
 
 def test_cell_frequencies_follow_the_guide():
-    """Cells are picked with probability p_k = (1 - beta) w_k / W + beta / n:
-    counts within 5 standard deviations; with beta = 0 a cell of weight 0
-    is never picked."""
+    """Cells of the faces the point sees are picked with probability
+    p_k / P_vis, p_k = (1 - beta) w_k / W + beta / n: counts within 5
+    standard deviations, none on the other faces; with beta = 0 a cell of
+    weight 0 is never picked."""
     w = _random_guide(3)
-    S = 400_000
+    S = 200_000
     u = inputs.rays.sample_numbers(1, S, 22)
-    x = np.array([[0.0, 0.0, -3.0]], np.float32)
-    n = np.array([[0.0, 0.0, 1.0]], np.float32)
+    # a point that sees three faces: x > 1, y < -1, z < -1 (faces 1, 2, 4)
+    x = np.array([[2.5, -3.0, -1.7]], np.float32)
+    n = np.array([[-1.0, 1.0, 1.0]], np.float32)
+    vis = shade.visible_faces(x)[0]
+    assert list(np.nonzero(vis)[0]) == [1, 2, 4]
     for beta in (0.0, 0.25):
         _, _, _, cell = shade.guided_proxy_rays(x, n, u, w, G, beta)
         p, cdf = shade.guide_cdf(w, beta)
         assert cdf[-1] == pytest.approx(1.0, abs=1e-12)
+        on = np.repeat(vis, G * G)
+        q = np.where(on, p, 0.0) / p[on].sum()
         cnt = np.bincount(cell, minlength=p.size)
-        sd = np.sqrt(S * p * (1 - p))
-        assert np.all(np.abs(cnt - S * p) <= 5 * sd + 1e-9)
+        sd = np.sqrt(S * q * (1 - q))
+        assert np.all(np.abs(cnt - S * q) <= 5 * sd + 1e-9)
+        assert np.all(cnt[~on] == 0)
         if beta == 0.0:
             assert np.all(cnt[w == 0] == 0)
 
