@@ -455,24 +455,34 @@ def guided_variant(inputs, oct32, steps):
     P, N, U = (torch.from_numpy(a).cuda() for a in (pts, nrm, u))
     E = torch.empty((len(pts), 3), device="cuda")
     bg = (0.05, 0.05, 0.08)
-    ms, _ = time_launches(lambda: oct32.proxy_irradiance_guided(P, N, U, w, G, defensive=0.25, background=bg,
+    ms, _ = time_launches(lambda: oct32.proxy_irradiance_guided(P, N, U, w, G, defensive=0.5, background=bg,
                                                                 irradiance=E), steps, 2)
-    sub = np.arange(0, len(pts), 256)
-    Ps, Ns = P[sub].contiguous(), N[sub].contiguous()
-    ref, _ = oct32.proxy_irradiance(Ps, Ns, torch.from_numpy(inputs.rays.sample_numbers(len(sub), 4096, 91)).cuda(),
+    # estimator quality on every 64th point: the variance of a sample's
+    # luminance term (over the point's 16 samples, averaged over the points)
+    # and the mean squared error of the 16-sample estimates against a
+    # 4096-sample uniform reference on every 256th point
+    sub = np.arange(0, len(pts), 64)
+    Ps, Ns, U16 = P[sub].contiguous(), N[sub].contiguous(), U[sub].contiguous()
+    Eu, tu = oct32.proxy_irradiance(Ps, Ns, U16, background=bg, want_terms=True)
+    Eg, tg = oct32.proxy_irradiance_guided(Ps, Ns, U16, w, G, defensive=0.5, background=bg, want_terms=True)
+    ref_sub = np.arange(0, len(sub), 4)
+    ref, _ = oct32.proxy_irradiance(Ps[ref_sub].contiguous(), Ns[ref_sub].contiguous(),
+                                    torch.from_numpy(inputs.rays.sample_numbers(len(ref_sub), 4096, 91)).cuda(),
                                     background=bg)
-    U16 = U[sub].contiguous()
-    Eu, _ = oct32.proxy_irradiance(Ps, Ns, U16, background=bg)
-    Eg, _ = oct32.proxy_irradiance_guided(Ps, Ns, U16, w, G, defensive=0.25, background=bg)
     torch.cuda.synchronize()
-    lum = lambda a: a.double().mean(1)
-    mse_u = float(((lum(Eu) - lum(ref)) ** 2).mean())
-    mse_g = float(((lum(Eg) - lum(ref)) ** 2).mean())
+    lum = lambda a: a.double().mean(-1)
+    var_u = float(lum(tu).var(1).mean())
+    var_g = float(lum(tg).var(1).mean())
+    mse_u = float(((lum(Eu[ref_sub]) - lum(ref)) ** 2).mean())
+    mse_g = float(((lum(Eg[ref_sub]) - lum(ref)) ** 2).mean())
     rec = {"grid": G, "probes_per_cell": R, "guide_ms": ms_guide, "points": len(pts), "samples_per_point": 16,
-           "ms": ms, "points_per_s": len(pts) / (ms * 1e-3), "defensive": 0.25,
+           "ms": ms, "points_per_s": len(pts) / (ms * 1e-3), "defensive": 0.5,
+           "term_variance_ratio_uniform_over_guided": var_u / var_g if var_g > 0 else None,
            "mse_ratio_uniform_over_guided": mse_u / mse_g if mse_g > 0 else None,
-           "mse_sample": f"{len(sub)} points, 16 samples, against a 4096-sample uniform reference"}
-    log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms, MSE ratio {rec['mse_ratio_uniform_over_guided']}")
+           "quality_sample": f"term variance over {len(sub)} points x 16 samples; MSE over {len(ref_sub)} points "
+                             f"against a 4096-sample uniform reference"}
+    log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms, variance ratio "
+        f"{rec['term_variance_ratio_uniform_over_guided']}, MSE ratio {rec['mse_ratio_uniform_over_guided']}")
     return rec
 
 

@@ -303,20 +303,23 @@ lq_status lq_proxy_irradiance_guided(const lq_octree *tree, const float *points,
  * counter (Morton code of the voxel, sample index, 0, 0), key (low and high
  * 32 bits of seed); the first three output words u give the offsets
  * (u >> 8) 2^-24 along x, y, z in units of the voxel edge.  Decisions (the
- * centre test, shell membership) are taken in FP64, the samples' blob terms
- * and the sums in float32.
+ * centre test, shell membership) are taken as in FP64; per sample, the blob
+ * exponents are FP64 and the exponentials and sums float32; the sums over
+ * samples are FP64 across blocks of 16 samples.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t n_blobs;          /* 1..32                                           */
     int32_t n_shells;         /* 0..8                                            */
     int32_t sh_degree;        /* 0..4                                            */
     int32_t reserved;
-    const double *blobs;      /* host [n_blobs][8]: centre x, y, z, radius r > 0,
-                                 log-density amplitude a, radiance e_r, e_g, e_b
-                                 (each in (0, l_max))                            */
+    const double *blobs;      /* host [n_blobs][8]: centre x, y, z (in [-2, 2]),
+                                 radius r (in [1e-3, 4]), log-density amplitude a
+                                 (|a| <= 12), radiance e_r, e_g, e_b (each in
+                                 (0, l_max))                                     */
     const double *blob_sh;    /* host [n_blobs][3][(sh_degree+1)^2 - 1]: h_kcj for
                                  j >= 1 (NULL for degree 0)                      */
-    const double *shells;     /* host [n_shells][4]: centre x, y, z, radius      */
+    const double *shells;     /* host [n_shells][4]: centre x, y, z, radius (each
+                                 in [-2, 2])                                     */
     double shell_half_width, log_density_base, sigma_max, l_max;
 } lq_field_desc;
 

@@ -22,14 +22,16 @@
 //   k_centre_compact  the Morton codes of the kept voxels, ascending;
 //   k_distill<NB>     one lane per kept voxel: n_samples positions from
 //                     Philox4x32-10 (counter = code, sample index, 0, 0;
-//                     key = seed), the blob terms in float32 with every
-//                     blob's weight kept in registers (NB >= blobs, fully
-//                     unrolled), shell membership in FP64 (a decision), and
-//                     the means.  The higher SH coefficients are linear in
-//                     the weights, so their mean is sum_k mean(w_k) h_k:
-//                     the lane averages the NB weights and combines them
-//                     with h once at the end (the same value as averaging
-//                     the per-sample coefficients, in other rounding);
+//                     key = seed), the blob exponents in FP64, their
+//                     exponentials and the per-sample sums in float32 with
+//                     every blob's weight kept in registers (NB >= blobs,
+//                     fully unrolled), shell membership as in FP64 (a
+//                     decision), and the means.  The higher SH coefficients
+//                     are linear in the weights, so their mean is
+//                     sum_k mean(w_k) h_k: the lane averages the NB weights
+//                     and combines them with h once at the end (the same
+//                     value as averaging the per-sample coefficients, in
+//                     other rounding);
 //   tree build        per level, bottom-up: run heads of the parent codes,
 //                     a scan for the parents' positions, their compaction;
 //                     then the child table, breadth-first, Morton order
@@ -59,8 +61,11 @@ constexpr int kScanBlock = 1024;
 struct FieldArgs {
     int nb, ns, K, pad;
     float cx[kMaxBlobs], cy[kMaxBlobs], cz[kMaxBlobs], inv2r2[kMaxBlobs], amp[kMaxBlobs];
+    float cxl[kMaxBlobs], cyl[kMaxBlobs], czl[kMaxBlobs];     // centre = float32 + lower part
     float er[kMaxBlobs], eg[kMaxBlobs], eb[kMaxBlobs];
-    float log_base, sigma_max, inv_lmax, pad2;
+    float sx[kMaxShells], sy[kMaxShells], sz[kMaxShells], sr[kMaxShells];
+    float sxl[kMaxShells], syl[kMaxShells], szl[kMaxShells];
+    float log_base, sigma_max, l_max, half_width, threshold, pad2[3];
     double dcx[kMaxBlobs], dcy[kMaxBlobs], dcz[kMaxBlobs], dinv2r2[kMaxBlobs], damp[kMaxBlobs];
     double dsx[kMaxShells], dsy[kMaxShells], dsz[kMaxShells], dsr[kMaxShells];
     double dhalf_width, dthreshold;   // density(centre) >= prune  <=>  S >= dthreshold
@@ -76,18 +81,30 @@ __device__ inline uint32_t compact3(uint32_t v) {   // every third bit, from bit
     return v;
 }
 
+// Shell membership, decided as in FP64: a float32 distance first (centres
+// as a float32 pair, so each difference is within 2 ulp of its own value;
+// positions and centres within [-2, 2]: the distance is off by under
+// 2e-6), and FP64 only when its margin to a shell boundary is below 1e-5.
+__device__ inline bool in_shell_f64(const FieldArgs &f, int j, double x, double y, double z) {
+    const double dx = x - f.dsx[j], dy = y - f.dsy[j], dz = z - f.dsz[j];
+    const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+    return fabs(dist - f.dsr[j]) < f.dhalf_width;
+}
+
 __device__ inline bool in_shell(const FieldArgs &f, double x, double y, double z) {
+    const float xf = (float)x, yf = (float)y, zf = (float)z;
     bool in = false;
     for (int j = 0; j < f.ns; ++j) {
-        const double dx = x - f.dsx[j], dy = y - f.dsy[j], dz = z - f.dsz[j];
-        const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-        in = in || fabs(dist - f.dsr[j]) < f.dhalf_width;
+        const float dx = (xf - f.sx[j]) - f.sxl[j], dy = (yf - f.sy[j]) - f.syl[j], dz = (zf - f.sz[j]) - f.szl[j];
+        const float dist = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+        const float m = fabsf(dist - f.sr[j]) - f.half_width;
+        if (fabsf(m) > 1e-5f) in = in || m < 0.0f;
+        else in = in || in_shell_f64(f, j, x, y, z);
     }
     return in;
 }
 
-__device__ inline bool centre_kept(const FieldArgs &f, double x, double y, double z) {
-    if (in_shell(f, x, y, z)) return true;
+__device__ inline bool centre_kept_f64(const FieldArgs &f, double x, double y, double z) {
     double S = 0.0;
     for (int k = 0; k < f.nb; ++k) {
         const double dx = x - f.dcx[k], dy = y - f.dcy[k], dz = z - f.dcz[k];
@@ -95,6 +112,28 @@ __device__ inline bool centre_kept(const FieldArgs &f, double x, double y, doubl
         S += f.damp[k] * exp(-d2 * f.dinv2r2[k]);
     }
     return S >= f.dthreshold;
+}
+
+// The centre test, decided as in FP64: S in float32 first, FP64 only when
+// S_32 lies within 4e-3 of the threshold.  Bound: voxel centres are exact
+// in float32 and blob centres are float32 pairs, so every difference, the
+// squared distance and lw = -d^2 / (2 r^2) carry under 6 ulp of relative
+// error, and exp2 one more: each term a g is off by under
+// |a| (6 |lw| + 2) 2^-24 <= |a| (6 / e + 2) 2^-24 (g |lw| <= 1 / e), under
+// 1.1e-4 for 32 blobs of |a| <= 12; the running sum adds under
+// 32 2^-24 sum |a| g <= 7.4e-4.
+__device__ inline bool centre_kept(const FieldArgs &f, double x, double y, double z) {
+    if (in_shell(f, x, y, z)) return true;
+    const float xf = (float)x, yf = (float)y, zf = (float)z;
+    float S = 0.0f;
+    for (int k = 0; k < f.nb; ++k) {
+        const float dx = (xf - f.cx[k]) - f.cxl[k], dy = (yf - f.cy[k]) - f.cyl[k], dz = (zf - f.cz[k]) - f.czl[k];
+        const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        S = fmaf(f.amp[k], __builtin_amdgcn_exp2f(-d2 * f.inv2r2[k] * 1.4426950408889634f), S);
+    }
+    const float m = S - f.threshold;
+    if (fabsf(m) > 4e-3f) return m >= 0.0f;
+    return centre_kept_f64(f, x, y, z);
 }
 
 // Occupancy of the voxels [chunk * kWordsPerChunk * 64, ...) in Morton
@@ -180,16 +219,16 @@ __global__ __launch_bounds__(kWordsPerChunk) void k_centre_compact(const unsigne
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): 10 rounds of two
 // 32x32 -> 64-bit multiplications with the key bumped by the Weyl constants.
+// Each product is one 64-bit multiply (a single v_mad_u64_u32).
 __device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
                                      uint32_t out[4]) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -199,12 +238,32 @@ __device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint
     out[3] = c3;
 }
 
-__device__ inline float exp_f(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
-
 // One lane per kept voxel i < n: the means over n_samples positions.
-// sh_out[i][c][k]; hi [nb][3][K - 1] (device).
+// sh_out[i][c][k]; hi [nb][3][K - 1] (device, FP64).  rec: NB records of
+// four doubles (centre, -log2(e) / (2 r^2)), then NB float4 records
+// (amplitude, radiance); those past nb are padded so that their terms
+// vanish (exp2 of a huge negative argument is exactly 0).
+//
+// Precision: the exponent t_k = -log2(e) |x - c_k|^2 / (2 r_k^2) is taken in
+// FP64 (full rate on this chip, like float32 without packing): a softmax
+// weight depends on the absolute error of t_k - max_j t_j, and at points far
+// from every blob (|t| in the hundreds, on the shells) float32 would leave
+// relative errors of 1e-4 in the weights.  exp2, log2 and the per-sample
+// sums are float32; the sums over samples run in blocks of kBlock samples
+// (float32 inside a block, FP64 across blocks), and the higher coefficients
+// sum_k mean(w_k) h_k are formed in FP64 once per voxel.
+//
+// The records are read inside the sample loop through an offset the
+// compiler cannot prove constant (zero is 0), so they arrive by scalar
+// loads from cache each sample instead of being held across the loop, where
+// they would overflow the scalar register file; groups of four blobs are
+// separated by scheduling barriers so that the loads are not all issued at
+// once.  The Philox round keys are likewise recomputed by scalar adds.
+constexpr int kBlock = 16;
+
 template <int NB>
-__global__ __launch_bounds__(kThreads) void k_distill(const FieldArgs f, const float *hi, int depth, int n_samples,
+__global__ __launch_bounds__(kThreads) void k_distill(const FieldArgs f, const double *__restrict__ rec,
+                                                      uint32_t zero, const double *hi, int depth, int n_samples,
                                                       uint32_t key0, uint32_t key1, const uint32_t *codes,
                                                       uint64_t n, float *sigma_out, float *sh_out) {
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -214,71 +273,96 @@ __global__ __launch_bounds__(kThreads) void k_distill(const FieldArgs f, const f
     const double lox = -1.0 + (double)compact3(code) * hd;
     const double loy = -1.0 + (double)compact3(code >> 1) * hd;
     const double loz = -1.0 + (double)compact3(code >> 2) * hd;
-    float wbar[NB];
+    constexpr float kLog2e = 1.4426950408889634f;
+    constexpr float kLn2InvY00 = 0.69314718055994531f * 3.5449077018110318f;
+    const float log_base2 = f.log_base * kLog2e;
+    double wsum[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) wbar[k] = 0.0f;
-    float sig_acc = 0.0f, dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f;
-    for (int j = 0; j < n_samples; ++j) {
-        uint32_t u[4];
-        philox4x32_10(code, (uint32_t)j, 0u, 0u, key0, key1, u);
-        // the position exactly in FP64 (cell + offset: 34 bits), then float32
-        const double xd = lox + (double)(u[0] >> 8) * 0x1p-24 * hd;
-        const double yd = loy + (double)(u[1] >> 8) * 0x1p-24 * hd;
-        const double zd = loz + (double)(u[2] >> 8) * 0x1p-24 * hd;
-        const float x = (float)xd, y = (float)yd, z = (float)zd;
-        float lw[NB];
-        float m = -INFINITY;
+    for (int k = 0; k < NB; ++k) wsum[k] = 0.0;
+    double sig_sum = 0.0, dc0_sum = 0.0, dc1_sum = 0.0, dc2_sum = 0.0;
+    for (int j0 = 0; j0 < n_samples; j0 += kBlock) {
+        const int j1 = min(n_samples, j0 + kBlock);
+        float wb[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            if (k < f.nb) {
-                const float dx = x - f.cx[k], dy = y - f.cy[k], dz = z - f.cz[k];
-                const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                lw[k] = -d2 * f.inv2r2[k];
-                m = fmaxf(m, lw[k]);
+        for (int k = 0; k < NB; ++k) wb[k] = 0.0f;
+        float sig_acc = 0.0f, dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f;
+        for (int j = j0; j < j1; ++j) {
+            const uint32_t jz = (uint32_t)j & zero;   // 0, opaque to the compiler
+            const double4 *qa = reinterpret_cast<const double4 *>(rec) + jz;
+            const float4 *qb = reinterpret_cast<const float4 *>(qa + NB);
+            uint32_t u[4];
+            philox4x32_10(code, (uint32_t)j, 0u, 0u, key0 + jz, key1 + jz, u);
+            // the position exactly in FP64 (cell + offset: 34 bits)
+            const double x = lox + (double)(u[0] >> 8) * 0x1p-24 * hd;
+            const double y = loy + (double)(u[1] >> 8) * 0x1p-24 * hd;
+            const double z = loz + (double)(u[2] >> 8) * 0x1p-24 * hd;
+            // t_k = log2 of blob k's Gaussian, m = max_k t_k (FP64)
+            double t[NB];
+            double m = -INFINITY;
+#pragma unroll
+            for (int g = 0; g < NB; g += 4) {
+#pragma unroll
+                for (int k = g; k < g + 4; ++k) {
+                    const double4 a = qa[k];
+                    const double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+                    t[k] = fma(dz, dz, fma(dy, dy, dx * dx)) * a.w;
+                    m = fmax(m, t[k]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        float s = 0.0f, sa = 0.0f, e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+            float e[NB];
+            float s = 0.0f, sa = 0.0f, e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            if (k < f.nb) {
-                const float e = exp_f(lw[k] - m);
-                lw[k] = e;
-                s += e;
-                sa = fmaf(f.amp[k], e, sa);
-                e0 = fmaf(f.er[k], e, e0);
-                e1 = fmaf(f.eg[k], e, e1);
-                e2 = fmaf(f.eb[k], e, e2);
+            for (int g = 0; g < NB; g += 4) {
+#pragma unroll
+                for (int k = g; k < g + 4; ++k) {
+                    const float4 b = qb[k];
+                    e[k] = __builtin_amdgcn_exp2f((float)(t[k] - m));
+                    s += e[k];
+                    sa = fmaf(b.x, e[k], sa);
+                    e0 = fmaf(b.y, e[k], e0);
+                    e1 = fmaf(b.z, e[k], e1);
+                    e2 = fmaf(b.w, e[k], e2);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        const float inv = 1.0f / s;
+            const float inv = __builtin_amdgcn_rcpf(s);
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (k < f.nb) wbar[k] = fmaf(lw[k], inv, wbar[k]);
-        // density: sum_k a_k g_k = exp(m) sum_k a_k e_k
-        float sg = fminf(exp_f(f.log_base + sa * exp_f(m)), f.sigma_max);
-        if (f.ns > 0 && in_shell(f, xd, yd, zd)) sg = f.sigma_max;
-        sig_acc += sg;
-        // DC: logit(E / L_max) / Y_00, Y_00 = 1 / (2 sqrt(pi))
-        const float fr0 = e0 * inv * f.inv_lmax, fr1 = e1 * inv * f.inv_lmax, fr2 = e2 * inv * f.inv_lmax;
-        constexpr float kInvY00 = 3.5449077018110318f;   // 2 sqrt(pi)
-        dc0 += (logf(fr0) - log1pf(-fr0)) * kInvY00;
-        dc1 += (logf(fr1) - log1pf(-fr1)) * kInvY00;
-        dc2 += (logf(fr2) - log1pf(-fr2)) * kInvY00;
+            for (int k = 0; k < NB; ++k) wb[k] = fmaf(e[k], inv, wb[k]);
+            // density: exp(log_base + sum_k a_k g_k), sum_k a_k g_k = 2^m sa
+            float sg = fminf(
+                __builtin_amdgcn_exp2f(fmaf(__builtin_amdgcn_exp2f((float)m) * kLog2e, sa, log_base2)),
+                f.sigma_max);
+            if (f.ns > 0 && in_shell(f, x, y, z)) sg = f.sigma_max;
+            sig_acc += sg;
+            // DC: logit(E / L_max) / Y_00 = ln(E / (L_max - E)) 2 sqrt(pi),
+            // E = e_c / s: log2(e_c / (L_max s - e_c)) ln 2 2 sqrt(pi)
+            const float ls = f.l_max * s;
+            dc0 = fmaf(__builtin_amdgcn_logf(e0 * __builtin_amdgcn_rcpf(ls - e0)), kLn2InvY00, dc0);
+            dc1 = fmaf(__builtin_amdgcn_logf(e1 * __builtin_amdgcn_rcpf(ls - e1)), kLn2InvY00, dc1);
+            dc2 = fmaf(__builtin_amdgcn_logf(e2 * __builtin_amdgcn_rcpf(ls - e2)), kLn2InvY00, dc2);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) wsum[k] += (double)wb[k];
+        sig_sum += (double)sig_acc;
+        dc0_sum += (double)dc0;
+        dc1_sum += (double)dc1;
+        dc2_sum += (double)dc2;
     }
-    const float invn = 1.0f / (float)n_samples;
-    sigma_out[i] = sig_acc * invn;
+    const double invn = 1.0 / (double)n_samples;
+    sigma_out[i] = (float)(sig_sum * invn);
     const int K = f.K;
     float *row = sh_out + i * (uint64_t)(3 * K);
-    row[0] = dc0 * invn;
-    row[K] = dc1 * invn;
-    row[2 * K] = dc2 * invn;
+    row[0] = (float)(dc0_sum * invn);
+    row[K] = (float)(dc1_sum * invn);
+    row[2 * K] = (float)(dc2_sum * invn);
     for (int c = 0; c < 3; ++c)
         for (int j = 1; j < K; ++j) {
-            float acc = 0.0f;
+            double acc = 0.0;
 #pragma unroll
             for (int k = 0; k < NB; ++k)
-                if (k < f.nb) acc = fmaf(wbar[k], hi[(k * 3 + c) * (K - 1) + (j - 1)], acc);
-            row[c * K + j] = acc * invn;
+                if (k < f.nb) acc = fma(wsum[k], hi[(k * 3 + c) * (K - 1) + (j - 1)], acc);
+            row[c * K + j] = (float)(acc * invn);
         }
 }
 
@@ -408,8 +492,10 @@ lq_status field_args(const lq_field_desc *fd, int depth, float prune_sigma, Fiel
     f.K = K;
     for (int k = 0; k < f.nb; ++k) {
         const double *b = fd->blobs + 8 * k;
-        if (!(b[3] > 0.0) || !std::isfinite(b[0] + b[1] + b[2] + b[4]))
-            return dfail(LQ_ERR_INVALID_ARG, "a blob has a bad centre, radius or amplitude");
+        if (!(b[3] >= 1e-3 && b[3] <= 4.0) || !std::isfinite(b[0] + b[1] + b[2] + b[4]) || std::fabs(b[0]) > 2.0 ||
+            std::fabs(b[1]) > 2.0 || std::fabs(b[2]) > 2.0 || std::fabs(b[4]) > 12.0)
+            return dfail(LQ_ERR_INVALID_ARG,
+                         "a blob needs a centre in [-2, 2]^3, a radius in [1e-3, 4] and |amplitude| <= 12");
         for (int c = 0; c < 3; ++c)
             if (!(b[5 + c] > 0.0) || !(b[5 + c] < fd->l_max))
                 return dfail(LQ_ERR_INVALID_ARG, "blob radiance must be in (0, l_max)");
@@ -422,6 +508,9 @@ lq_status field_args(const lq_field_desc *fd, int depth, float prune_sigma, Fiel
         f.cx[k] = (float)b[0];
         f.cy[k] = (float)b[1];
         f.cz[k] = (float)b[2];
+        f.cxl[k] = (float)(b[0] - (double)f.cx[k]);
+        f.cyl[k] = (float)(b[1] - (double)f.cy[k]);
+        f.czl[k] = (float)(b[2] - (double)f.cz[k]);
         f.inv2r2[k] = (float)inv;
         f.amp[k] = (float)b[4];
         f.er[k] = (float)b[5];
@@ -429,17 +518,50 @@ lq_status field_args(const lq_field_desc *fd, int depth, float prune_sigma, Fiel
         f.eb[k] = (float)b[7];
     }
     for (int j = 0; j < f.ns; ++j) {
+        for (int a = 0; a < 4; ++a)
+            if (!std::isfinite(fd->shells[4 * j + a]) || std::fabs(fd->shells[4 * j + a]) > 2.0)
+                return dfail(LQ_ERR_INVALID_ARG, "shell centres and radii must lie in [-2, 2]");
         f.dsx[j] = fd->shells[4 * j];
         f.dsy[j] = fd->shells[4 * j + 1];
         f.dsz[j] = fd->shells[4 * j + 2];
         f.dsr[j] = fd->shells[4 * j + 3];
+        f.sx[j] = (float)f.dsx[j];
+        f.sy[j] = (float)f.dsy[j];
+        f.sz[j] = (float)f.dsz[j];
+        f.sr[j] = (float)f.dsr[j];
+        f.sxl[j] = (float)(f.dsx[j] - (double)f.sx[j]);
+        f.syl[j] = (float)(f.dsy[j] - (double)f.sy[j]);
+        f.szl[j] = (float)(f.dsz[j] - (double)f.sz[j]);
     }
     f.dhalf_width = fd->shell_half_width;
+    f.half_width = (float)fd->shell_half_width;
     f.dthreshold = log((double)prune_sigma) - fd->log_density_base;
+    f.threshold = (float)f.dthreshold;
     f.log_base = (float)fd->log_density_base;
     f.sigma_max = (float)fd->sigma_max;
-    f.inv_lmax = (float)(1.0 / fd->l_max);
+    f.l_max = (float)fd->l_max;
     return LQ_OK;
+}
+
+
+// The sample loop's blob records (k_distill), as bytes: NB x {cx, cy, cz,
+// -log2(e) / (2 r^2)} in FP64, then NB x {amplitude, radiance} in float32;
+// the records past nb sit far outside the field with a huge falloff, so
+// their exp2 terms are exactly 0, and their amplitude and radiance are 0.
+std::vector<unsigned char> blob_records(const FieldArgs &f, int NB) {
+    std::vector<unsigned char> r((size_t)NB * 48, 0);
+    for (int k = 0; k < NB; ++k) {
+        double q[4] = {1000.0, 1000.0, 1000.0, -1e300};
+        float w[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (k < f.nb) {
+            q[0] = f.dcx[k], q[1] = f.dcy[k], q[2] = f.dcz[k];
+            q[3] = -f.dinv2r2[k] * 1.4426950408889634;
+            w[0] = f.amp[k], w[1] = f.er[k], w[2] = f.eg[k], w[3] = f.eb[k];
+        }
+        memcpy(r.data() + 32 * k, q, 32);
+        memcpy(r.data() + 32 * NB + 16 * k, w, 16);
+    }
+    return r;
 }
 
 }  // namespace
@@ -474,15 +596,14 @@ lq_status lq_distill_leaves(const lq_field_desc *field, int32_t max_depth, float
     DevBufs b;
     unsigned long long *bits;
     uint32_t *counts, *offs, *tot;
-    float *d_hi = nullptr;
+    double *d_hi = nullptr;
     if ((e = b.alloc(&bits, n_words)) != hipSuccess || (e = b.alloc(&counts, n_chunks)) != hipSuccess ||
         (e = b.alloc(&offs, n_chunks)) != hipSuccess || (e = b.alloc(&tot, 1)) != hipSuccess)
         return dfail(LQ_ERR_OOM, "device scratch of the distillation");
     if (K > 1) {
-        std::vector<float> hi((size_t)f.nb * 3 * (K - 1));
-        for (size_t t = 0; t < hi.size(); ++t) hi[t] = (float)field->blob_sh[t];
-        if ((e = b.alloc(&d_hi, hi.size())) != hipSuccess) return dfail(LQ_ERR_OOM, "device copy of blob_sh");
-        if ((e = hipMemcpy(d_hi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        const size_t nh = (size_t)f.nb * 3 * (K - 1);
+        if ((e = b.alloc(&d_hi, nh)) != hipSuccess) return dfail(LQ_ERR_OOM, "device copy of blob_sh");
+        if ((e = hipMemcpy(d_hi, field->blob_sh, nh * 8, hipMemcpyHostToDevice)) != hipSuccess)
             return dhip(e, "copying blob_sh");
     }
     hipLaunchKernelGGL(k_centre_bits, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, f, max_depth, n_vox, bits,
@@ -500,15 +621,21 @@ lq_status lq_distill_leaves(const lq_field_desc *field, int32_t max_depth, float
                        codes, (uint64_t)capacity);
     const unsigned nb = (unsigned)((total + kThreads - 1) / kThreads);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (f.nb <= 8)
-        hipLaunchKernelGGL(k_distill<8>, dim3(nb), dim3(kThreads), 0, s, f, d_hi, max_depth, n_samples, k0, k1,
-                           codes, (uint64_t)total, sigma, sh);
-    else if (f.nb <= 16)
-        hipLaunchKernelGGL(k_distill<16>, dim3(nb), dim3(kThreads), 0, s, f, d_hi, max_depth, n_samples, k0, k1,
-                           codes, (uint64_t)total, sigma, sh);
+    const int NB = f.nb <= 8 ? 8 : f.nb <= 16 ? 16 : 32;
+    std::vector<unsigned char> rec = blob_records(f, NB);
+    double *d_rec;
+    if ((e = b.alloc(&d_rec, rec.size() / 8)) != hipSuccess) return dfail(LQ_ERR_OOM, "device copy of the blobs");
+    if ((e = hipMemcpy(d_rec, rec.data(), rec.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return dhip(e, "copying the blobs");
+    if (NB == 8)
+        hipLaunchKernelGGL(k_distill<8>, dim3(nb), dim3(kThreads), 0, s, f, d_rec, 0u, d_hi, max_depth, n_samples,
+                           k0, k1, codes, (uint64_t)total, sigma, sh);
+    else if (NB == 16)
+        hipLaunchKernelGGL(k_distill<16>, dim3(nb), dim3(kThreads), 0, s, f, d_rec, 0u, d_hi, max_depth, n_samples,
+                           k0, k1, codes, (uint64_t)total, sigma, sh);
     else
-        hipLaunchKernelGGL(k_distill<32>, dim3(nb), dim3(kThreads), 0, s, f, d_hi, max_depth, n_samples, k0, k1,
-                           codes, (uint64_t)total, sigma, sh);
+        hipLaunchKernelGGL(k_distill<32>, dim3(nb), dim3(kThreads), 0, s, f, d_rec, 0u, d_hi, max_depth, n_samples,
+                           k0, k1, codes, (uint64_t)total, sigma, sh);
     if ((e = hipGetLastError()) != hipSuccess) return dhip(e, "launching the distillation");
     // the scratch above is freed on return: wait for its last use
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return dhip(e, "the distillation");

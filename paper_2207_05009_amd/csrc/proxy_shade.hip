@@ -358,8 +358,9 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
     // list slot (8 B), a ray (24 B), its weight (4 B), its radiance and
     // opacity (16 B); guided, the cell probabilities and running sums
     const size_t guide_bytes = guided ? (size_t)(2 * n_cells + 1) * 8 : 0;
+    const size_t guide_at = (256 + (size_t)m * 52 + 255) & ~(size_t)255;   // 8-byte (here 256) aligned
     unsigned char *buf = nullptr;
-    if ((e = hipMallocAsync((void **)&buf, 256 + (size_t)m * 52 + guide_bytes, s)) != hipSuccess)
+    if ((e = hipMallocAsync((void **)&buf, guide_at + guide_bytes, s)) != hipSuccess)
         return shade_fail(LQ_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     unsigned long long *n_live = reinterpret_cast<unsigned long long *>(buf);
     int64_t *live = reinterpret_cast<int64_t *>(buf + 256);
@@ -367,7 +368,7 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
     float *d = o + 3 * m, *w = o + 6 * m, *rgb = o + 7 * m, *alpha = o + 10 * m;
     Guide g{};
     if (guided) {
-        double *gd = reinterpret_cast<double *>(buf + 256 + (size_t)m * 52);
+        double *gd = reinterpret_cast<double *>(buf + guide_at);
         g.prob = gd;
         g.cdf = gd + n_cells;
         g.G = grid;

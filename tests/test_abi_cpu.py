@@ -154,6 +154,11 @@ def test_distillation_rejects_bad_fields(L):
     d2, keep2 = lumiq.field_desc(bad)
     assert L.lq_distill_leaves(C.byref(d2), 3, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -1
     assert b"radiance" in L.lq_last_error()
+    bad = dict(p)
+    bad["radii"] = np.asarray(p["radii"]) * 0.0 + 1e-4
+    d3, keep3 = lumiq.field_desc(bad)
+    assert L.lq_distill_leaves(C.byref(d3), 3, 0.01, 16, 0, 0, 0, None, None, None, C.byref(n), None) == -1
+    assert b"radius" in L.lq_last_error()
     h = C.c_void_p()
     assert L.lq_octree_from_leaves(11, 2, None, None, None, 0, 2048.0, 0.1, 0.9, 0, 0, C.byref(h)) == -1
     assert L.lq_octree_download(None, None, None, None) == -1

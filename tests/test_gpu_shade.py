@@ -238,3 +238,36 @@ def test_guided_sampling_reduces_variance(lq, c0_tree):
          f"(min {ratio.min():.2f}), |z| max {z.max():.2f}")
     assert np.median(ratio) >= 1.5
     assert np.median(z) < 2.0 and z.max() < 8.0
+
+
+def test_guided_full_size_configuration(lq, c1_tree):
+    """The benchmark's guided configuration on the depth-9 luminaire: the
+    guide (16 x 16 cells per face, 64 probes per cell) against the oracle's,
+    and the guided sampler on floor points (a seeded sample of the
+    1024 x 1024 grid, 16 samples each) sample by sample against the oracle,
+    with a synthetic guide of the same size."""
+    import torch
+    G, R = 16, 64
+    oct_ = lq.Octree(c1_tree, "f32")
+    u = inputs.rays.probe_numbers(shade.guide_cells(G), R, 90)
+    w = oct_.proxy_guide(G, _dev(u))
+    torch.cuda.synchronize()
+    w = w.cpu().numpy().astype(np.float64)
+    ref, q = shade.guide_weights(c1_tree, G, u)
+    slack = (np.abs(q["alt_L"].mean(1) - q["L"].mean(1)) * q["alt_valid"]).reshape(-1, R).sum(1) / R
+    err = np.abs(w - ref) - slack
+    tol = 1e-4 * np.maximum(np.abs(ref), 1e-3 * ref.max())
+    _say(f"full-size guide: max |dw| / tol {(err / tol).max():.3f}")
+    assert np.all(err <= tol)
+    pts, nrm = inputs.rays.floor_points(1024, 1024)
+    idx = np.sort(np.random.default_rng(92).choice(len(pts), 300, replace=False))
+    pts, nrm = pts[idx], nrm[idx]
+    uu = inputs.rays.sample_numbers(len(pts), 16, 93)
+    gw = inputs.rays.guide_weights(shade.guide_cells(G), 94)
+    B = (0.05, 0.05, 0.08)
+    E, terms = oct_.proxy_irradiance_guided(_dev(pts), _dev(nrm), _dev(uu), _dev(gw), G, defensive=0.25,
+                                            background=B, want_terms=True)
+    torch.cuda.synchronize()
+    orc = shade.proxy_irradiance_guided(c1_tree, pts, nrm, uu, gw, G, 0.25, background=B)
+    _check(c1_tree, pts, nrm, uu, B, "linear", terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64), orc=orc)
