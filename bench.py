@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rays/s: octree radiance query FP32 vs FP16 vs MLP surrogate at ≤1% rel err"
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TFLOPS = 78.6      # vector FMA without packed float32 (= the FP64 rate)
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2207_05009_amd", "csrc")
 
@@ -440,13 +441,18 @@ def floor_variant(inputs, oct32, steps):
 def guided_variant(inputs, oct32, steps):
     """Radiance-field-guided proxy sampling on the floor grid: the guide
     (16 x 16 cells per face, 64 probe rays per cell, one lq_proxy_guide
-    call), the guided irradiance call (1,048,576 points x 16 samples, the
-    floor workload of the uniform variant), and the mean squared error of
-    both estimators at 16 samples per point against a 4,096-sample uniform
-    reference on 4,096 of the points."""
+    call) and the guided irradiance call (1,048,576 points x 16 samples, the
+    floor workload of the uniform variant), timed; then the estimator's
+    quality on 4,096 of the points at 256 samples each: the variance of one
+    sample's luminance term (the error of an n-sample estimate is this over
+    n, both estimators being unbiased) for the uniform estimator over the
+    whole proxy, for the guided one with defensive share 1 (uniform over the
+    faces the point sees) and with 0.5 (the guide's share), and the mean
+    z-score of the guided against the uniform means (near 0 when both
+    estimate the same integral)."""
     import numpy as np
     import torch
-    G, R = 16, 64
+    G, R, Q = 16, 64, 256
     up = torch.from_numpy(inputs.rays.probe_numbers(6 * G * G, R, 90)).cuda()
     w = torch.empty((6 * G * G,), device="cuda")
     ms_guide, _ = time_launches(lambda: oct32.proxy_guide(G, up, weights=w), steps, 1)
@@ -457,32 +463,26 @@ def guided_variant(inputs, oct32, steps):
     bg = (0.05, 0.05, 0.08)
     ms, _ = time_launches(lambda: oct32.proxy_irradiance_guided(P, N, U, w, G, defensive=0.5, background=bg,
                                                                 irradiance=E), steps, 2)
-    # estimator quality on every 64th point: the variance of a sample's
-    # luminance term (over the point's 16 samples, averaged over the points)
-    # and the mean squared error of the 16-sample estimates against a
-    # 4096-sample uniform reference on every 256th point
-    sub = np.arange(0, len(pts), 64)
-    Ps, Ns, U16 = P[sub].contiguous(), N[sub].contiguous(), U[sub].contiguous()
-    Eu, tu = oct32.proxy_irradiance(Ps, Ns, U16, background=bg, want_terms=True)
-    Eg, tg = oct32.proxy_irradiance_guided(Ps, Ns, U16, w, G, defensive=0.5, background=bg, want_terms=True)
-    ref_sub = np.arange(0, len(sub), 4)
-    ref, _ = oct32.proxy_irradiance(Ps[ref_sub].contiguous(), Ns[ref_sub].contiguous(),
-                                    torch.from_numpy(inputs.rays.sample_numbers(len(ref_sub), 4096, 91)).cuda(),
-                                    background=bg)
+    sub = np.arange(0, len(pts), 256)
+    Ps, Ns = P[sub].contiguous(), N[sub].contiguous()
+    Uq = torch.from_numpy(inputs.rays.sample_numbers(len(sub), Q, 91)).cuda()
+    _, tu = oct32.proxy_irradiance(Ps, Ns, Uq, background=bg, want_terms=True)
+    _, t1 = oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=1.0, background=bg, want_terms=True)
+    _, th = oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=0.5, background=bg, want_terms=True)
     torch.cuda.synchronize()
-    lum = lambda a: a.double().mean(-1)
-    var_u = float(lum(tu).var(1).mean())
-    var_g = float(lum(tg).var(1).mean())
-    mse_u = float(((lum(Eu[ref_sub]) - lum(ref)) ** 2).mean())
-    mse_g = float(((lum(Eg[ref_sub]) - lum(ref)) ** 2).mean())
+    lum = lambda a: a.double().mean(-1).cpu().numpy()
+    lu, l1, lh = lum(tu), lum(t1), lum(th)
+    vu, v1, vh = (float(a.var(1).mean()) for a in (lu, l1, lh))
+    z = (lh.mean(1) - lu.mean(1)) / np.maximum(np.sqrt((lu.var(1) + lh.var(1)) / Q), 1e-30)
     rec = {"grid": G, "probes_per_cell": R, "guide_ms": ms_guide, "points": len(pts), "samples_per_point": 16,
            "ms": ms, "points_per_s": len(pts) / (ms * 1e-3), "defensive": 0.5,
-           "term_variance_ratio_uniform_over_guided": var_u / var_g if var_g > 0 else None,
-           "mse_ratio_uniform_over_guided": mse_u / mse_g if mse_g > 0 else None,
-           "quality_sample": f"term variance over {len(sub)} points x 16 samples; MSE over {len(ref_sub)} points "
-                             f"against a 4096-sample uniform reference"}
-    log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms, variance ratio "
-        f"{rec['term_variance_ratio_uniform_over_guided']}, MSE ratio {rec['mse_ratio_uniform_over_guided']}")
+           "term_variance": {"uniform_whole_proxy": vu, "visible_faces_uniform": v1, "guided_defensive_0.5": vh},
+           "variance_ratio_uniform_over_guided": vu / vh if vh > 0 else None,
+           "variance_ratio_visible_uniform_over_guided": v1 / vh if vh > 0 else None,
+           "mean_z_guided_vs_uniform": float(z.mean()),
+           "quality_sample": f"{len(sub)} floor points x {Q} samples"}
+    log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms; term variance uniform {vu:.4g}, "
+        f"visible-face uniform {v1:.4g}, guided {vh:.4g}; mean z {z.mean():.3f}")
     return rec
 
 
@@ -495,8 +495,12 @@ def distill_variant(lumiq, steps):
     with 256 samples per kept voxel, one lq_distill_leaves call per step
     (centre test, compaction, sampling and averaging; the call reads the
     kept count back to size the launch).  The sampling kernel is bound by
-    its arithmetic: per sample 24 + 23 n_blobs float32 operations (an FMA
-    counts 2, a transcendental 1) against the chip's float32 vector peak."""
+    its arithmetic: per sample 24 + 23 n_blobs operations (an FMA counts 2,
+    a transcendental 1; 9 of each blob's 23 in FP64, the rest float32).
+    Its time is the call's minus that of a counting call (the centre test
+    and scan alone); the peak is the chip's vector FMA rate without packed
+    float32 math, which is also its FP64 rate: 256 CUs x 4 SIMDs x 16 lanes
+    x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s."""
     import torch
     import inputs
     from inputs.trees import field_params
@@ -512,7 +516,13 @@ def distill_variant(lumiq, steps):
                                         lumiq._ptr(codes), lumiq._ptr(sig), lumiq._ptr(sh), lumiq.C.byref(cnt),
                                         lumiq._stream(None)))
 
+    def count():
+        lumiq.check(L.lq_distill_leaves(lumiq.C.byref(desc), 9, 0.01, DISTILL_SAMPLES, 2022, 0, 0, None, None,
+                                        None, lumiq.C.byref(cnt), lumiq._stream(None)))
+
     ms, _ = time_launches(call, steps, 2)
+    ms_count, _ = time_launches(count, steps, 2)
+    ms_sample = ms - ms_count
     nb = len(p["radii"])
     flop = n * DISTILL_SAMPLES * (24 + 23 * nb)
     t0 = time.perf_counter()
@@ -522,12 +532,15 @@ def distill_variant(lumiq, steps):
     info = tree.info()
     tree.free()
     rec = {"depth": 9, "voxels": 1 << 27, "kept": int(n), "samples_per_voxel": DISTILL_SAMPLES, "ms": ms,
+           "ms_centre_test_and_scan": ms_count, "ms_sampling": ms_sample,
            "samples_per_s": n * DISTILL_SAMPLES / (ms * 1e-3),
-           "roofline": {"bound": "alu", "achieved": round(flop / (ms * 1e-3) / 1e12, 2), "peak": 157.3,
-                        "unit": "TFLOP/s", "frac": round(flop / (ms * 1e-3) / 157.3e12, 4),
+           "roofline": {"bound": "alu", "achieved": round(flop / (ms_sample * 1e-3) / 1e12, 2),
+                        "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flop / (ms_sample * 1e-3) / (ALU_PEAK_TFLOPS * 1e12), 4),
                         "flop_per_sample": 24 + 23 * nb},
            "octree_build_and_load_s": round(t_tree, 3), "n_nodes": info["n_nodes"]}
-    log(f"distillation: {ms:.3f} ms for {n} voxels x {DISTILL_SAMPLES} samples")
+    log(f"distillation: {ms:.3f} ms for {n} voxels x {DISTILL_SAMPLES} samples "
+        f"(centre test and scan {ms_count:.3f} ms)")
     del keep
     return rec
 
