@@ -545,8 +545,11 @@ struct Marcher {
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
                 if (ax != xa && r.d[ax] != 0.0f) fast = fast && later(tc[ax], xt);
-            const int nx = (xa == 0 ? r.d[0] : (xa == 1 ? r.d[1] : r.d[2])) > 0.0f ? lo_sel(lo, xa) + Sz
-                                                                                    : lo_sel(lo, xa) - 1;
+            // the next cell along the exit axis, as selects (written as
+            // nested conditionals the compiler branches on the axis)
+            const float dxa = xa == 2 ? r.d[2] : (xa == 1 ? r.d[1] : r.d[0]);
+            const int loa = xa == 2 ? lo[2] : (xa == 1 ? lo[1] : lo[0]);
+            const int nx = loa + (dxa > 0.0f ? Sz : -1);
             leave = nx < 0 || nx >= N;
             nq[0] = xa == 0 ? nx : nq[0];
             nq[1] = xa == 1 ? nx : nq[1];
