@@ -228,20 +228,52 @@ __global__ void k_guide_reduce(const float *rgb, int R, int n_cells, float *weig
     weights[c] = (float)(s / R);
 }
 
-// The cell probabilities and their running sums, in cell order, by one
-// thread (FP64): W = sum w, p_k = (1 - beta) (w_k / W) + beta / n (1 / n
-// each when W = 0), cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.
-__global__ void k_guide_cdf(const float *weights, int n, double beta, double *prob, double *cdf) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double W = 0.0;
-    for (int k = 0; k < n; ++k) W += (double)weights[k];
-    double run = 0.0;
-    cdf[0] = 0.0;
-    for (int k = 0; k < n; ++k) {
-        const double p = W > 0.0 ? (1.0 - beta) * ((double)weights[k] / W) + beta / n : 1.0 / n;
-        prob[k] = p;
-        run += p;
-        cdf[k + 1] = run;
+// The cell probabilities and their running sums, in cell order (FP64):
+// W = sum w, p_k = (1 - beta) (w_k / W) + beta / n (1 / n each when W = 0),
+// cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.  The sums are sequential (their
+// order fixes the FP64 results); one block stages the weights in LDS chunk
+// by chunk with coalesced loads, computes a chunk's p_k in parallel, and
+// thread 0 runs the sums over LDS.
+constexpr int kCdfBlock = 256;
+constexpr int kCdfChunk = 2048;   // cells staged in LDS at a time
+
+__global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, int n, double beta, double *prob,
+                                                         double *cdf) {
+    __shared__ double s_v[kCdfChunk];
+    __shared__ double s_W;
+    const int t = threadIdx.x;
+    double W = 0.0;   // thread 0 only
+    for (int c0 = 0; c0 < n; c0 += kCdfChunk) {
+        const int m = min(kCdfChunk, n - c0);
+        for (int i = t; i < m; i += kCdfBlock) s_v[i] = (double)weights[c0 + i];
+        __syncthreads();
+        if (t == 0)
+            for (int i = 0; i < m; ++i) W += s_v[i];
+        __syncthreads();
+    }
+    if (t == 0) {
+        s_W = W;
+        cdf[0] = 0.0;
+    }
+    __syncthreads();
+    W = s_W;
+    double run = 0.0;   // thread 0 only
+    for (int c0 = 0; c0 < n; c0 += kCdfChunk) {
+        const int m = min(kCdfChunk, n - c0);
+        for (int i = t; i < m; i += kCdfBlock) {
+            const double p = W > 0.0 ? (1.0 - beta) * ((double)weights[c0 + i] / W) + beta / n : 1.0 / n;
+            prob[c0 + i] = p;
+            s_v[i] = p;
+        }
+        __syncthreads();
+        if (t == 0)
+            for (int i = 0; i < m; ++i) {
+                run += s_v[i];
+                s_v[i] = run;
+            }
+        __syncthreads();
+        for (int i = t; i < m; i += kCdfBlock) cdf[c0 + i + 1] = s_v[i];
+        __syncthreads();
     }
 }
 
@@ -375,7 +407,7 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
         g.n_cells = n_cells;
         g.step = (float)(2.0 / grid);
         g.area = (2.0 / grid) * (2.0 / grid);
-        hipLaunchKernelGGL(k_guide_cdf, dim3(1), dim3(64), 0, s, weights, n_cells, (double)defensive,
+        hipLaunchKernelGGL(k_guide_cdf, dim3(1), dim3(kCdfBlock), 0, s, weights, n_cells, (double)defensive,
                            const_cast<double *>(g.prob), const_cast<double *>(g.cdf));
     }
     hipLaunchKernelGGL(k_proxy_zero, dim3(1), dim3(1), 0, s, n_live);
