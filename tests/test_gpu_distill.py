@@ -58,6 +58,7 @@ def _params(depth, n_blobs, n_shells, deg, seed, occupancy=0.3):
     (4, 12, 0, 3, 7, 8),       # template 16, odd sample count
     (3, 24, 3, 0, 1, 9),       # template 32, SH degree 0, one sample
     (1, 3, 0, 4, 64, 10),      # the smallest grid, SH degree 4
+    (2, 5, 1, 1, 37, 12),      # two whole blocks of 16 samples and a ragged one
 ])
 def test_distillation_matches_oracle(lq, depth, n_blobs, n_shells, deg, samples, seed):
     import torch

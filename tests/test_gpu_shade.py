@@ -214,6 +214,27 @@ def test_guided_irradiance_parity(lq, c0_tree, which, model, beta):
            E.cpu().numpy().astype(np.float64), orc=orc)
 
 
+@pytest.mark.parametrize("G", [1, 40])
+@pytest.mark.parametrize("beta", [0.0, 0.25])
+def test_guided_grid_sizes(lq, c0_tree, G, beta):
+    """The smallest guide (one cell per face) and one of 9,600 cells, more
+    than one LDS chunk of the cell table (2,048 cells): the guided estimator
+    against the oracle sample by sample and point by point."""
+    import torch
+    pts, nrm = inputs.rays.scattered_points(300, 25)
+    u = inputs.rays.sample_numbers(300, 32, 26)
+    w = inputs.rays.guide_weights(shade.guide_cells(G), 27)
+    B = (0.2, 0.5, 1.0)
+    _say(f"guided proxy irradiance, grid {G} ({shade.guide_cells(G)} cells), beta {beta}")
+    oct_ = lq.Octree(c0_tree, "f32")
+    E, terms = oct_.proxy_irradiance_guided(_dev(pts), _dev(nrm), _dev(u), _dev(w), G, defensive=beta,
+                                            background=B, want_terms=True)
+    torch.cuda.synchronize()
+    orc = shade.proxy_irradiance_guided(c0_tree, pts, nrm, u, w, G, beta, background=B)
+    _check(c0_tree, pts, nrm, u, B, "linear", terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64), orc=orc)
+
+
 def test_guided_sampling_reduces_variance(lq, c0_tree):
     """On the floor below the luminaire, with the guide built on the GPU
     from probe rays: the guided and uniform estimates agree within their
