@@ -525,6 +525,9 @@ def distill_variant(lumiq, steps):
     ms_sample = ms - ms_count
     nb = len(p["radii"])
     flop = n * DISTILL_SAMPLES * (24 + 23 * nb)
+    # what the call writes: the centre-test bits of every voxel, then per kept
+    # voxel its code, density and 3 x 9 SH coefficients (float32)
+    wbytes = (1 << 27) // 8 + n * (4 + 4 + 3 * 9 * 4)
     t0 = time.perf_counter()
     tree = lumiq.octree_from_leaves(9, 2, codes, sig, sh, l_max=p["l_max"])
     torch.cuda.synchronize()
@@ -538,6 +541,7 @@ def distill_variant(lumiq, steps):
                         "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(flop / (ms_sample * 1e-3) / (ALU_PEAK_TFLOPS * 1e12), 4),
                         "flop_per_sample": 24 + 23 * nb},
+           "hbm_bytes_written": wbytes, "hbm_write_frac": round(wbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),
            "octree_build_and_load_s": round(t_tree, 3), "n_nodes": info["n_nodes"]}
     log(f"distillation: {ms:.3f} ms for {n} voxels x {DISTILL_SAMPLES} samples "
         f"(centre test and scan {ms_count:.3f} ms)")
