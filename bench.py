@@ -257,6 +257,12 @@ def error_records(samples, trees, rays):
 
     for name, smp in samples.items():
         idx, kind = smp["idx"], smp.get("kind", "octree")
+        if kind == "floor":
+            out[name] = floor_error(trees["c1"], smp)
+            continue
+        if kind == "distill":
+            out[name] = distill_error(smp)
+            continue
         if kind == "uneven":
             recs = []
             tk = smp["tree_of"]
@@ -300,6 +306,47 @@ def error_records(samples, trees, rays):
                 "rel_l2": float(np.linalg.norm(g - ref["L"]) / np.linalg.norm(ref["L"]))}
         out[name] = rec
     return out
+
+
+def floor_error(tree, smp):
+    """Irradiance of a seeded sample of floor points against the oracle on
+    the same points and sample numbers (uniform or guided by the GPU's guide
+    weights): per point, the largest channel error relative to max(|E_ref|,
+    the point's mean sample weight x 1e-6 L_max); a point with a
+    threshold-ambiguous sample ray is compared with the nearer of its two
+    sums (main and alternative candidates)."""
+    import numpy as np
+    from oracle import shade
+    if "guide" in smp:
+        orc = shade.proxy_irradiance_guided(tree, smp["pts"], smp["nrm"], smp["u"], smp["guide"], smp["G"],
+                                            smp["beta"], background=smp["bg"])
+    else:
+        orc = shade.proxy_irradiance(tree, smp["pts"], smp["nrm"], smp["u"], background=smp["bg"])
+    g = np.asarray(smp["E"], np.float64)
+    alt_E = orc["terms_alt"].mean(axis=1)
+    fl = orc["w"].mean(axis=1)[:, None] * 1e-6 * tree.l_max + 1e-30
+    e_main = (np.abs(g - orc["E"]) / np.maximum(np.abs(orc["E"]), fl)).max(1)
+    e_alt = (np.abs(g - alt_E) / np.maximum(np.abs(alt_E), fl)).max(1)
+    amb = orc["alt_valid"].any(axis=1)
+    err = np.where(amb, np.minimum(e_main, e_alt), e_main)
+    return {"points": int(len(g)), "samples_per_point": int(smp["u"].shape[1]), "max_rel": float(err.max()),
+            "p99_rel": float(np.quantile(err, 0.99)), "median_rel": float(np.median(err)),
+            "n_ambiguous_points": int(amb.sum()),
+            "vs": "FP64 oracle (sample rays, query, blend, per-point mean) on the same points and numbers"}
+
+
+def distill_error(smp):
+    """Means of a seeded sample of distilled voxels against the oracle's
+    256-sample means of the same voxels: relative errors with floors 1e-3
+    (density) and 1e-2 (SH coefficients)."""
+    import numpy as np
+    from oracle import distill as od
+    f = od.field_from_params(smp["params"])
+    sig, sh = od.average_samples(f, smp["depth"], smp["codes"], 256, smp["seed"])
+    es = np.abs(smp["sigma"].astype(np.float64) - sig) / np.maximum(np.abs(sig), 1e-3)
+    eh = np.abs(smp["sh"].astype(np.float64).reshape(sh.shape) - sh) / np.maximum(np.abs(sh), 1e-2)
+    return {"voxels": int(len(sig)), "density_max_rel": float(es.max()), "sh_max_rel": float(eh.max()),
+            "sh_median_rel": float(np.median(eh)), "vs": "FP64 oracle means of the same voxels"}
 
 
 def heuristic_bias(tree, rays):
@@ -419,11 +466,15 @@ def sh_sweep_variant(lumiq, o, d, steps):
     return out
 
 
-def floor_variant(inputs, oct32, steps):
+SHADE_SAMPLE = 300   # floor points (and distilled voxels) the CPU leg checks
+
+
+def floor_variant(inputs, oct32, steps, samples=None):
     """The consumer side: irradiance from the luminaire's proxy (emission plus
     background through it) on a 1024 x 1024 floor grid 0.5 below the proxy,
     16 uniform proxy samples per point, one call per step (sample rays, the
     query over them, the per-point blend and sum)."""
+    import numpy as np
     import torch
     pts, nrm = inputs.rays.floor_points(1024, 1024)
     u = inputs.rays.sample_numbers(len(pts), 16, 5)
@@ -432,13 +483,17 @@ def floor_variant(inputs, oct32, steps):
     ms, _ = time_launches(lambda: oct32.proxy_irradiance(P, N, U, background=(0.05, 0.05, 0.08), irradiance=E),
                           steps, 2)
     n_rays = len(pts) * 16
+    if samples is not None:
+        idx = np.sort(np.random.default_rng(41).choice(len(pts), SHADE_SAMPLE, replace=False))
+        samples["floor_irradiance"] = {"kind": "floor", "idx": idx, "E": E.cpu().numpy()[idx],
+                                       "pts": pts[idx], "nrm": nrm[idx], "u": u[idx], "bg": (0.05, 0.05, 0.08)}
     rec = {"points": len(pts), "samples_per_point": 16, "ms": ms, "points_per_s": len(pts) / (ms * 1e-3),
            "sample_rays_per_s": n_rays / (ms * 1e-3)}
     log(f"floor irradiance: {ms:.3f} ms for {n_rays} sample rays")
     return rec
 
 
-def guided_variant(inputs, oct32, steps):
+def guided_variant(inputs, oct32, steps, samples=None):
     """Radiance-field-guided proxy sampling on the floor grid: the guide
     (16 x 16 cells per face, 64 probe rays per cell, one lq_proxy_guide
     call) and the guided irradiance call (1,048,576 points x 16 samples, the
@@ -463,6 +518,11 @@ def guided_variant(inputs, oct32, steps):
     bg = (0.05, 0.05, 0.08)
     ms, _ = time_launches(lambda: oct32.proxy_irradiance_guided(P, N, U, w, G, defensive=0.5, background=bg,
                                                                 irradiance=E), steps, 2)
+    if samples is not None:
+        idx = np.sort(np.random.default_rng(42).choice(len(pts), SHADE_SAMPLE, replace=False))
+        samples["floor_irradiance_guided"] = {"kind": "floor", "idx": idx, "E": E.cpu().numpy()[idx],
+                                              "pts": pts[idx], "nrm": nrm[idx], "u": u[idx], "bg": bg,
+                                              "guide": w.cpu().numpy(), "G": G, "beta": 0.5}
     sub = np.arange(0, len(pts), 256)
     Ps, Ns = P[sub].contiguous(), N[sub].contiguous()
     Uq = torch.from_numpy(inputs.rays.sample_numbers(len(sub), Q, 91)).cuda()
@@ -489,7 +549,7 @@ def guided_variant(inputs, oct32, steps):
 DISTILL_SAMPLES = 256
 
 
-def distill_variant(lumiq, steps):
+def distill_variant(lumiq, steps, samples=None):
     """Plenoctree distillation (Sec. 5): the continuous field behind the
     depth-9 luminaire (16 blobs + 4 shells, SH degree 2) distilled at 512^3
     with 256 samples per kept voxel, one lq_distill_leaves call per step
@@ -522,6 +582,12 @@ def distill_variant(lumiq, steps):
 
     ms, _ = time_launches(call, steps, 2)
     ms_count, _ = time_launches(count, steps, 2)
+    if samples is not None:
+        import numpy as np
+        idx = np.sort(np.random.default_rng(43).choice(n, SHADE_SAMPLE, replace=False))
+        samples["distillation"] = {"kind": "distill", "idx": idx, "params": p, "depth": 9, "seed": 2022,
+                                   "codes": codes.cpu().numpy().view(np.uint32)[idx].astype(np.uint64),
+                                   "sigma": sig.cpu().numpy()[idx], "sh": sh.cpu().numpy()[idx]}
     ms_sample = ms - ms_count
     nb = len(p["radii"])
     flop = n * DISTILL_SAMPLES * (24 + 23 * nb)
@@ -771,9 +837,10 @@ def main():
         del ro_t, rd_t, rrgb, ralpha
 
     if not args.no_variants:
-        variants["floor_irradiance"] = floor_variant(inputs, oct32, max(5, args.steps // 4))
-        variants["floor_irradiance_guided"] = guided_variant(inputs, oct32, max(5, args.steps // 4))
-        variants["distillation"] = distill_variant(lumiq, 5)
+        variants["floor_irradiance"] = floor_variant(inputs, oct32, max(5, args.steps // 4), samples=samples)
+        variants["floor_irradiance_guided"] = guided_variant(inputs, oct32, max(5, args.steps // 4),
+                                                             samples=samples)
+        variants["distillation"] = distill_variant(lumiq, 5, samples=samples)
 
     if args.sh_sweep:
         variants["sh_sweep_camera"] = sh_sweep_variant(lumiq, o, d, max(5, args.steps // 2))
