@@ -58,16 +58,20 @@ __device__ inline uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// The radiance and opacity of a finished ray go out as non-temporal stores:
+// lanes finish at different steps, so each store fills only part of a line,
+// and without the hint those partial lines occupy L2 until evicted
+// (incoherent batches: room f32 5.81 -> 5.74 ms, f16 5.37 -> 5.28 ms).
 template <class M>
 __device__ inline void write_ray(const QueryArgs &a, int64_t i, const M &m, bool trace) {
     RayOut r;
     m.result(r);
     if (a.rgb) {
-        a.rgb[3 * i] = r.rgb[0];
-        a.rgb[3 * i + 1] = r.rgb[1];
-        a.rgb[3 * i + 2] = r.rgb[2];
+        __builtin_nontemporal_store(r.rgb[0], a.rgb + 3 * i);
+        __builtin_nontemporal_store(r.rgb[1], a.rgb + 3 * i + 1);
+        __builtin_nontemporal_store(r.rgb[2], a.rgb + 3 * i + 2);
     }
-    if (a.alpha) a.alpha[i] = r.alpha;
+    if (a.alpha) __builtin_nontemporal_store(r.alpha, a.alpha + i);
     if (trace) {
         a.count[i] = r.count;
         a.hash[i] = r.hash;
