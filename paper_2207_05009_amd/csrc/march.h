@@ -362,8 +362,14 @@ struct Marcher {
     LQ_HD bool init(const DevTree &t, const float *o3, const float *d3) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
+#ifdef __HIP_DEVICE_COMPILE__
+            // read once: non-temporal, so the rays do not displace tree lines in L2
+            r.o[ax] = __builtin_nontemporal_load(o3 + ax);
+            r.d[ax] = __builtin_nontemporal_load(d3 + ax);
+#else
             r.o[ax] = o3[ax];
             r.d[ax] = d3[ax];
+#endif
         }
         L0 = L1 = L2 = 0;
         T = 1;
