@@ -57,6 +57,13 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            # PyTorch ships a HIP runtime of its own and puts it in the process's
+            # global symbol scope when imported.  Importing it before the library
+            # is loaded binds the library's HIP calls to that same runtime, the one
+            # that owns torch's memory and streams.  Loaded the other way round, the
+            # library would start the system runtime first, and torch's runtime,
+            # started second, finds no GPU.
+            import torch  # noqa: F401
             L = C.CDLL(LIB_PATH)
             vp, i64, i32, u32 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32
             L.lq_last_error.restype = C.c_char_p
