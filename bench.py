@@ -493,21 +493,25 @@ def floor_variant(inputs, oct32, steps, samples=None):
     return rec
 
 
+QUALITY_POINTS, QUALITY_SAMPLES = 4096, 4096
+
+
 def guided_variant(inputs, oct32, steps, samples=None):
     """Radiance-field-guided proxy sampling on the floor grid: the guide
     (16 x 16 cells per face, 64 probe rays per cell, one lq_proxy_guide
     call) and the guided irradiance call (1,048,576 points x 16 samples, the
     floor workload of the uniform variant), timed; then the estimator's
-    quality on 4,096 of the points at 256 samples each: the variance of one
-    sample's luminance term (the error of an n-sample estimate is this over
-    n, both estimators being unbiased) for the uniform estimator over the
-    whole proxy, for the guided one with defensive share 1 (uniform over the
-    faces the point sees) and with 0.5 (the guide's share), and the mean
-    z-score of the guided against the uniform means (near 0 when both
-    estimate the same integral)."""
+    quality on 4,096 random points of the floor at 4,096 samples each: the
+    variance of one sample's luminance term (the error of an n-sample
+    estimate is this over n, both estimators being unbiased), mean and
+    median over the points, for the uniform estimator over the whole proxy,
+    for the guided one with defensive share 1 (uniform cells, the face
+    chosen by the geometry mix among the faces the point sees) and with 0.5
+    (the guide's share), and the mean z-score of the guided against the
+    uniform means (near 0 when both estimate the same integral)."""
     import numpy as np
     import torch
-    G, R, Q = 16, 64, 256
+    G, R, Q = 16, 64, QUALITY_SAMPLES
     up = torch.from_numpy(inputs.rays.probe_numbers(6 * G * G, R, 90)).cuda()
     w = torch.empty((6 * G * G,), device="cuda")
     ms_guide, _ = time_launches(lambda: oct32.proxy_guide(G, up, weights=w), steps, 1)
@@ -523,26 +527,37 @@ def guided_variant(inputs, oct32, steps, samples=None):
         samples["floor_irradiance_guided"] = {"kind": "floor", "idx": idx, "E": E.cpu().numpy()[idx],
                                               "pts": pts[idx], "nrm": nrm[idx], "u": u[idx], "bg": bg,
                                               "guide": w.cpu().numpy(), "G": G, "beta": 0.5}
-    sub = np.arange(0, len(pts), 256)
+    # quality: 4,096 seeded random floor points, 4,096 samples each (the
+    # per-point variance of a heavy-tailed term needs many samples; mean and
+    # median over the points)
+    sub = np.sort(np.random.default_rng(44).choice(len(pts), QUALITY_POINTS, replace=False))
     Ps, Ns = P[sub].contiguous(), N[sub].contiguous()
     Uq = torch.from_numpy(inputs.rays.sample_numbers(len(sub), Q, 91)).cuda()
-    _, tu = oct32.proxy_irradiance(Ps, Ns, Uq, background=bg, want_terms=True)
-    _, t1 = oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=1.0, background=bg, want_terms=True)
-    _, th = oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=0.5, background=bg, want_terms=True)
+
+    def term_stats(t):
+        lum = t.double().mean(-1)
+        return lum.mean(1).cpu().numpy(), lum.var(1).cpu().numpy()
+
+    mu, vu = term_stats(oct32.proxy_irradiance(Ps, Ns, Uq, background=bg, want_terms=True)[1])
+    m1, v1 = term_stats(oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=1.0, background=bg,
+                                                      want_terms=True)[1])
+    mh, vh = term_stats(oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=0.5, background=bg,
+                                                      want_terms=True)[1])
     torch.cuda.synchronize()
-    lum = lambda a: a.double().mean(-1).cpu().numpy()
-    lu, l1, lh = lum(tu), lum(t1), lum(th)
-    vu, v1, vh = (float(a.var(1).mean()) for a in (lu, l1, lh))
-    z = (lh.mean(1) - lu.mean(1)) / np.maximum(np.sqrt((lu.var(1) + lh.var(1)) / Q), 1e-30)
+    z = (mh - mu) / np.maximum(np.sqrt((vu + vh) / Q), 1e-30)
+    stats = lambda v: {"mean": float(v.mean()), "median": float(np.median(v))}
     rec = {"grid": G, "probes_per_cell": R, "guide_ms": ms_guide, "points": len(pts), "samples_per_point": 16,
            "ms": ms, "points_per_s": len(pts) / (ms * 1e-3), "defensive": 0.5,
-           "term_variance": {"uniform_whole_proxy": vu, "visible_faces_uniform": v1, "guided_defensive_0.5": vh},
-           "variance_ratio_uniform_over_guided": vu / vh if vh > 0 else None,
-           "variance_ratio_visible_uniform_over_guided": v1 / vh if vh > 0 else None,
+           "term_variance": {"uniform_whole_proxy": stats(vu), "guided_defensive_1": stats(v1),
+                             "guided_defensive_0.5": stats(vh)},
+           "variance_ratio_uniform_over_guided": float(vu.mean() / vh.mean()) if vh.mean() > 0 else None,
+           "median_point_variance_ratio_uniform_over_guided": float(np.median(vu / np.maximum(vh, 1e-300))),
+           "variance_ratio_defensive_1_over_0.5": float(v1.mean() / vh.mean()) if vh.mean() > 0 else None,
            "mean_z_guided_vs_uniform": float(z.mean()),
-           "quality_sample": f"{len(sub)} floor points x {Q} samples"}
-    log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms; term variance uniform {vu:.4g}, "
-        f"visible-face uniform {v1:.4g}, guided {vh:.4g}; mean z {z.mean():.3f}")
+           "quality_sample": f"{len(sub)} random floor points x {Q} samples"}
+    log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms; term variance (mean / median over "
+        f"points) uniform {vu.mean():.4g} / {np.median(vu):.4g}, guided defensive 1 {v1.mean():.4g} / "
+        f"{np.median(v1):.4g}, guided defensive 0.5 {vh.mean():.4g} / {np.median(vh):.4g}; mean z {z.mean():.3f}")
     return rec
 
 

@@ -262,15 +262,24 @@ lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const 
  * (1 / (6 grid^2) each when W = 0), summed in cell order in FP64 into
  * cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.  A point receives light only
  * through the faces it sees from the front (side * x_axis > 1), so its
- * samples pick among those faces' cells: with P_f = cdf[(f + 1) grid^2] -
- * cdf[f grid^2] and P_vis the sum of P_f over the visible faces, sample s
- * of point i walks the visible faces in order with t = u[i][s][0] P_vis;
- * in the face where t < P_f (the last visible face takes any remainder) it
- * picks the largest cell k of the face with cdf[k] <= cdf[f grid^2] + t,
- * and the point of that cell at u[i][s][1], u[i][s][2] as above.  Its area
- * density is p_k / (P_vis (2 / grid)^2), and its term L_o cos(theta_x)
+ * samples pick among those faces' cells.  Face f has guide mass
+ * P_f = cdf[(f + 1) grid^2] - cdf[f grid^2] and, with c_f its centre
+ * (side on its axis, 0 on the others), the geometry weight
+ *     g_f = max(0, n.(c_f - x)) (side x_axis - 1) / |c_f - x|^4,
+ * the integrand cos(theta_x) cos(theta_y) / r^2 at c_f up to the constant
+ * 1 / |n|.  With P_vis and S the sums of P_f and P_f g_f over the visible
+ * faces, face f is chosen with probability
+ *     Q_f = 0.5 P_f g_f / S + 0.5 P_f / P_vis   (P_f / P_vis when S = 0):
+ * sample s of point i walks the visible faces in order with t = u[i][s][0];
+ * in the face where t < Q_f (the last visible face takes any remainder) it
+ * picks the largest cell k of the face with
+ * cdf[k] <= cdf[f grid^2] + (t / Q_f) P_f (t / Q_f taken as 0 when
+ * Q_f = 0), and the point of that cell at
+ * u[i][s][1], u[i][s][2] as above.  All of the choice is FP64 from the
+ * float32 inputs, sums in axis and face order.  The sample's area density
+ * is p_k (Q_f / P_f) / (2 / grid)^2, and its term L_o cos(theta_x)
  * cos(theta_y) / (|y - x|^2 p_A) (zero as in lq_proxy_irradiance, for a
- * point that sees no face, and for a cell of p_k = 0).  The estimate stays
+ * point that sees no face, and for a cell of p_k Q_f = 0).  The estimate stays
  * unbiased for any guide with defensive > 0; defensive in [0, 1], grid in
  * 1..256.  Scratch: as lq_proxy_irradiance plus 8 (12 grid^2 + 1) bytes.
  */

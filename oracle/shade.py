@@ -186,28 +186,63 @@ def visible_faces(x):
     return out
 
 
-def guided_cell(cdf, G, vis, u0):
-    """The cell a sample picks: t = u0 P_vis walks the visible faces in
-    order (face f holds cells [f G^2, (f + 1) G^2) and probability
-    P_f = cdf[(f + 1) G^2] - cdf[f G^2]): in the face where t < P_f (the
-    last visible face takes any remainder) the cell is the largest k of the
-    face with cdf[k] <= cdf[f G^2] + t.  Returns (cell, P_vis); cell -1 when
-    no face is visible or P_vis = 0."""
+FACE_MIX = 0.5   # share of the face choice weighted by the face-centre geometry
+
+
+def face_geometry(x, n, f):
+    """Geometry weight of face f for a point x with normal n, at the face's
+    centre c (c_a = side, the other coordinates 0): max(0, n.(c - x)) (side
+    x_a - 1) / |c - x|^4, the irradiance integrand cos(theta_x)
+    cos(theta_y) / r^2 there up to the point's constant factor 1 / |n|.
+    FP64 from the float32 inputs, each sum in axis order."""
+    a, sgn = f >> 1, (1.0 if f & 1 else -1.0)
+    xd = [float(v) for v in np.asarray(x, np.float32)]
+    nd = [float(v) for v in np.asarray(n, np.float32)]
+    d = [(sgn if b == a else 0.0) - xd[b] for b in range(3)]
+    r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+    ndot = nd[0] * d[0] + nd[1] * d[1] + nd[2] * d[2]
+    h = sgn * xd[a] - 1.0
+    return (ndot * h) / (r2 * r2) if ndot > 0.0 else 0.0
+
+
+def guided_cell(cdf, G, x, n, u0):
+    """The cell a sample picks.  The point sees faces vis (side x_axis > 1);
+    P_f = cdf[(f + 1) G^2] - cdf[f G^2] is face f's guide mass, P_vis their
+    sum over the visible faces, g_f = face_geometry and S = sum of P_f g_f
+    over them.  Face f is chosen with probability
+        Q_f = FACE_MIX P_f g_f / S + (1 - FACE_MIX) P_f / P_vis
+    (P_f / P_vis when S = 0): t = u0 walks the visible faces in order, and
+    in the face where t < Q_f (the last visible face takes any remainder)
+    the cell is the largest k of the face with cdf[k] <= cdf[f G^2] + r P_f,
+    r = t / Q_f (0 when Q_f = 0).  Returns (cell, Q_f / P_f): the cell's
+    area density is p_k (Q_f / P_f) / A_cell.  Cell -1 when no face is
+    visible or P_vis = 0."""
     gg = G * G
+    xs = np.asarray(x, np.float32)
+    vis = visible_faces(xs)[0]
     P = [cdf[(f + 1) * gg] - cdf[f * gg] for f in range(6)]
     pv = 0.0
+    gs = 0.0
+    g = [0.0] * 6
     for f in range(6):
         if vis[f]:
+            g[f] = face_geometry(xs, n, f)
             pv += P[f]
+            gs += P[f] * g[f]
     if not pv > 0.0:
         return -1, 0.0
-    t = float(u0) * pv
+    Q = [0.0] * 6
+    for f in range(6):
+        if vis[f]:
+            Q[f] = FACE_MIX * (P[f] * g[f] / gs) + (1.0 - FACE_MIX) * (P[f] / pv) if gs > 0.0 else P[f] / pv
+    t = float(np.float32(u0))
     last = max(f for f in range(6) if vis[f])
     for f in range(6):
         if not vis[f]:
             continue
-        if t < P[f] or f == last:
-            target = cdf[f * gg] + t
+        if t < Q[f] or f == last:
+            r = t / Q[f] if Q[f] > 0.0 else 0.0
+            target = cdf[f * gg] + r * P[f]
             lo, hi = f * gg, f * gg + gg - 1
             while lo < hi:
                 mid = (lo + hi + 1) // 2
@@ -215,8 +250,8 @@ def guided_cell(cdf, G, vis, u0):
                     lo = mid
                 else:
                     hi = mid - 1
-            return lo, pv
-        t -= P[f]
+            return lo, (Q[f] / P[f] if P[f] > 0.0 else 0.0)
+        t -= Q[f]
     return -1, 0.0
 
 
@@ -224,20 +259,20 @@ def guided_proxy_rays(points, normals, u, weights, G, beta):
     """Rays and weights of guided samples: u [n, S, 3]: u0 picks the cell
     among the faces the point sees (guided_cell), u1, u2 the point in it.
     The Monte Carlo weight is cos(theta_x) cos(theta_y) / (|y - x|^2 p_A)
-    with p_A = p_k / (P_vis A_cell); zero below the horizon, and for a point
-    that sees no face."""
+    with p_A = p_k (Q_f / P_f) / A_cell; zero below the horizon, and for a
+    point that sees no face."""
     x = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
-    nrm = np.asarray(normals, np.float64).reshape(-1, 3)
+    nrm32 = np.asarray(normals, np.float32).reshape(-1, 3)
+    nrm = nrm32.astype(np.float64)
     u = np.ascontiguousarray(u, np.float32)
     n, S = u.shape[0], u.shape[1]
     u = u.reshape(n * S, 3)
     p, cdf = guide_cdf(weights, beta)
-    vis = visible_faces(x)
     cell = np.empty(n * S, np.int64)
-    pvis = np.zeros(n * S)
+    factor = np.zeros(n * S)
     for i in range(n):
         for j in range(S):
-            cell[i * S + j], pvis[i * S + j] = guided_cell(cdf, G, vis[i], u[i * S + j, 0])
+            cell[i * S + j], factor[i * S + j] = guided_cell(cdf, G, x[i], nrm32[i], u[i * S + j, 0])
     dead = cell < 0
     cell = np.where(dead, 0, cell)
     y, face, axis, sgn = _cell_point(cell, u[:, 1], u[:, 2], G)
@@ -253,7 +288,7 @@ def guided_proxy_rays(points, normals, u, weights, G, beta):
     h = sgn.astype(np.float64) * xs.astype(np.float64)[rows, axis] - 1.0
     cos_y = h / np.where(dist > 0, dist, 1.0)
     area = (2.0 / G) ** 2
-    pa = np.where(dead, 0.0, p[cell] / np.where(dead, 1.0, pvis) / area)
+    pa = np.where(dead, 0.0, p[cell] * factor / area)
     ok = (h > 0) & (cos_x > 0) & (dist2 > 0) & (nlen > 0) & (pa > 0)
     w = np.where(ok, cos_x * cos_y / np.where(dist2 > 0, dist2, 1.0) / np.where(pa > 0, pa, 1.0), 0.0)
     d[~ok] = 0.0

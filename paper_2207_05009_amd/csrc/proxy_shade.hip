@@ -62,39 +62,71 @@ struct Guide {
     double area;          // (2 / G)^2
 };
 
-// returns the cell (or -1 when the point sees no face, or P_vis = 0) and P_vis
-__device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, float u0, double &pvis) {
+constexpr double kFaceMix = 0.5;   // share of the face choice weighted by the face-centre geometry
+
+// Picks the cell of a guided sample.  The point x (normal n) sees the faces
+// with side * x_axis > 1; P_f is face f's guide mass, P_vis their sum,
+// g_f = max(0, n.(c_f - x)) (side x_axis - 1) / |c_f - x|^4 the irradiance
+// integrand cos cos / r^2 at the face centre c_f (up to the constant 1/|n|)
+// and S the sum of P_f g_f.  Face f is taken with probability
+// Q_f = kFaceMix P_f g_f / S + (1 - kFaceMix) P_f / P_vis (P_f / P_vis when
+// S = 0), the cell within it by inverting the guide CDF.  All of it in FP64
+// from the float32 inputs, sums in axis and face order, so that the choice
+// is reproducible bit for bit.  Returns the cell (-1 when no face is visible
+// or P_vis = 0) and Q_f / P_f in `factor`: the sample's area density is
+// p_k factor / A_cell.
+__device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, float n0, float n1, float n2,
+                                 float u0, double &factor) {
     const int gg = g.G * g.G;
+    const double xd[3] = {(double)x0, (double)x1, (double)x2};
+    const double nd[3] = {(double)n0, (double)n1, (double)n2};
     bool vis[6];
-    double P[6];
-    double pv = 0.0;
+    double P[6], Q[6], gf[6];
+    double pv = 0.0, gs = 0.0;
     int last = -1;
+    factor = 0.0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const float xa = (f >> 1) == 0 ? x0 : ((f >> 1) == 1 ? x1 : x2);
+        const int ax = f >> 1;
+        const float xa = ax == 0 ? x0 : (ax == 1 ? x1 : x2);
         vis[f] = ((f & 1) ? xa : -xa) > 1.0f;
         P[f] = g.cdf[(f + 1) * gg] - g.cdf[f * gg];
+        gf[f] = 0.0;
         if (vis[f]) {
+            const double sg = (f & 1) ? 1.0 : -1.0;
+            double d[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) d[b] = (b == ax ? sg : 0.0) - xd[b];
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double ndot = nd[0] * d[0] + nd[1] * d[1] + nd[2] * d[2];
+            const double h = sg * xd[ax] - 1.0;
+            gf[f] = ndot > 0.0 ? (ndot * h) / (r2 * r2) : 0.0;
             pv += P[f];
+            gs += P[f] * gf[f];
             last = f;
         }
     }
-    pvis = pv;
     if (!(pv > 0.0)) return -1;
-    double t = (double)u0 * pv;
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+        Q[f] = !vis[f] ? 0.0
+                       : (gs > 0.0 ? kFaceMix * (P[f] * gf[f] / gs) + (1.0 - kFaceMix) * (P[f] / pv) : P[f] / pv);
+    double t = (double)u0;
     for (int f = 0; f < 6; ++f) {
         if (!vis[f]) continue;
-        if (t < P[f] || f == last) {
-            const double target = g.cdf[f * gg] + t;
+        if (t < Q[f] || f == last) {
+            const double r = Q[f] > 0.0 ? t / Q[f] : 0.0;
+            const double target = g.cdf[f * gg] + r * P[f];
             int lo = f * gg, hi = f * gg + gg - 1;   // cdf[lo] <= target holds for lo = f gg
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (g.cdf[mid] <= target) lo = mid;
                 else hi = mid - 1;
             }
+            factor = P[f] > 0.0 ? Q[f] / P[f] : 0.0;
             return lo;
         }
-        t -= P[f];
+        t -= Q[f];
     }
     return -1;
 }
@@ -123,10 +155,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
             int f;
             float a, b, inv_density = kInvAreaDensity;
             if (g.cdf) {
-                double pvis = 0.0;
-                int k = guide_cell(g, x0, x1, x2, u0, pvis);
-                const double pk = k >= 0 ? g.prob[k] : 0.0;
-                inv_density = pk > 0.0 ? (float)(pvis * g.area / pk) : 0.0f;
+                double factor = 0.0;
+                int k = guide_cell(g, x0, x1, x2, n0, n1, n2, u0, factor);
+                const double pa = k >= 0 ? g.prob[k] * factor / g.area : 0.0;
+                inv_density = pa > 0.0 ? (float)(1.0 / pa) : 0.0f;
                 k = k < 0 ? 0 : k;                    // a dead sample: any cell, weight 0
                 const int gg = g.G * g.G;
                 f = k / gg;

@@ -171,31 +171,68 @@ def test_uniform_guide_is_area_uniform():
         assert np.allclose(w[live] * r2 / (cos_x * cos_y), 4.0, rtol=1e-9)
 
 
+def _face_choice(x, n, P, vis):
+    """Face probabilities from their definition: half in proportion to the
+    guide mass, half to the guide mass times cos cos / r^2 at the face
+    centre (r^4 in the denominator: cos_y = h / r, cos_x = n.d / (|n| r),
+    and the constant 1 / |n| cancels)."""
+    x = x.astype(np.float64)
+    n = n.astype(np.float64)
+    centres = np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0], [0, 0, -1], [0, 0, 1]], np.float64)
+    d = centres - x
+    h = np.abs(x[np.arange(6) >> 1]) - 1.0
+    g = np.clip(d @ n, 0.0, None) * h / np.einsum("ij,ij->i", d, d) ** 2
+    Pv = np.where(vis, P, 0.0)
+    if (Pv * g).sum() == 0:
+        return Pv / Pv.sum()
+    return 0.5 * Pv * g / (Pv * g).sum() + 0.5 * Pv / Pv.sum()
+
+
 def test_cell_frequencies_follow_the_guide():
     """Cells of the faces the point sees are picked with probability
-    p_k / P_vis, p_k = (1 - beta) w_k / W + beta / n: counts within 5
-    standard deviations, none on the other faces; with beta = 0 a cell of
-    weight 0 is never picked."""
+    Q_f p_k / P_f: faces by the mix of guide mass and face-centre geometry,
+    cells within a face by p_k = (1 - beta) w_k / W + beta / n.  Counts
+    within 5 standard deviations, none on the other faces; with beta = 0 a
+    cell of weight 0 is never picked."""
     w = _random_guide(3)
     S = 200_000
     u = inputs.rays.sample_numbers(1, S, 22)
-    # a point that sees three faces: x > 1, y < -1, z < -1 (faces 1, 2, 4)
-    x = np.array([[2.5, -3.0, -1.7]], np.float32)
-    n = np.array([[-1.0, 1.0, 1.0]], np.float32)
-    vis = shade.visible_faces(x)[0]
-    assert list(np.nonzero(vis)[0]) == [1, 2, 4]
-    for beta in (0.0, 0.25):
-        _, _, _, cell = shade.guided_proxy_rays(x, n, u, w, G, beta)
-        p, cdf = shade.guide_cdf(w, beta)
-        assert cdf[-1] == pytest.approx(1.0, abs=1e-12)
-        on = np.repeat(vis, G * G)
-        q = np.where(on, p, 0.0) / p[on].sum()
-        cnt = np.bincount(cell, minlength=p.size)
-        sd = np.sqrt(S * q * (1 - q))
-        assert np.all(np.abs(cnt - S * q) <= 5 * sd + 1e-9)
-        assert np.all(cnt[~on] == 0)
-        if beta == 0.0:
-            assert np.all(cnt[w == 0] == 0)
+    # points that see three faces: x > 1, y < -1, z < -1 (faces 1, 2, 4),
+    # the second with a normal that turns away from face 4's centre
+    for x, n in ((np.array([[2.5, -3.0, -1.7]], np.float32), np.array([[-1.0, 1.0, 1.0]], np.float32)),
+                 (np.array([[1.3, -2.2, -1.4]], np.float32), np.array([[0.0, -1.0, 3.0]], np.float32))):
+        vis = shade.visible_faces(x)[0]
+        assert list(np.nonzero(vis)[0]) == [1, 2, 4]
+        for beta in (0.0, 0.25):
+            _, _, _, cell = shade.guided_proxy_rays(x, n, u, w, G, beta)
+            p, cdf = shade.guide_cdf(w, beta)
+            assert cdf[-1] == pytest.approx(1.0, abs=1e-12)
+            P = p.reshape(6, G * G).sum(1)
+            Q = _face_choice(x[0], n[0], P, vis)
+            q = np.repeat(np.where(P > 0, Q / np.where(P > 0, P, 1), 0.0), G * G) * p
+            on = np.repeat(vis, G * G)
+            assert q.sum() == pytest.approx(1.0, abs=1e-12)
+            cnt = np.bincount(cell, minlength=p.size)
+            sd = np.sqrt(S * q * (1 - q))
+            assert np.all(np.abs(cnt - S * q) <= 5 * sd + 1e-9)
+            assert np.all(cnt[~on] == 0)
+            if beta == 0.0:
+                assert np.all(cnt[w == 0] == 0)
+
+
+def test_face_choice_keeps_a_defensive_share():
+    """A visible face whose centre lies behind the point's tangent plane
+    has geometry weight 0 yet keeps half its guide-mass share."""
+    x = np.array([1.3, -2.2, -1.4], np.float32)
+    n = np.array([0.0, -1.0, 3.0], np.float32)
+    assert shade.face_geometry(x, n, 4) == 0.0 and shade.face_geometry(x, n, 2) > 0.0
+    w = np.ones(shade.guide_cells(G), np.float32)
+    _, cdf = shade.guide_cdf(w, 0.0)
+    # face 4 is the last visible face: u0 just below 1 lands in it
+    cell, factor = shade.guided_cell(cdf, G, x, n, np.float32(0.9999))
+    assert cell // (G * G) == 4
+    # P_f = 1/6 on every face, P_vis = 1/2: Q_4 = 0.5 (1/6) / (1/2) = 1/6
+    assert factor == pytest.approx((1.0 / 6.0) / (1.0 / 6.0), rel=1e-12)
 
 
 @pytest.mark.parametrize("pose", range(len(POSES)))
