@@ -204,7 +204,18 @@ struct Event {
     float P, t;
 };
 
+// v[a] for an axis a in 0..2.  sel3 is the form for the rare exact paths
+// (the compiler branches on the axis there); sel3v reads the three values
+// first and selects among them, which compiles to two v_cndmask per pick
+// instead of a branch tree with exec-mask handling -- the form for the
+// segment length, computed for every composited leaf.  (Selecting among
+// v[0..2] by an index-like condition such as a > 1, or a & 2, makes the
+// compiler index the array instead: a stack copy in scratch memory.)
 LQ_HD inline float sel3(const float (&v)[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
+LQ_HD inline float sel3v(const float (&v)[3], int a) {
+    const float v0 = v[0], v1 = v[1], v2 = v[2];
+    return a == 2 ? v2 : (a == 1 ? v1 : v0);
+}
 
 LQ_HD inline float tapprox(const Ray &r, int a, float P) { return (P - sel3(r.o, a)) * sel3(r.inv, a); }
 
@@ -281,15 +292,15 @@ LQ_HD inline int locate(const Ray &r, int b, int lo, int hi, const Event &e, flo
 // t(x) - t(e) for the exit crossing x, with full relative precision
 LQ_HD inline float seg_dt(const Ray &r, const Event &e, int xa, float xP, float xt) {
     if (e.ax < 0) return xt;
-    if (e.ax == xa) return (xP - e.P) * sel3(r.inv, xa);
-    float dx = sel3(r.d, xa), de = sel3(r.d, e.ax);
+    if (e.ax == xa) return (xP - e.P) * sel3v(r.inv, xa);
+    float dx = sel3v(r.d, xa), de = sel3v(r.d, e.ax);
     float X1, X0, V1, V0;
-    two_sum_f(xP, -sel3(r.o, xa), X1, X0);
-    two_sum_f(e.P, -sel3(r.o, e.ax), V1, V0);
+    two_sum_f(xP, -sel3v(r.o, xa), X1, X0);
+    two_sum_f(e.P, -sel3v(r.o, e.ax), V1, V0);
     float p1 = X1 * de, p0 = fmaf(X1, de, -p1);
     float q1 = V1 * dx, q0 = fmaf(V1, dx, -q1);
     float num = (p1 - q1) + ((p0 - q0) + (X0 * de - V0 * dx));
-    return num * (sel3(r.inv, xa) * sel3(r.inv, e.ax));
+    return num * (sel3v(r.inv, xa) * sel3v(r.inv, e.ax));
 }
 
 LQ_HD inline uint32_t spread3(uint32_t v) {
