@@ -303,6 +303,18 @@ LQ_HD inline float seg_dt(const Ray &r, const Event &e, int xa, float xP, float 
     return num * (sel3v(r.inv, xa) * sel3v(r.inv, e.ax));
 }
 
+// child octant of cell q at bit sh: bit sh of x, y, z in bits 0, 1, 2
+LQ_HD inline int octant_at(const int (&q)[3], int sh) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const uint32_t b0 = __builtin_amdgcn_ubfe((uint32_t)q[0], (uint32_t)sh, 1u);
+    const uint32_t b1 = __builtin_amdgcn_ubfe((uint32_t)q[1], (uint32_t)sh, 1u);
+    const uint32_t b2 = __builtin_amdgcn_ubfe((uint32_t)q[2], (uint32_t)sh, 1u);
+    return (int)(b0 | (b1 << 1) | (b2 << 2));
+#else
+    return ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
+#endif
+}
+
 LQ_HD inline uint32_t spread3(uint32_t v) {
     v &= 0x3FFu;
     v = (v | (v << 16)) & 0x030000FFu;
@@ -519,7 +531,7 @@ struct Marcher {
         while (descend) {
             path[level * path_stride] = node;
             int sh = D - 1 - level;
-            int oct = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
+            const int oct = octant_at(q, sh);
             c = child[(uint32_t)node * 8u + (uint32_t)oct];   // n_nodes < 2^29 (checked at load)
             ++level;
             if (c <= 0 || level >= D) break;
