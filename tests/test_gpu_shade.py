@@ -214,12 +214,13 @@ def test_guided_irradiance_parity(lq, c0_tree, which, model, beta):
            E.cpu().numpy().astype(np.float64), orc=orc)
 
 
-@pytest.mark.parametrize("G", [1, 40])
+@pytest.mark.parametrize("G", [1, 40, 256])
 @pytest.mark.parametrize("beta", [0.0, 0.25])
 def test_guided_grid_sizes(lq, c0_tree, G, beta):
-    """The smallest guide (one cell per face) and one of 9,600 cells, more
-    than one LDS chunk of the cell table (2,048 cells): the guided estimator
-    against the oracle sample by sample and point by point."""
+    """The smallest guide (one cell per face), one of 9,600 cells (more
+    than one LDS chunk of the cell table, 2,048 cells) and the largest grid
+    the call accepts (256: 393,216 cells): the guided estimator against the
+    oracle sample by sample and point by point."""
     import torch
     pts, nrm = inputs.rays.scattered_points(300, 25)
     u = inputs.rays.sample_numbers(300, 32, 26)
