@@ -256,8 +256,8 @@ lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const 
  * luminances are summed in FP64 in probe order.
  *
  * lq_proxy_irradiance_guided: lq_proxy_irradiance with the sample's cell
- * drawn from the guide.  With W the sum of the weights (any non-negative
- * finite values), cell k has probability
+ * drawn from the guide.  With W the sum of the weights (a weight that is
+ * negative, NaN or infinite counts as 0), cell k has probability
  *     p_k = (1 - defensive) w_k / W + defensive / (6 grid^2)
  * (1 / (6 grid^2) each when W = 0), summed in cell order in FP64 into
  * cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.  A point receives light only

@@ -28,6 +28,8 @@ component; the weight and the sum are FP64.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from . import core
@@ -159,8 +161,9 @@ def guide_weights(tree, G, u_probe, model: int = core.LINEAR, storage: str = "f3
 def guide_cdf(weights, beta):
     """Cell probabilities and their cumulative sums in FP64, summed in cell
     order: W = w_0 + w_1 + ..., p_k = (1 - beta) (w_k / W) + beta / n (all
-    1 / n when W = 0), cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k."""
-    w = [float(v) for v in np.asarray(weights, np.float32)]
+    1 / n when W = 0), cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.  A weight
+    that is negative, NaN or infinite counts as 0."""
+    w = [float(v) if (v > 0 and math.isfinite(v)) else 0.0 for v in np.asarray(weights, np.float32)]
     n = len(w)
     W = 0.0
     for v in w:

@@ -269,6 +269,10 @@ __global__ void k_guide_reduce(const float *rgb, int R, int n_cells, float *weig
 constexpr int kCdfBlock = 256;
 constexpr int kCdfChunk = 2048;   // cells staged in LDS at a time
 
+// a cell's weight as the table uses it: negative, NaN and infinite weights
+// count as 0
+__device__ inline double guide_weight(float w) { return w > 0.0f && w < INFINITY ? (double)w : 0.0; }
+
 __global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, int n, double beta, double *prob,
                                                          double *cdf) {
     __shared__ double s_v[kCdfChunk];
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, i
     double W = 0.0;   // thread 0 only
     for (int c0 = 0; c0 < n; c0 += kCdfChunk) {
         const int m = min(kCdfChunk, n - c0);
-        for (int i = t; i < m; i += kCdfBlock) s_v[i] = (double)weights[c0 + i];
+        for (int i = t; i < m; i += kCdfBlock) s_v[i] = guide_weight(weights[c0 + i]);
         __syncthreads();
         if (t == 0)
             for (int i = 0; i < m; ++i) W += s_v[i];
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, i
     for (int c0 = 0; c0 < n; c0 += kCdfChunk) {
         const int m = min(kCdfChunk, n - c0);
         for (int i = t; i < m; i += kCdfBlock) {
-            const double p = W > 0.0 ? (1.0 - beta) * ((double)weights[c0 + i] / W) + beta / n : 1.0 / n;
+            const double p = W > 0.0 ? (1.0 - beta) * (guide_weight(weights[c0 + i]) / W) + beta / n : 1.0 / n;
             prob[c0 + i] = p;
             s_v[i] = p;
         }

@@ -236,6 +236,25 @@ def test_guided_grid_sizes(lq, c0_tree, G, beta):
            E.cpu().numpy().astype(np.float64), orc=orc)
 
 
+def test_guided_invalid_weights(lq, c0_tree):
+    """Negative, NaN and infinite guide weights count as 0 on both sides."""
+    import torch
+    G = 8
+    pts, nrm = inputs.rays.scattered_points(200, 28)
+    u = inputs.rays.sample_numbers(200, 32, 29)
+    w = inputs.rays.guide_weights(shade.guide_cells(G), 30)
+    w[[3, 50, 77, 200, 301]] = [-1.0, np.nan, np.inf, -np.inf, -0.0]
+    B = (0.2, 0.5, 1.0)
+    _say("guided proxy irradiance with invalid guide weights")
+    oct_ = lq.Octree(c0_tree, "f32")
+    E, terms = oct_.proxy_irradiance_guided(_dev(pts), _dev(nrm), _dev(u), _dev(w), G, defensive=0.1,
+                                            background=B, want_terms=True)
+    torch.cuda.synchronize()
+    orc = shade.proxy_irradiance_guided(c0_tree, pts, nrm, u, w, G, 0.1, background=B)
+    _check(c0_tree, pts, nrm, u, B, "linear", terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64), orc=orc)
+
+
 def test_guided_sampling_reduces_variance(lq, c0_tree):
     """On the floor below the luminaire, with the guide built on the GPU
     from probe rays: the guided and uniform estimates agree within their

@@ -260,6 +260,24 @@ def test_guided_estimate_is_unbiased(pose):
     assert np.all(np.abs(r["E"][0] - B * ref) < 5 * se + 1e-12), (r["E"][0], B * ref, se)
 
 
+def test_invalid_weights_count_as_zero():
+    """Negative, NaN and infinite weights take no share of the guide: the
+    table equals the one with those weights set to 0, and a guide of only
+    such weights is the uniform one."""
+    w = _random_guide(5)
+    bad = w.copy()
+    k = np.flatnonzero(w > 0)[:4]
+    bad[k] = [-1.0, np.nan, np.inf, -np.inf]
+    ref = w.copy()
+    ref[k] = 0.0
+    for beta in (0.0, 0.3):
+        p, cdf = shade.guide_cdf(bad, beta)
+        p0, cdf0 = shade.guide_cdf(ref, beta)
+        assert np.array_equal(p, p0) and np.array_equal(cdf, cdf0)
+    p, _ = shade.guide_cdf(np.full(shade.guide_cells(G), np.nan, np.float32), 0.0)
+    assert np.allclose(p, 1.0 / p.size)
+
+
 def test_guide_of_an_opaque_uniform_luminaire():
     """Every probe of an opaque uniform luminaire sees its emission Phi, so
     every cell's guide weight is Phi's luminance (channel mean)."""
