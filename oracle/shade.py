@@ -106,9 +106,14 @@ def proxy_irradiance(tree, points, normals, u, background=(0.0, 0.0, 0.0), model
 # receives light through the faces it sees from the front (sgn x_axis > 1);
 # the others contribute exactly zero, so a sample of x picks among the cells
 # of those faces only, with probability p_k / P_vis(x) (P_vis the sum of
-# p over them), and a uniform point in the cell: its area density is
-# p_k / (P_vis A_cell) with A_cell = (2 / G)^2.  The estimate is unbiased
+# p over them), and a uniform point in the cell.  The estimate is unbiased
 # whenever every cell of a visible face has p_k > 0 (beta > 0 ensures it).
+# With D > 1 direction bins the guide is directional: each probe also falls
+# in one of D x D bins of its outward direction (the light it measures
+# leaves the cell along -d) on the face's two tangent axes, a cell has one
+# weight per bin, and each bin its own table; a shading point uses, on
+# every face it sees, the bin of its own direction from the face's centre
+# (face f's table is cdf[b_f(x)]).
 
 def guide_cells(G):
     return 6 * G * G
@@ -148,14 +153,74 @@ def guide_probe_rays(G, u_probe):
     return y, d
 
 
-def guide_weights(tree, G, u_probe, model: int = core.LINEAR, storage: str = "f32"):
-    """Mean probe luminance per cell (float64), and the oracle's query
+def direction_bin(v, l2, D):
+    """Tangent bin 0..D-1 of a direction whose component on a tangent axis
+    is v and whose squared length is l2: the number of thresholds
+    theta_j = 2 j / D - 1 (j = 1..D-1) with v / sqrt(l2) >= theta_j, decided
+    on squares (FP64) so that no square root enters the decision.  v and l2
+    are FP64 arrays (or scalars)."""
+    if isinstance(v, float) and isinstance(l2, float):   # one direction: plain floats, the same operations
+        i = 0
+        for j in range(1, D):
+            th = (2.0 * j) / D - 1.0
+            if th < 0.0:
+                ok = v >= 0.0 or v * v <= (th * th) * l2
+            elif th == 0.0:
+                ok = v >= 0.0
+            else:
+                ok = v >= 0.0 and v * v >= (th * th) * l2
+            i = j if ok else i
+        return i
+    v = np.asarray(v, np.float64)
+    l2 = np.asarray(l2, np.float64)
+    i = np.zeros(np.broadcast(v, l2).shape, np.int64)
+    for j in range(1, D):
+        th = (2.0 * j) / D - 1.0
+        if th < 0.0:
+            ok = (v >= 0.0) | (v * v <= (th * th) * l2)
+        elif th == 0.0:
+            ok = v >= 0.0
+        else:
+            ok = (v >= 0.0) & (v * v >= (th * th) * l2)
+        i = np.where(ok, j, i)
+    return i
+
+
+def face_direction_bin(face, w, D):
+    """Bin i1 D + i2 of an outward direction w [m, 3] (FP64 values) through
+    face `face`: i1, i2 the tangent bins of its components on the face's
+    next two axes (cyclic); the squared length summed in axis order."""
+    w = np.asarray(w, np.float64).reshape(-1, 3)
+    face = np.broadcast_to(np.asarray(face, np.int64), (w.shape[0],))
+    a = face >> 1
+    rows = np.arange(w.shape[0])
+    l2 = w[:, 0] * w[:, 0] + w[:, 1] * w[:, 1] + w[:, 2] * w[:, 2]
+    return direction_bin(w[rows, (a + 1) % 3], l2, D) * D + direction_bin(w[rows, (a + 2) % 3], l2, D)
+
+
+def guide_weights(tree, G, u_probe, model: int = core.LINEAR, storage: str = "f32", D: int = 1):
+    """Guide weights [6 G^2 * D^2], cell-major: the mean probe luminance of
+    each cell (D = 1), or per direction bin of the probes' outward
+    direction -d (FP64 sums in probe order; a bin no probe of the cell fell
+    in takes the cell's mean over all its probes); and the oracle's query
     output on the probes (for candidate checks)."""
     o, d = guide_probe_rays(G, u_probe)
     q = core.query(tree, o, d, model=model, storage=storage)
     R = np.asarray(u_probe).shape[1]
-    lum = q["L"].mean(1).reshape(-1, R)
-    return lum.mean(1), q
+    n = guide_cells(G)
+    lum = q["L"].mean(1)
+    if D == 1:
+        return lum.reshape(-1, R).mean(1), q
+    cell = np.repeat(np.arange(n), R)
+    b = face_direction_bin(cell // (G * G), -d.astype(np.float64), D)
+    s = np.zeros((n, D * D))
+    c = np.zeros((n, D * D))
+    np.add.at(s, (cell, b), lum)
+    np.add.at(c, (cell, b), 1.0)
+    tot = np.zeros(n)
+    np.add.at(tot, cell, lum)
+    w = np.where(c > 0, s / np.where(c > 0, c, 1.0), (tot / R)[:, None])
+    return w.reshape(-1), q
 
 
 def guide_cdf(weights, beta):
@@ -176,6 +241,14 @@ def guide_cdf(weights, beta):
     for k in range(n):
         cdf[k + 1] = cdf[k] + p[k]
     return np.array(p), np.array(cdf)
+
+
+def guide_tables(weights, beta, D):
+    """One table per direction bin: (p [D^2, n], cdf [D^2, n + 1]), bin b
+    from the weights w[k D^2 + b] by guide_cdf."""
+    w = np.asarray(weights, np.float32).reshape(-1, D * D)
+    pc = [guide_cdf(w[:, b], beta) for b in range(D * D)]
+    return np.array([x[0] for x in pc]), np.array([x[1] for x in pc])
 
 
 def visible_faces(x):
@@ -208,32 +281,45 @@ def face_geometry(x, n, f):
     return (ndot * h) / (r2 * r2) if ndot > 0.0 else 0.0
 
 
-def guided_cell(cdf, G, x, n, u0):
-    """The cell a sample picks.  The point sees faces vis (side x_axis > 1);
-    P_f = cdf[(f + 1) G^2] - cdf[f G^2] is face f's guide mass, P_vis their
-    sum over the visible faces, g_f = face_geometry and S = sum of P_f g_f
-    over them.  Face f is chosen with probability
+def guided_cell(cdf, G, x, n, u0, D=1):
+    """The cell a sample picks.  cdf [D^2, 6 G^2 + 1]: the tables of the
+    direction bins (guide_tables).  The point sees faces vis (side
+    x_axis > 1); on face f it uses table b_f, the bin of its direction
+    x - c_f from the face's centre (face_direction_bin), with guide mass
+    P_f = cdf[b_f][(f + 1) G^2] - cdf[b_f][f G^2]; P_vis is their sum over
+    the visible faces, g_f = face_geometry and S = sum of P_f g_f.  Face f
+    is chosen with probability
         Q_f = FACE_MIX P_f g_f / S + (1 - FACE_MIX) P_f / P_vis
     (P_f / P_vis when S = 0): t = u0 walks the visible faces in order, and
     in the face where t < Q_f (the last visible face takes any remainder)
-    the cell is the largest k of the face with cdf[k] <= cdf[f G^2] + r P_f,
-    r = t / Q_f (0 when Q_f = 0).  Returns (cell, Q_f / P_f): the cell's
-    area density is p_k (Q_f / P_f) / A_cell.  Cell -1 when no face is
-    visible or P_vis = 0."""
+    the cell is the largest k of the face with
+    cdf[b_f][k] <= cdf[b_f][f G^2] + r P_f, r = t / Q_f (0 when Q_f = 0).
+    Returns (cell, b_f, Q_f / P_f): the cell's area density is
+    p[b_f][k] (Q_f / P_f) / A_cell.  Cell -1 when no face is visible or
+    P_vis = 0."""
     gg = G * G
+    cdf = np.asarray(cdf).reshape(D * D, -1)
     xs = np.asarray(x, np.float32)
     vis = visible_faces(xs)[0]
-    P = [cdf[(f + 1) * gg] - cdf[f * gg] for f in range(6)]
+    xd = xs.astype(np.float64)
+    bins = [0] * 6
+    P = [0.0] * 6
     pv = 0.0
     gs = 0.0
     g = [0.0] * 6
     for f in range(6):
         if vis[f]:
+            a, sgn = f >> 1, (1.0 if f & 1 else -1.0)
+            w = [float(xd[k]) - (sgn if k == a else 0.0) for k in range(3)]
+            l2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2]
+            bins[f] = direction_bin(w[(a + 1) % 3], l2, D) * D + direction_bin(w[(a + 2) % 3], l2, D)
+            c = cdf[bins[f]]
+            P[f] = c[(f + 1) * gg] - c[f * gg]
             g[f] = face_geometry(xs, n, f)
             pv += P[f]
             gs += P[f] * g[f]
     if not pv > 0.0:
-        return -1, 0.0
+        return -1, 0, 0.0
     Q = [0.0] * 6
     for f in range(6):
         if vis[f]:
@@ -244,25 +330,27 @@ def guided_cell(cdf, G, x, n, u0):
         if not vis[f]:
             continue
         if t < Q[f] or f == last:
+            c = cdf[bins[f]]
             r = t / Q[f] if Q[f] > 0.0 else 0.0
-            target = cdf[f * gg] + r * P[f]
+            target = c[f * gg] + r * P[f]
             lo, hi = f * gg, f * gg + gg - 1
             while lo < hi:
                 mid = (lo + hi + 1) // 2
-                if cdf[mid] <= target:
+                if c[mid] <= target:
                     lo = mid
                 else:
                     hi = mid - 1
-            return lo, (Q[f] / P[f] if P[f] > 0.0 else 0.0)
+            return lo, bins[f], (Q[f] / P[f] if P[f] > 0.0 else 0.0)
         t -= Q[f]
-    return -1, 0.0
+    return -1, 0, 0.0
 
 
-def guided_proxy_rays(points, normals, u, weights, G, beta):
+def guided_proxy_rays(points, normals, u, weights, G, beta, D=1):
     """Rays and weights of guided samples: u [n, S, 3]: u0 picks the cell
     among the faces the point sees (guided_cell), u1, u2 the point in it.
-    The Monte Carlo weight is cos(theta_x) cos(theta_y) / (|y - x|^2 p_A)
-    with p_A = p_k (Q_f / P_f) / A_cell; zero below the horizon, and for a
+    weights [6 G^2 D^2], cell-major.  The Monte Carlo weight is
+    cos(theta_x) cos(theta_y) / (|y - x|^2 p_A) with
+    p_A = p[b_f][k] (Q_f / P_f) / A_cell; zero below the horizon, and for a
     point that sees no face."""
     x = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
     nrm32 = np.asarray(normals, np.float32).reshape(-1, 3)
@@ -270,12 +358,14 @@ def guided_proxy_rays(points, normals, u, weights, G, beta):
     u = np.ascontiguousarray(u, np.float32)
     n, S = u.shape[0], u.shape[1]
     u = u.reshape(n * S, 3)
-    p, cdf = guide_cdf(weights, beta)
+    p, cdf = guide_tables(weights, beta, D)
     cell = np.empty(n * S, np.int64)
+    cbin = np.zeros(n * S, np.int64)
     factor = np.zeros(n * S)
     for i in range(n):
         for j in range(S):
-            cell[i * S + j], factor[i * S + j] = guided_cell(cdf, G, x[i], nrm32[i], u[i * S + j, 0])
+            cell[i * S + j], cbin[i * S + j], factor[i * S + j] = guided_cell(cdf, G, x[i], nrm32[i],
+                                                                              u[i * S + j, 0], D)
     dead = cell < 0
     cell = np.where(dead, 0, cell)
     y, face, axis, sgn = _cell_point(cell, u[:, 1], u[:, 2], G)
@@ -291,7 +381,7 @@ def guided_proxy_rays(points, normals, u, weights, G, beta):
     h = sgn.astype(np.float64) * xs.astype(np.float64)[rows, axis] - 1.0
     cos_y = h / np.where(dist > 0, dist, 1.0)
     area = (2.0 / G) ** 2
-    pa = np.where(dead, 0.0, p[cell] * factor / area)
+    pa = np.where(dead, 0.0, p[cbin, cell] * factor / area)
     ok = (h > 0) & (cos_x > 0) & (dist2 > 0) & (nlen > 0) & (pa > 0)
     w = np.where(ok, cos_x * cos_y / np.where(dist2 > 0, dist2, 1.0) / np.where(pa > 0, pa, 1.0), 0.0)
     d[~ok] = 0.0
@@ -299,12 +389,12 @@ def guided_proxy_rays(points, normals, u, weights, G, beta):
 
 
 def proxy_irradiance_guided(tree, points, normals, u, weights, G, beta, background=(0.0, 0.0, 0.0),
-                            model: int = core.LINEAR, storage: str = "f32") -> dict:
+                            model: int = core.LINEAR, storage: str = "f32", D: int = 1) -> dict:
     """The guided estimate per point (E [n, 3]) and its terms, as
     proxy_irradiance does for uniform sampling."""
     u = np.asarray(u, np.float32)
     n, S = u.shape[0], u.shape[1]
-    o, d, w, cell = guided_proxy_rays(points, normals, u, weights, G, beta)
+    o, d, w, cell = guided_proxy_rays(points, normals, u, weights, G, beta, D)
     q = core.query(tree, o, d, model=model, storage=storage)
     B = np.asarray(background, np.float64)[None, :]
     lo = q["L"] + (1.0 - q["alpha"])[:, None] * B

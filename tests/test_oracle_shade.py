@@ -229,7 +229,7 @@ def test_face_choice_keeps_a_defensive_share():
     w = np.ones(shade.guide_cells(G), np.float32)
     _, cdf = shade.guide_cdf(w, 0.0)
     # face 4 is the last visible face: u0 just below 1 lands in it
-    cell, factor = shade.guided_cell(cdf, G, x, n, np.float32(0.9999))
+    cell, _, factor = shade.guided_cell(cdf, G, x, n, np.float32(0.9999))
     assert cell // (G * G) == 4
     # P_f = 1/6 on every face, P_vis = 1/2: Q_4 = 0.5 (1/6) / (1/2) = 1/6
     assert factor == pytest.approx((1.0 / 6.0) / (1.0 / 6.0), rel=1e-12)
@@ -276,6 +276,107 @@ def test_invalid_weights_count_as_zero():
         assert np.array_equal(p, p0) and np.array_equal(cdf, cdf0)
     p, _ = shade.guide_cdf(np.full(shade.guide_cells(G), np.nan, np.float32), 0.0)
     assert np.allclose(p, 1.0 / p.size)
+
+
+def _bin_by_normalising(v, l2, D):
+    """The tangent bin from its definition with the square root taken."""
+    return np.clip(np.floor((v / np.sqrt(l2) + 1.0) * 0.5 * D), 0, D - 1).astype(np.int64)
+
+
+def test_direction_bins():
+    """Bins decided on squares against bins of the normalised component,
+    away from the thresholds; thresholds that a direction meets exactly
+    (components 1, 2, 2: 1/3 of its length) count as passed."""
+    rng = np.random.default_rng(7)
+    w = rng.normal(size=(20000, 3)).astype(np.float32).astype(np.float64)
+    l2 = (w * w).sum(1)
+    for D in (2, 3, 4):
+        c = w[:, 0] / np.sqrt(l2)
+        th = 2.0 * np.arange(1, D) / D - 1.0
+        away = np.min(np.abs(c[:, None] - th[None, :]), axis=1) > 1e-9
+        got = shade.direction_bin(w[:, 0], l2, D)
+        assert np.array_equal(got[away], _bin_by_normalising(w[away, 0], l2[away], D))
+    assert shade.direction_bin(0.0, 1.0, 2) == 1
+    # one direction (plain floats) and arrays take the same decisions
+    for D in (2, 3, 4):
+        got = shade.direction_bin(w[:500, 1], l2[:500], D)
+        assert all(shade.direction_bin(float(a), float(b), D) == g for a, b, g in zip(w[:500, 1], l2[:500], got))
+    assert shade.direction_bin(1.0, 9.0, 3) == 2 and shade.direction_bin(-1.0, 9.0, 3) == 1
+    # face 4 (z = -1): tangent axes x then y; (3, 0, -4) / 5 has x component 0.6
+    assert shade.face_direction_bin(4, np.array([[3.0, 0.0, -4.0]]), 4)[0] == 3 * 4 + 2
+
+
+def _random_directional_guide(seed, D):
+    rng = np.random.default_rng(seed)
+    w = rng.exponential(1.0, shade.guide_cells(G) * D * D).astype(np.float32)
+    w[rng.random(w.size) < 0.3] = 0.0
+    return w
+
+
+def test_directional_cell_frequencies():
+    """With D x D direction bins, cells are picked with probability
+    Q_f p[b_f][k] / P_f, b_f the bin of the point's direction from face f's
+    centre (computed here with the square root), Q_f as in the
+    direction-averaged case from the bins' face masses."""
+    D = 2
+    w = _random_directional_guide(13, D)
+    S = 100_000
+    u = inputs.rays.sample_numbers(1, S, 27)
+    x = np.array([[2.5, -3.0, -1.7]], np.float32)
+    n = np.array([[-1.0, 1.0, 1.0]], np.float32)
+    vis = shade.visible_faces(x)[0]
+    centres = np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0], [0, 0, -1], [0, 0, 1]], np.float64)
+    for beta in (0.0, 0.25):
+        _, _, _, cell = shade.guided_proxy_rays(x, n, u, w, G, beta, D)
+        p, cdf = shade.guide_tables(w, beta, D)
+        gg = G * G
+        P = np.zeros(6)
+        pk = np.zeros(p.shape[1])
+        for f in np.nonzero(vis)[0]:
+            a = f >> 1
+            dvec = x[0].astype(np.float64) - centres[f]
+            l2 = (dvec * dvec).sum()
+            b = _bin_by_normalising(dvec[(a + 1) % 3], l2, D) * D + _bin_by_normalising(dvec[(a + 2) % 3], l2, D)
+            P[f] = p[b, f * gg:(f + 1) * gg].sum()
+            pk[f * gg:(f + 1) * gg] = p[b, f * gg:(f + 1) * gg]
+        Q = _face_choice(x[0], n[0], P, vis)
+        q = np.repeat(np.where(P > 0, Q / np.where(P > 0, P, 1), 0.0), gg) * pk
+        assert q.sum() == pytest.approx(1.0, abs=1e-12)
+        cnt = np.bincount(cell, minlength=q.size)
+        sd = np.sqrt(S * q * (1 - q))
+        assert np.all(np.abs(cnt - S * q) <= 5 * sd + 1e-9)
+
+
+@pytest.mark.parametrize("pose", range(len(POSES)))
+def test_directional_guided_estimate_is_unbiased(pose):
+    """The estimator with a 3 x 3 directional guide against Lambert's closed
+    form for an opaque uniform luminaire, within 5 standard errors."""
+    D = 3
+    x, n = POSES[pose]
+    ref = _box_projected_solid_angle(x, n)
+    w = _random_directional_guide(30 + pose, D)
+    S = 100_000
+    u = inputs.rays.sample_numbers(1, S, 70 + pose)
+    c = np.array([[-1.0], [0.5], [2.0]])
+    tree = inputs.uniform_tree(2, 1e6, c)
+    phi = inputs.L_MAX / (1.0 + np.exp(-c[:, 0].astype(np.float32).astype(np.float64) * Y00))
+    r = shade.proxy_irradiance_guided(tree, np.array([x], np.float32), np.array([n], np.float32), u, w, G, 0.2,
+                                      D=D)
+    se = r["terms"][0].std(axis=0) / math.sqrt(S)
+    assert np.all(np.abs(r["E"][0] - phi * ref) < 5 * se + 1e-9), (r["E"][0], phi * ref, se)
+
+
+def test_directional_guide_of_an_opaque_uniform_luminaire():
+    """Every probe of an opaque uniform luminaire sees Phi, so every
+    (cell, direction bin) weight is Phi's luminance, including bins no
+    probe fell in (they take the cell's mean)."""
+    c = np.array([[-1.0], [0.5], [2.0]])
+    tree = inputs.uniform_tree(2, 1e6, c)
+    phi = inputs.L_MAX / (1.0 + np.exp(-c[:, 0].astype(np.float32).astype(np.float64) * Y00))
+    u = inputs.rays.probe_numbers(shade.guide_cells(4), 8, 25)
+    wts, _ = shade.guide_weights(tree, 4, u, D=3)
+    assert wts.shape == (shade.guide_cells(4) * 9,)
+    assert np.allclose(wts, phi.mean(), rtol=1e-9)
 
 
 def test_guide_of_an_opaque_uniform_luminaire():
