@@ -246,48 +246,65 @@ lq_status lq_proxy_irradiance(const lq_octree *tree, const float *points, const 
  * cells on it along the face's next two axes in cyclic order, cell
  * k = (f grid + i) grid + j.
  *
- * lq_proxy_guide: the guide weight of every cell, the mean luminance (mean
- * of R, G, B) of the emission that lq_query_radiance returns for n_probes
- * probe rays per cell.  Probe r of cell k reads u_probe[k][r][0..4] in
- * [0, 1): it starts at the cell's point with coordinates
- * -1 + (i + u0) 2 / grid and -1 + (j + u1) 2 / grid (float32) and aims at
- * the point 2 (u2, u3, u4) - 1 inside the box.  weights [6 grid^2] float32,
- * u_probe [6 grid^2][n_probes][5] float32: device arrays.  The probe
- * luminances are summed in FP64 in probe order.
+ * Direction bins: with dir_res = D > 1 the guide is directional.  An
+ * outward direction w through face f (axis a) falls in bin i1 D + i2,
+ * where i1 and i2 are the tangent bins of its components on axes a + 1 and
+ * a + 2 (cyclic).  The tangent bin of a component v, with l2 = |w|^2
+ * summed in axis order, is the number of thresholds th_j = 2 j / D - 1
+ * (j = 1..D-1) that v / sqrt(l2) reaches.  Each test is decided on
+ * squares in FP64: for th < 0, v >= 0 or v^2 <= th^2 l2; for th = 0,
+ * v >= 0; for th > 0, v >= 0 and v^2 >= th^2 l2.  dir_res in 1..4.
+ *
+ * lq_proxy_guide: the guide weights, D^2 per cell (cell-major, weight
+ * k D^2 + b).  Weight (k, b) is the mean luminance (mean of R, G, B) of
+ * the emission that lq_query_radiance returns for those of the cell's
+ * n_probes probe rays whose outward direction -d falls in bin b.  A bin
+ * that none of them fell in takes the mean over all the cell's probes
+ * (D = 1: that mean alone).  Probe r of cell k reads
+ * u_probe[k][r][0..4] in [0, 1): it starts at the cell's point with
+ * coordinates -1 + (i + u0) 2 / grid and -1 + (j + u1) 2 / grid (float32)
+ * and aims at the point 2 (u2, u3, u4) - 1 inside the box.
+ * weights [6 grid^2 D^2] float32, u_probe [6 grid^2][n_probes][5]
+ * float32: device arrays.  The probe luminances are summed in FP64 in probe
+ * order.
  *
  * lq_proxy_irradiance_guided: lq_proxy_irradiance with the sample's cell
- * drawn from the guide.  With W the sum of the weights (a weight that is
- * negative, NaN or infinite counts as 0), cell k has probability
- *     p_k = (1 - defensive) w_k / W + defensive / (6 grid^2)
- * (1 / (6 grid^2) each when W = 0), summed in cell order in FP64 into
- * cdf[0] = 0, cdf[k + 1] = cdf[k] + p_k.  A point receives light only
- * through the faces it sees from the front (side * x_axis > 1), so its
- * samples pick among those faces' cells.  Face f has guide mass
- * P_f = cdf[(f + 1) grid^2] - cdf[f grid^2] and, with c_f its centre
- * (side on its axis, 0 on the others), the geometry weight
+ * drawn from the guide, weights [6 grid^2 D^2] as lq_proxy_guide writes
+ * them.  Each direction bin b has its own table.  With W_b the sum of the
+ * bin's weights (a weight that is negative, NaN or infinite counts as 0),
+ * cell k has probability
+ *     p_b[k] = (1 - defensive) w_(k,b) / W_b + defensive / (6 grid^2)
+ * (1 / (6 grid^2) each when W_b = 0), summed in cell order in FP64 into
+ * cdf_b[0] = 0, cdf_b[k + 1] = cdf_b[k] + p_b[k].  A point receives light
+ * only through the faces it sees from the front (side * x_axis > 1), so
+ * its samples pick among those faces' cells.  On face f it uses the table
+ * of b_f, the bin of its direction x - c_f from the face's centre c_f
+ * (side on the face's axis, 0 on the others).  The face's guide mass is
+ * P_f = cdf_b_f[(f + 1) grid^2] - cdf_b_f[f grid^2], and its geometry
+ * weight is
  *     g_f = max(0, n.(c_f - x)) (side x_axis - 1) / |c_f - x|^4,
  * the integrand cos(theta_x) cos(theta_y) / r^2 at c_f up to the constant
  * 1 / |n|.  With P_vis and S the sums of P_f and P_f g_f over the visible
  * faces, face f is chosen with probability
- *     Q_f = 0.5 P_f g_f / S + 0.5 P_f / P_vis   (P_f / P_vis when S = 0):
- * sample s of point i walks the visible faces in order with t = u[i][s][0];
- * in the face where t < Q_f (the last visible face takes any remainder) it
- * picks the largest cell k of the face with
- * cdf[k] <= cdf[f grid^2] + (t / Q_f) P_f (t / Q_f taken as 0 when
- * Q_f = 0), and the point of that cell at
- * u[i][s][1], u[i][s][2] as above.  All of the choice is FP64 from the
- * float32 inputs, sums in axis and face order.  The sample's area density
- * is p_k (Q_f / P_f) / (2 / grid)^2, and its term L_o cos(theta_x)
- * cos(theta_y) / (|y - x|^2 p_A) (zero as in lq_proxy_irradiance, for a
- * point that sees no face, and for a cell of p_k Q_f = 0).  The estimate stays
- * unbiased for any guide with defensive > 0; defensive in [0, 1], grid in
- * 1..256.  Scratch: as lq_proxy_irradiance plus 8 (12 grid^2 + 1) bytes.
+ *     Q_f = 0.5 P_f g_f / S + 0.5 P_f / P_vis   (P_f / P_vis when S = 0).
+ * Sample s of point i walks the visible faces in order with
+ * t = u[i][s][0].  In the face where t < Q_f (the last visible face takes
+ * any remainder) it picks the largest cell k of the face with
+ * cdf_b_f[k] <= cdf_b_f[f grid^2] + (t / Q_f) P_f (t / Q_f taken as 0 when
+ * Q_f = 0), and the point of that cell at u[i][s][1], u[i][s][2] as above.
+ * All of the choice is FP64 from the float32 inputs, sums in axis and face
+ * order.  The sample's area density is p_b_f[k] (Q_f / P_f) / (2 / grid)^2,
+ * and its term L_o cos(theta_x) cos(theta_y) / (|y - x|^2 p_A) (zero as in
+ * lq_proxy_irradiance, for a point that sees no face, and for a cell of
+ * p_b_f[k] Q_f = 0).  The estimate stays unbiased for any guide with
+ * defensive > 0; defensive in [0, 1], grid in 1..256.  Scratch: as
+ * lq_proxy_irradiance plus 8 D^2 (12 grid^2 + 1) bytes.
  */
-lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t n_probes, const float *u_probe,
-                         int model, float *weights, void *hip_stream);
+lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t dir_res, int32_t n_probes,
+                         const float *u_probe, int model, float *weights, void *hip_stream);
 lq_status lq_proxy_irradiance_guided(const lq_octree *tree, const float *points, const float *normals,
                                      int64_t n_points, const float *u, int32_t n_samples,
-                                     const float *weights, int32_t grid, float defensive,
+                                     const float *weights, int32_t grid, int32_t dir_res, float defensive,
                                      const float *background_rgb, int model, float *irradiance,
                                      float *sample_terms, void *hip_stream);
 

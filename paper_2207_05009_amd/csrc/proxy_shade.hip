@@ -55,48 +55,84 @@ constexpr int kAimCells = 6 * kCellsPerSide * kCellsPerSide;
 // cdf[f G^2] + t (FP64, in the order the table was summed); u1, u2 give
 // the point in the cell, and the area density is p_k / (P_vis A_cell).
 struct Guide {
-    const double *cdf;    // [n_cells + 1], or null: uniform sampling
-    const double *prob;   // [n_cells]
-    int G, n_cells;
+    const double *cdf;    // [D^2][n_cells + 1], or null: uniform sampling
+    const double *prob;   // [D^2][n_cells]
+    int G, n_cells, D;    // D x D direction bins per cell
     float step;           // 2 / G (float32)
     double area;          // (2 / G)^2
 };
 
+// Tangent bin 0..D-1 of a direction with tangent component v and squared
+// length l2: the number of thresholds 2 j / D - 1 (j = 1..D-1) that
+// v / sqrt(l2) reaches, decided on squares in FP64 (no square root).
+__device__ inline int direction_bin(double v, double l2, int D) {
+    int i = 0;
+    for (int j = 1; j < D; ++j) {
+        const double th = (2.0 * j) / D - 1.0;
+        bool ok;
+        if (th < 0.0) ok = v >= 0.0 || v * v <= (th * th) * l2;
+        else if (th == 0.0) ok = v >= 0.0;
+        else ok = v >= 0.0 && v * v >= (th * th) * l2;
+        i = ok ? j : i;
+    }
+    return i;
+}
+
+// Bin i1 D + i2 of an outward direction w through a face of axis a: i1, i2
+// the tangent bins of its components on axes a + 1 and a + 2 (cyclic); the
+// squared length summed in axis order.
+__device__ inline int face_direction_bin(int a, double w0, double w1, double w2, int D) {
+    const double l2 = w0 * w0 + w1 * w1 + w2 * w2;
+    const double t1 = a == 0 ? w1 : (a == 1 ? w2 : w0);
+    const double t2 = a == 0 ? w2 : (a == 1 ? w0 : w1);
+    return direction_bin(t1, l2, D) * D + direction_bin(t2, l2, D);
+}
+
 constexpr double kFaceMix = 0.5;   // share of the face choice weighted by the face-centre geometry
 
 // Picks the cell of a guided sample.  The point x (normal n) sees the faces
-// with side * x_axis > 1; P_f is face f's guide mass, P_vis their sum,
+// with side * x_axis > 1.  On face f it uses table b_f, the direction bin
+// of x - c_f (c_f the face's centre); P_f = cdf_b_f[(f + 1) G^2] -
+// cdf_b_f[f G^2] is the face's guide mass, P_vis their sum,
 // g_f = max(0, n.(c_f - x)) (side x_axis - 1) / |c_f - x|^4 the irradiance
-// integrand cos cos / r^2 at the face centre c_f (up to the constant 1/|n|)
+// integrand cos cos / r^2 at the face centre (up to the constant 1/|n|)
 // and S the sum of P_f g_f.  Face f is taken with probability
 // Q_f = kFaceMix P_f g_f / S + (1 - kFaceMix) P_f / P_vis (P_f / P_vis when
-// S = 0), the cell within it by inverting the guide CDF.  All of it in FP64
+// S = 0), the cell within it by inverting its table.  All of it in FP64
 // from the float32 inputs, sums in axis and face order, so that the choice
 // is reproducible bit for bit.  Returns the cell (-1 when no face is visible
-// or P_vis = 0) and Q_f / P_f in `factor`: the sample's area density is
-// p_k factor / A_cell.
+// or P_vis = 0), its table in `bin` and Q_f / P_f in `factor`: the
+// sample's area density is prob_bin[k] factor / A_cell.
 __device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, float n0, float n1, float n2,
-                                 float u0, double &factor) {
+                                 float u0, int &bin, double &factor) {
     const int gg = g.G * g.G;
+    const int stride = g.n_cells + 1;
     const double xd[3] = {(double)x0, (double)x1, (double)x2};
     const double nd[3] = {(double)n0, (double)n1, (double)n2};
     bool vis[6];
+    int fb[6];
     double P[6], Q[6], gf[6];
     double pv = 0.0, gs = 0.0;
     int last = -1;
     factor = 0.0;
+    bin = 0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int ax = f >> 1;
         const float xa = ax == 0 ? x0 : (ax == 1 ? x1 : x2);
         vis[f] = ((f & 1) ? xa : -xa) > 1.0f;
-        P[f] = g.cdf[(f + 1) * gg] - g.cdf[f * gg];
+        P[f] = 0.0;
         gf[f] = 0.0;
+        fb[f] = 0;
         if (vis[f]) {
             const double sg = (f & 1) ? 1.0 : -1.0;
             double d[3];
 #pragma unroll
             for (int b = 0; b < 3; ++b) d[b] = (b == ax ? sg : 0.0) - xd[b];
+            // the outward direction x - c_f is -d
+            fb[f] = g.D > 1 ? face_direction_bin(ax, -d[0], -d[1], -d[2], g.D) : 0;
+            const double *c = g.cdf + (size_t)fb[f] * stride;
+            P[f] = c[(f + 1) * gg] - c[f * gg];
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             const double ndot = nd[0] * d[0] + nd[1] * d[1] + nd[2] * d[2];
             const double h = sg * xd[ax] - 1.0;
@@ -115,15 +151,17 @@ __device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, f
     for (int f = 0; f < 6; ++f) {
         if (!vis[f]) continue;
         if (t < Q[f] || f == last) {
+            const double *c = g.cdf + (size_t)fb[f] * stride;
             const double r = Q[f] > 0.0 ? t / Q[f] : 0.0;
-            const double target = g.cdf[f * gg] + r * P[f];
-            int lo = f * gg, hi = f * gg + gg - 1;   // cdf[lo] <= target holds for lo = f gg
+            const double target = c[f * gg] + r * P[f];
+            int lo = f * gg, hi = f * gg + gg - 1;   // c[lo] <= target holds for lo = f gg
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (g.cdf[mid] <= target) lo = mid;
+                if (c[mid] <= target) lo = mid;
                 else hi = mid - 1;
             }
             factor = P[f] > 0.0 ? Q[f] / P[f] : 0.0;
+            bin = fb[f];
             return lo;
         }
         t -= Q[f];
@@ -156,8 +194,9 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
             float a, b, inv_density = kInvAreaDensity;
             if (g.cdf) {
                 double factor = 0.0;
-                int k = guide_cell(g, x0, x1, x2, n0, n1, n2, u0, factor);
-                const double pa = k >= 0 ? g.prob[k] * factor / g.area : 0.0;
+                int bin = 0;
+                int k = guide_cell(g, x0, x1, x2, n0, n1, n2, u0, bin, factor);
+                const double pa = k >= 0 ? g.prob[(size_t)bin * g.n_cells + k] * factor / g.area : 0.0;
                 inv_density = pa > 0.0 ? (float)(1.0 / pa) : 0.0f;
                 k = k < 0 ? 0 : k;                    // a dead sample: any cell, weight 0
                 const int gg = g.G * g.G;
@@ -247,17 +286,32 @@ __global__ void k_guide_rays(int G, int R, int64_t n, const float *u, float step
     d[3 * j + 2] = t2 - y2;
 }
 
-// Mean luminance (channel mean) of each cell's R probes, summed in FP64 in
-// probe order.
-__global__ void k_guide_reduce(const float *rgb, int R, int n_cells, float *weights) {
+// Guide weights of each cell, D^2 of them (cell-major): the mean luminance
+// (channel mean) of the cell's probes whose outward direction -d falls in
+// the bin, summed in FP64 in probe order; a bin none of them fell in takes
+// the mean over all R probes (D = 1: that mean alone).
+__global__ void k_guide_reduce(const float *rgb, const float *d, int R, int n_cells, int G, int D, float *weights) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
-    double s = 0.0;
+    const int a = (c / (G * G)) >> 1;
+    double tot = 0.0;
     for (int r = 0; r < R; ++r) {
         const float *q = rgb + 3 * ((int64_t)c * R + r);
-        s += ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
+        tot += ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
     }
-    weights[c] = (float)(s / R);
+    for (int b = 0; b < D * D; ++b) {
+        double s = 0.0;
+        int cnt = 0;
+        for (int r = 0; r < R && D > 1; ++r) {
+            const int64_t j = (int64_t)c * R + r;
+            const float *dj = d + 3 * j;
+            if (face_direction_bin(a, -(double)dj[0], -(double)dj[1], -(double)dj[2], D) != b) continue;
+            const float *q = rgb + 3 * j;
+            s += ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
+            ++cnt;
+        }
+        weights[(size_t)c * D * D + b] = (float)(cnt > 0 ? s / cnt : tot / R);
+    }
 }
 
 // The cell probabilities and their running sums, in cell order (FP64):
@@ -273,15 +327,18 @@ constexpr int kCdfChunk = 2048;   // cells staged in LDS at a time
 // count as 0
 __device__ inline double guide_weight(float w) { return w > 0.0f && w < INFINITY ? (double)w : 0.0; }
 
-__global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, int n, double beta, double *prob,
+__global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, int n, int D, double beta, double *prob,
                                                          double *cdf) {
     __shared__ double s_v[kCdfChunk];
     __shared__ double s_W;
     const int t = threadIdx.x;
+    const int nb = D * D, b = blockIdx.x;   // block b builds the table of direction bin b
+    prob += (size_t)b * n;
+    cdf += (size_t)b * (n + 1);
     double W = 0.0;   // thread 0 only
     for (int c0 = 0; c0 < n; c0 += kCdfChunk) {
         const int m = min(kCdfChunk, n - c0);
-        for (int i = t; i < m; i += kCdfBlock) s_v[i] = guide_weight(weights[c0 + i]);
+        for (int i = t; i < m; i += kCdfBlock) s_v[i] = guide_weight(weights[(size_t)(c0 + i) * nb + b]);
         __syncthreads();
         if (t == 0)
             for (int i = 0; i < m; ++i) W += s_v[i];
@@ -297,7 +354,8 @@ __global__ __launch_bounds__(kCdfBlock) void k_guide_cdf(const float *weights, i
     for (int c0 = 0; c0 < n; c0 += kCdfChunk) {
         const int m = min(kCdfChunk, n - c0);
         for (int i = t; i < m; i += kCdfBlock) {
-            const double p = W > 0.0 ? (1.0 - beta) * (guide_weight(weights[c0 + i]) / W) + beta / n : 1.0 / n;
+            const double p =
+                W > 0.0 ? (1.0 - beta) * (guide_weight(weights[(size_t)(c0 + i) * nb + b]) / W) + beta / n : 1.0 / n;
             prob[c0 + i] = p;
             s_v[i] = p;
         }
@@ -392,7 +450,8 @@ namespace lq {
 namespace {
 
 lq_status proxy_common(const lq_octree *tree, const float *points, const float *normals, int64_t n_points,
-                       const float *u, int32_t n_samples, const float *weights, int32_t grid, float defensive,
+                       const float *u, int32_t n_samples, const float *weights, int32_t grid, int32_t dir_res,
+                       float defensive,
                        const float *background_rgb, int model, float *irradiance, float *sample_terms,
                        void *hip_stream) {
     if (!tree) return shade_fail(LQ_ERR_INVALID_ARG, "tree is NULL");
@@ -402,6 +461,7 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
     if (n_points > ((int64_t)1 << 36) / n_samples) return shade_fail(LQ_ERR_INVALID_ARG, "n_points * n_samples too large");
     const bool guided = weights != nullptr;
     if (guided && (grid < 1 || grid > 256)) return shade_fail(LQ_ERR_INVALID_ARG, "grid must be in 1..256");
+    if (guided && (dir_res < 1 || dir_res > 4)) return shade_fail(LQ_ERR_INVALID_ARG, "dir_res must be in 1..4");
     if (guided && !(defensive >= 0.0f && defensive <= 1.0f))
         return shade_fail(LQ_ERR_INVALID_ARG, "defensive must be in [0, 1]");
     if (n_points == 0) return LQ_OK;
@@ -413,6 +473,7 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
     if (e != hipSuccess) return shade_fail(LQ_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
     const int64_t m = n_points * n_samples;
     const int n_cells = guided ? 6 * grid * grid : 0;
+    const int n_bins = guided ? dir_res * dir_res : 0;
     lq_status st;
     if ((st = check_device_array(points, (size_t)n_points * 12, dev, "points")) != LQ_OK) return st;
     if ((st = check_device_array(normals, (size_t)n_points * 12, dev, "normals")) != LQ_OK) return st;
@@ -420,12 +481,14 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
     if ((st = check_device_array(irradiance, (size_t)n_points * 12, dev, "irradiance")) != LQ_OK) return st;
     if (sample_terms && (st = check_device_array(sample_terms, (size_t)m * 12, dev, "sample_terms")) != LQ_OK)
         return st;
-    if (guided && (st = check_device_array(weights, (size_t)n_cells * 4, dev, "weights")) != LQ_OK) return st;
+    if (guided && (st = check_device_array(weights, (size_t)n_cells * n_bins * 4, dev, "weights")) != LQ_OK)
+        return st;
     hipStream_t s = (hipStream_t)hip_stream;
     // stream-ordered scratch: the live-ray counter (256 B), then per sample a
     // list slot (8 B), a ray (24 B), its weight (4 B), its radiance and
-    // opacity (16 B); guided, the cell probabilities and running sums
-    const size_t guide_bytes = guided ? (size_t)(2 * n_cells + 1) * 8 : 0;
+    // opacity (16 B); guided, the cell probabilities and running sums of
+    // every direction bin
+    const size_t guide_bytes = guided ? (size_t)n_bins * (2 * n_cells + 1) * 8 : 0;
     const size_t guide_at = (256 + (size_t)m * 52 + 255) & ~(size_t)255;   // 8-byte (here 256) aligned
     unsigned char *buf = nullptr;
     if ((e = hipMallocAsync((void **)&buf, guide_at + guide_bytes, s)) != hipSuccess)
@@ -438,12 +501,14 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
     if (guided) {
         double *gd = reinterpret_cast<double *>(buf + guide_at);
         g.prob = gd;
-        g.cdf = gd + n_cells;
+        g.cdf = gd + (size_t)n_bins * n_cells;
         g.G = grid;
         g.n_cells = n_cells;
+        g.D = dir_res;
         g.step = (float)(2.0 / grid);
         g.area = (2.0 / grid) * (2.0 / grid);
-        hipLaunchKernelGGL(k_guide_cdf, dim3(1), dim3(kCdfBlock), 0, s, weights, n_cells, (double)defensive,
+        hipLaunchKernelGGL(k_guide_cdf, dim3((unsigned)n_bins), dim3(kCdfBlock), 0, s, weights, n_cells, dir_res,
+                           (double)defensive,
                            const_cast<double *>(g.prob), const_cast<double *>(g.cdf));
     }
     hipLaunchKernelGGL(k_proxy_zero, dim3(1), dim3(1), 0, s, n_live);
@@ -475,24 +540,25 @@ extern "C" lq_status lq_proxy_irradiance(const lq_octree *tree, const float *poi
                                          int64_t n_points, const float *u, int32_t n_samples,
                                          const float *background_rgb, int model, float *irradiance,
                                          float *sample_terms, void *hip_stream) {
-    return proxy_common(tree, points, normals, n_points, u, n_samples, nullptr, 0, 0.0f, background_rgb, model,
+    return proxy_common(tree, points, normals, n_points, u, n_samples, nullptr, 0, 1, 0.0f, background_rgb, model,
                         irradiance, sample_terms, hip_stream);
 }
 
 extern "C" lq_status lq_proxy_irradiance_guided(const lq_octree *tree, const float *points, const float *normals,
                                                 int64_t n_points, const float *u, int32_t n_samples,
-                                                const float *weights, int32_t grid, float defensive,
-                                                const float *background_rgb, int model, float *irradiance,
-                                                float *sample_terms, void *hip_stream) {
+                                                const float *weights, int32_t grid, int32_t dir_res,
+                                                float defensive, const float *background_rgb, int model,
+                                                float *irradiance, float *sample_terms, void *hip_stream) {
     if (!weights) return shade_fail(LQ_ERR_INVALID_ARG, "weights is NULL");
-    return proxy_common(tree, points, normals, n_points, u, n_samples, weights, grid, defensive, background_rgb,
-                        model, irradiance, sample_terms, hip_stream);
+    return proxy_common(tree, points, normals, n_points, u, n_samples, weights, grid, dir_res, defensive,
+                        background_rgb, model, irradiance, sample_terms, hip_stream);
 }
 
-extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t n_probes, const float *u_probe,
-                                    int model, float *weights, void *hip_stream) {
+extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t dir_res, int32_t n_probes,
+                                    const float *u_probe, int model, float *weights, void *hip_stream) {
     if (!tree) return shade_fail(LQ_ERR_INVALID_ARG, "tree is NULL");
     if (grid < 1 || grid > 256) return shade_fail(LQ_ERR_INVALID_ARG, "grid must be in 1..256");
+    if (dir_res < 1 || dir_res > 4) return shade_fail(LQ_ERR_INVALID_ARG, "dir_res must be in 1..4");
     if (n_probes < 1 || n_probes > 65536) return shade_fail(LQ_ERR_INVALID_ARG, "n_probes must be in 1..65536");
     if (model != LQ_LINEAR && model != LQ_EXP) return shade_fail(LQ_ERR_INVALID_ARG, "model must be LQ_LINEAR or LQ_EXP");
     const int dev = octree_device(tree);
@@ -502,7 +568,8 @@ extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t
     const int64_t n = (int64_t)n_cells * n_probes;
     lq_status st;
     if ((st = check_device_array(u_probe, (size_t)n * 20, dev, "u_probe")) != LQ_OK) return st;
-    if ((st = check_device_array(weights, (size_t)n_cells * 4, dev, "weights")) != LQ_OK) return st;
+    if ((st = check_device_array(weights, (size_t)n_cells * dir_res * dir_res * 4, dev, "weights")) != LQ_OK)
+        return st;
     hipStream_t s = (hipStream_t)hip_stream;
     float *buf = nullptr;    // probe rays (24 B) and their radiance (12 B)
     if ((e = hipMallocAsync((void **)&buf, (size_t)n * 36, s)) != hipSuccess)
@@ -516,8 +583,8 @@ extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t
     } else {
         st = query_scratch(tree, o, d, n, nullptr, nullptr, rgb, nullptr, model, s);
         if (st == LQ_OK) {
-            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s, rgb,
-                               n_probes, n_cells, weights);
+            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s, rgb, d,
+                               n_probes, n_cells, grid, dir_res, weights);
             if ((e = hipGetLastError()) != hipSuccess)
                 st = shade_fail(LQ_ERR_HIP, std::string("launching the guide reduction: ") + hipGetErrorString(e));
         }

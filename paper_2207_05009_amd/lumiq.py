@@ -83,8 +83,8 @@ def lib():
             L.lq_octree_from_leaves.argtypes = [i32, i32, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                                 C.c_int, C.c_int, C.POINTER(vp)]
             L.lq_octree_download.argtypes = [vp, vp, vp, vp]
-            L.lq_proxy_guide.argtypes = [vp, i32, i32, vp, C.c_int, vp, vp]
-            L.lq_proxy_irradiance_guided.argtypes = [vp, vp, vp, i64, vp, i32, vp, i32, C.c_float, vp, C.c_int,
+            L.lq_proxy_guide.argtypes = [vp, i32, i32, i32, vp, C.c_int, vp, vp]
+            L.lq_proxy_irradiance_guided.argtypes = [vp, vp, vp, i64, vp, i32, vp, i32, i32, C.c_float, vp, C.c_int,
                                                      vp, vp, vp]
             for name in ("lq_load_octree_desc", "lq_load_octree", "lq_octree_info",
                          "lq_query_radiance", "lq_query_trace", "lq_query_radiance_image",
@@ -223,23 +223,26 @@ class Octree:
                                         MODEL[model], _ptr(irradiance), _ptr(terms), _stream(stream)))
         return irradiance, terms
 
-    def proxy_guide(self, grid: int, u_probe, model: str = "linear", weights=None, stream=None):
-        """Guide weights [6 grid^2] of the proxy's cells from probe rays
-        (u_probe: float32 [6 grid^2, R, 5] CUDA tensor)."""
+    def proxy_guide(self, grid: int, u_probe, model: str = "linear", weights=None, stream=None,
+                    dir_res: int = 1):
+        """Guide weights [6 grid^2 dir_res^2] (cell-major) of the proxy's
+        cells from probe rays (u_probe: float32 [6 grid^2, R, 5] CUDA tensor),
+        one per direction bin."""
         import torch
         n_cells = 6 * grid * grid
         if u_probe.shape[0] != n_cells or u_probe.shape[2] != 5:
             raise ValueError(f"u_probe must be [{n_cells}, R, 5]")
         if weights is None:
-            weights = torch.empty((n_cells,), dtype=torch.float32, device=u_probe.device)
-        check(lib().lq_proxy_guide(self.handle, grid, u_probe.shape[1], _ptr(u_probe), MODEL[model],
+            weights = torch.empty((n_cells * dir_res * dir_res,), dtype=torch.float32, device=u_probe.device)
+        check(lib().lq_proxy_guide(self.handle, grid, dir_res, u_probe.shape[1], _ptr(u_probe), MODEL[model],
                                    _ptr(weights), _stream(stream)))
         return weights
 
     def proxy_irradiance_guided(self, points, normals, u, weights, grid: int, defensive: float = 0.25,
                                 background=None, model: str = "linear", want_terms: bool = False,
-                                irradiance=None, stream=None):
-        """proxy_irradiance with the samples' cells drawn from a guide."""
+                                irradiance=None, stream=None, dir_res: int = 1):
+        """proxy_irradiance with the samples' cells drawn from a guide
+        (weights [6 grid^2 dir_res^2], as proxy_guide writes them)."""
         import torch
         n, S = u.shape[0], u.shape[1]
         if irradiance is None:
@@ -247,7 +250,7 @@ class Octree:
         terms = torch.empty((n, S, 3), dtype=torch.float32, device=points.device) if want_terms else None
         bg = (C.c_float * 3)(*background) if background is not None else None
         check(lib().lq_proxy_irradiance_guided(self.handle, _ptr(points), _ptr(normals), n, _ptr(u), S,
-                                               _ptr(weights), grid, defensive, bg, MODEL[model],
+                                               _ptr(weights), grid, dir_res, defensive, bg, MODEL[model],
                                                _ptr(irradiance), _ptr(terms), _stream(stream)))
         return irradiance, terms
 

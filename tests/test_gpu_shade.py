@@ -189,6 +189,73 @@ def test_guide_weights_parity(lq, c0_tree):
         assert (w > 0).mean() > 0.5
 
 
+def _directional_slack(q, G, R, D, u):
+    """Per (cell, bin) allowance for threshold-ambiguous probes: the gap of
+    their candidates' luminance over the bin's probe count (a bin no probe
+    fell in: the cell's gap over R)."""
+    n = shade.guide_cells(G)
+    _, d = shade.guide_probe_rays(G, u)
+    cell = np.repeat(np.arange(n), R)
+    b = shade.face_direction_bin(cell // (G * G), -d.astype(np.float64), D)
+    gap = np.abs(q["alt_L"].mean(1) - q["L"].mean(1)) * q["alt_valid"]
+    s = np.zeros((n, D * D))
+    c = np.zeros((n, D * D))
+    np.add.at(s, (cell, b), gap)
+    np.add.at(c, (cell, b), 1.0)
+    tot = np.zeros(n)
+    np.add.at(tot, cell, gap)
+    return np.where(c > 0, s / np.where(c > 0, c, 1.0), (tot / R)[:, None]).reshape(-1)
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_directional_guide_weights_parity(lq, c0_tree, D):
+    """Direction-binned guide weights against the oracle's: every probe in
+    the same bin on both sides, then 1e-4 relative per (cell, bin)."""
+    import torch
+    G, R = 6, 48
+    u = inputs.rays.probe_numbers(shade.guide_cells(G), R, 71 + D)
+    oct_ = lq.Octree(c0_tree, "f32")
+    w = oct_.proxy_guide(G, _dev(u), dir_res=D)
+    torch.cuda.synchronize()
+    w = w.cpu().numpy().astype(np.float64)
+    ref, q = shade.guide_weights(c0_tree, G, u, D=D)
+    assert w.shape == ref.shape == (shade.guide_cells(G) * D * D,)
+    err = np.abs(w - ref) - _directional_slack(q, G, R, D, u)
+    tol = 1e-4 * np.maximum(np.abs(ref), 1e-3 * ref.max())
+    _say(f"directional guide D={D}: max |dw| / tol {(err / tol).max():.3f}")
+    assert np.all(err <= tol)
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+@pytest.mark.parametrize("beta", [0.0, 0.25])
+def test_directional_guided_irradiance_parity(lq, c0_tree, D, beta):
+    """The guided estimator with a direction-binned guide against the
+    oracle, sample by sample (bins, cells and weights) and point by point."""
+    import torch
+    G = 8
+    pts, nrm = inputs.rays.scattered_points(300, 33)
+    u = inputs.rays.sample_numbers(300, 48, 34)
+    w = inputs.rays.guide_weights(shade.guide_cells(G) * D * D, 35 + D)
+    B = (0.2, 0.5, 1.0)
+    _say(f"directional guided proxy irradiance, D={D}, beta {beta}")
+    oct_ = lq.Octree(c0_tree, "f32")
+    E, terms = oct_.proxy_irradiance_guided(_dev(pts), _dev(nrm), _dev(u), _dev(w), G, defensive=beta,
+                                            background=B, want_terms=True, dir_res=D)
+    torch.cuda.synchronize()
+    orc = shade.proxy_irradiance_guided(c0_tree, pts, nrm, u, w, G, beta, background=B, D=D)
+    _check(c0_tree, pts, nrm, u, B, "linear", terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64), orc=orc)
+
+
+def test_directional_guide_rejects_bad_resolution(lq, c0_tree):
+    import torch
+    oct_ = lq.Octree(c0_tree, "f32")
+    u = _dev(inputs.rays.probe_numbers(shade.guide_cells(2), 4, 36))
+    for D in (0, 5):
+        with pytest.raises(lq.LumiqError, match="dir_res"):
+            oct_.proxy_guide(2, u, dir_res=D, weights=torch.zeros(24 * 25, device="cuda"))
+
+
 @pytest.mark.parametrize("which", ["c0", "empty", "opaque"])
 @pytest.mark.parametrize("model", ["linear", "exp"])
 @pytest.mark.parametrize("beta", [0.0, 0.25])
@@ -310,5 +377,22 @@ def test_guided_full_size_configuration(lq, c1_tree):
                                             background=B, want_terms=True)
     torch.cuda.synchronize()
     orc = shade.proxy_irradiance_guided(c1_tree, pts, nrm, uu, gw, G, 0.25, background=B)
+    _check(c1_tree, pts, nrm, uu, B, "linear", terms.cpu().numpy().astype(np.float64),
+           E.cpu().numpy().astype(np.float64), orc=orc)
+    # the benchmark's directional guide (2 x 2 bins) at the same size
+    D = 2
+    wd = oct_.proxy_guide(G, _dev(u), dir_res=D)
+    torch.cuda.synchronize()
+    wd = wd.cpu().numpy().astype(np.float64)
+    refd, qd = shade.guide_weights(c1_tree, G, u, D=D)
+    err = np.abs(wd - refd) - _directional_slack(qd, G, R, D, u)
+    tol = 1e-4 * np.maximum(np.abs(refd), 1e-3 * refd.max())
+    _say(f"full-size directional guide: max |dw| / tol {(err / tol).max():.3f}")
+    assert np.all(err <= tol)
+    gwd = inputs.rays.guide_weights(shade.guide_cells(G) * D * D, 95)
+    E, terms = oct_.proxy_irradiance_guided(_dev(pts), _dev(nrm), _dev(uu), _dev(gwd), G, defensive=0.5,
+                                            background=B, want_terms=True, dir_res=D)
+    torch.cuda.synchronize()
+    orc = shade.proxy_irradiance_guided(c1_tree, pts, nrm, uu, gwd, G, 0.5, background=B, D=D)
     _check(c1_tree, pts, nrm, uu, B, "linear", terms.cpu().numpy().astype(np.float64),
            E.cpu().numpy().astype(np.float64), orc=orc)
