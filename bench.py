@@ -319,7 +319,7 @@ def floor_error(tree, smp):
     from oracle import shade
     if "guide" in smp:
         orc = shade.proxy_irradiance_guided(tree, smp["pts"], smp["nrm"], smp["u"], smp["guide"], smp["G"],
-                                            smp["beta"], background=smp["bg"])
+                                            smp["beta"], background=smp["bg"], D=smp["D"])
     else:
         orc = shade.proxy_irradiance(tree, smp["pts"], smp["nrm"], smp["u"], background=smp["bg"])
     g = np.asarray(smp["E"], np.float64)
@@ -494,39 +494,43 @@ def floor_variant(inputs, oct32, steps, samples=None):
 
 
 QUALITY_POINTS, QUALITY_SAMPLES = 4096, 4096
+GUIDE_DIRS = 2   # direction bins per tangent axis of the benchmarked guide (2 x 2 per cell)
 
 
 def guided_variant(inputs, oct32, steps, samples=None):
-    """Radiance-field-guided proxy sampling on the floor grid: the guide
-    (16 x 16 cells per face, 64 probe rays per cell, one lq_proxy_guide
-    call) and the guided irradiance call (1,048,576 points x 16 samples, the
-    floor workload of the uniform variant), timed; then the estimator's
-    quality on 4,096 random points of the floor at 4,096 samples each: the
-    variance of one sample's luminance term (the error of an n-sample
-    estimate is this over n, both estimators being unbiased), mean and
-    median over the points, for the uniform estimator over the whole proxy,
-    for the guided one with defensive share 1 (uniform cells, the face
-    chosen by the geometry mix among the faces the point sees) and with 0.5
-    (the guide's share), and the mean z-score of the guided against the
-    uniform means (near 0 when both estimate the same integral)."""
+    """Radiance-field-guided proxy sampling on the floor grid: the
+    direction-binned guide (16 x 16 cells per face, 2 x 2 direction bins,
+    64 probe rays per cell, one lq_proxy_guide call) and the guided
+    irradiance call (1,048,576 points x 16 samples, the floor workload of
+    the uniform variant), timed; then the estimator's quality on 4,096
+    random points of the floor at 4,096 samples each: the variance of one
+    sample's luminance term (the error of an n-sample estimate is this over
+    n, all estimators being unbiased), mean and median over the points, for
+    the uniform estimator over the whole proxy, for the guided one with
+    defensive share 1 (uniform cells, the face chosen by the geometry mix
+    among the faces the point sees), with the direction-averaged guide and
+    share 0.5, and with the direction-binned guide and share 0.5 (the timed
+    configuration); and the mean z-score of the last against the uniform
+    means (near 0 when both estimate the same integral)."""
     import numpy as np
     import torch
-    G, R, Q = 16, 64, QUALITY_SAMPLES
+    G, R, Q, D = 16, 64, QUALITY_SAMPLES, GUIDE_DIRS
     up = torch.from_numpy(inputs.rays.probe_numbers(6 * G * G, R, 90)).cuda()
-    w = torch.empty((6 * G * G,), device="cuda")
-    ms_guide, _ = time_launches(lambda: oct32.proxy_guide(G, up, weights=w), steps, 1)
+    w = torch.empty((6 * G * G * D * D,), device="cuda")
+    ms_guide, _ = time_launches(lambda: oct32.proxy_guide(G, up, weights=w, dir_res=D), steps, 1)
+    w1 = oct32.proxy_guide(G, up)
     pts, nrm = inputs.rays.floor_points(1024, 1024)
     u = inputs.rays.sample_numbers(len(pts), 16, 5)
     P, N, U = (torch.from_numpy(a).cuda() for a in (pts, nrm, u))
     E = torch.empty((len(pts), 3), device="cuda")
     bg = (0.05, 0.05, 0.08)
     ms, _ = time_launches(lambda: oct32.proxy_irradiance_guided(P, N, U, w, G, defensive=0.5, background=bg,
-                                                                irradiance=E), steps, 2)
+                                                                irradiance=E, dir_res=D), steps, 2)
     if samples is not None:
         idx = np.sort(np.random.default_rng(42).choice(len(pts), SHADE_SAMPLE, replace=False))
         samples["floor_irradiance_guided"] = {"kind": "floor", "idx": idx, "E": E.cpu().numpy()[idx],
                                               "pts": pts[idx], "nrm": nrm[idx], "u": u[idx], "bg": bg,
-                                              "guide": w.cpu().numpy(), "G": G, "beta": 0.5}
+                                              "guide": w.cpu().numpy(), "G": G, "beta": 0.5, "D": D}
     # quality: 4,096 seeded random floor points, 4,096 samples each (the
     # per-point variance of a heavy-tailed term needs many samples; mean and
     # median over the points)
@@ -539,25 +543,30 @@ def guided_variant(inputs, oct32, steps, samples=None):
         return lum.mean(1).cpu().numpy(), lum.var(1).cpu().numpy()
 
     mu, vu = term_stats(oct32.proxy_irradiance(Ps, Ns, Uq, background=bg, want_terms=True)[1])
-    m1, v1 = term_stats(oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=1.0, background=bg,
-                                                      want_terms=True)[1])
+    _, v1 = term_stats(oct32.proxy_irradiance_guided(Ps, Ns, Uq, w1, G, defensive=1.0, background=bg,
+                                                     want_terms=True)[1])
+    _, va = term_stats(oct32.proxy_irradiance_guided(Ps, Ns, Uq, w1, G, defensive=0.5, background=bg,
+                                                     want_terms=True)[1])
     mh, vh = term_stats(oct32.proxy_irradiance_guided(Ps, Ns, Uq, w, G, defensive=0.5, background=bg,
-                                                      want_terms=True)[1])
+                                                      want_terms=True, dir_res=D)[1])
     torch.cuda.synchronize()
     z = (mh - mu) / np.maximum(np.sqrt((vu + vh) / Q), 1e-30)
     stats = lambda v: {"mean": float(v.mean()), "median": float(np.median(v))}
-    rec = {"grid": G, "probes_per_cell": R, "guide_ms": ms_guide, "points": len(pts), "samples_per_point": 16,
-           "ms": ms, "points_per_s": len(pts) / (ms * 1e-3), "defensive": 0.5,
-           "term_variance": {"uniform_whole_proxy": stats(vu), "guided_defensive_1": stats(v1),
-                             "guided_defensive_0.5": stats(vh)},
+    rec = {"grid": G, "direction_bins": f"{D} x {D}", "probes_per_cell": R, "guide_ms": ms_guide,
+           "points": len(pts), "samples_per_point": 16, "ms": ms, "points_per_s": len(pts) / (ms * 1e-3),
+           "defensive": 0.5,
+           "term_variance": {"uniform_whole_proxy": stats(vu), "geometry_only_defensive_1": stats(v1),
+                             "direction_averaged_guide_0.5": stats(va), "directional_guide_0.5": stats(vh)},
            "variance_ratio_uniform_over_guided": float(vu.mean() / vh.mean()) if vh.mean() > 0 else None,
            "median_point_variance_ratio_uniform_over_guided": float(np.median(vu / np.maximum(vh, 1e-300))),
-           "variance_ratio_defensive_1_over_0.5": float(v1.mean() / vh.mean()) if vh.mean() > 0 else None,
+           "variance_ratio_direction_averaged_over_directional": float(va.mean() / vh.mean())
+           if vh.mean() > 0 else None,
            "mean_z_guided_vs_uniform": float(z.mean()),
            "quality_sample": f"{len(sub)} random floor points x {Q} samples"}
     log(f"guided floor irradiance: guide {ms_guide:.3f} ms, call {ms:.3f} ms; term variance (mean / median over "
-        f"points) uniform {vu.mean():.4g} / {np.median(vu):.4g}, guided defensive 1 {v1.mean():.4g} / "
-        f"{np.median(v1):.4g}, guided defensive 0.5 {vh.mean():.4g} / {np.median(vh):.4g}; mean z {z.mean():.3f}")
+        f"points) uniform {vu.mean():.4g} / {np.median(vu):.4g}, geometry only {v1.mean():.4g} / "
+        f"{np.median(v1):.4g}, direction-averaged guide {va.mean():.4g} / {np.median(va):.4g}, "
+        f"directional guide {vh.mean():.4g} / {np.median(vh):.4g}; mean z {z.mean():.3f}")
     return rec
 
 

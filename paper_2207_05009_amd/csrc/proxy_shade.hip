@@ -103,6 +103,7 @@ constexpr double kFaceMix = 0.5;   // share of the face choice weighted by the f
 // is reproducible bit for bit.  Returns the cell (-1 when no face is visible
 // or P_vis = 0), its table in `bin` and Q_f / P_f in `factor`: the
 // sample's area density is prob_bin[k] factor / A_cell.
+template <bool DIR>
 __device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, float n0, float n1, float n2,
                                  float u0, int &bin, double &factor) {
     const int gg = g.G * g.G;
@@ -130,7 +131,7 @@ __device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, f
 #pragma unroll
             for (int b = 0; b < 3; ++b) d[b] = (b == ax ? sg : 0.0) - xd[b];
             // the outward direction x - c_f is -d
-            fb[f] = g.D > 1 ? face_direction_bin(ax, -d[0], -d[1], -d[2], g.D) : 0;
+            if constexpr (DIR) fb[f] = face_direction_bin(ax, -d[0], -d[1], -d[2], g.D);
             const double *c = g.cdf + (size_t)fb[f] * stride;
             P[f] = c[(f + 1) * gg] - c[f * gg];
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -169,6 +170,9 @@ __device__ inline int guide_cell(const Guide &g, float x0, float x1, float x2, f
     return -1;
 }
 
+// DIR: a direction-binned guide (D > 1); the direction-averaged and the
+// uniform samplers are compiled without the bin decisions.
+template <bool DIR>
 __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points, const float *normals, int64_t m,
                                                             int S, const float *u, float *o, float *d, float *w,
                                                             int64_t *live, unsigned long long *n_live,
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_proxy_rays(const float *points,
             if (g.cdf) {
                 double factor = 0.0;
                 int bin = 0;
-                int k = guide_cell(g, x0, x1, x2, n0, n1, n2, u0, bin, factor);
+                int k = guide_cell<DIR>(g, x0, x1, x2, n0, n1, n2, u0, bin, factor);
                 const double pa = k >= 0 ? g.prob[(size_t)bin * g.n_cells + k] * factor / g.area : 0.0;
                 inv_density = pa > 0.0 ? (float)(1.0 / pa) : 0.0f;
                 k = k < 0 ? 0 : k;                    // a dead sample: any cell, weight 0
@@ -512,8 +516,11 @@ lq_status proxy_common(const lq_octree *tree, const float *points, const float *
                            const_cast<double *>(g.prob), const_cast<double *>(g.cdf));
     }
     hipLaunchKernelGGL(k_proxy_zero, dim3(1), dim3(1), 0, s, n_live);
-    hipLaunchKernelGGL(k_proxy_rays, dim3((unsigned)((m + kSamplesPerBlock - 1) / kSamplesPerBlock)),
-                       dim3(kShadeBlock), 0, s, points, normals, m, (int)n_samples, u, o, d, w, live, n_live, g);
+    {
+        auto kern = guided && dir_res > 1 ? k_proxy_rays<true> : k_proxy_rays<false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)((m + kSamplesPerBlock - 1) / kSamplesPerBlock)), dim3(kShadeBlock), 0,
+                           s, points, normals, m, (int)n_samples, u, o, d, w, live, n_live, g);
+    }
     e = hipGetLastError();
     st = LQ_OK;
     if (e != hipSuccess) {
