@@ -290,32 +290,33 @@ __global__ void k_guide_rays(int G, int R, int64_t n, const float *u, float step
     d[3 * j + 2] = t2 - y2;
 }
 
-// Guide weights of each cell, D^2 of them (cell-major): the mean luminance
-// (channel mean) of the cell's probes whose outward direction -d falls in
-// the bin, summed in FP64 in probe order; a bin none of them fell in takes
-// the mean over all R probes (D = 1: that mean alone).
+// Guide weights, D^2 per cell (cell-major), one thread per (cell, bin):
+// the mean luminance (channel mean) of the cell's probes whose outward
+// direction -d falls in the bin, summed in FP64 in probe order; a bin none
+// of them fell in takes the mean over all R probes (D = 1: that mean
+// alone).
 __global__ void k_guide_reduce(const float *rgb, const float *d, int R, int n_cells, int G, int D, float *weights) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = D * D;
+    if (id >= (int64_t)n_cells * nb) return;
+    const int c = (int)(id / nb), b = (int)(id % nb);
     const int a = (c / (G * G)) >> 1;
-    double tot = 0.0;
+    double tot = 0.0, s = 0.0;
+    int cnt = 0;
     for (int r = 0; r < R; ++r) {
-        const float *q = rgb + 3 * ((int64_t)c * R + r);
-        tot += ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
-    }
-    for (int b = 0; b < D * D; ++b) {
-        double s = 0.0;
-        int cnt = 0;
-        for (int r = 0; r < R && D > 1; ++r) {
-            const int64_t j = (int64_t)c * R + r;
+        const int64_t j = (int64_t)c * R + r;
+        const float *q = rgb + 3 * j;
+        const double l = ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
+        tot += l;
+        if (D > 1) {
             const float *dj = d + 3 * j;
-            if (face_direction_bin(a, -(double)dj[0], -(double)dj[1], -(double)dj[2], D) != b) continue;
-            const float *q = rgb + 3 * j;
-            s += ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
-            ++cnt;
+            if (face_direction_bin(a, -(double)dj[0], -(double)dj[1], -(double)dj[2], D) == b) {
+                s += l;
+                ++cnt;
+            }
         }
-        weights[(size_t)c * D * D + b] = (float)(cnt > 0 ? s / cnt : tot / R);
     }
+    weights[id] = (float)(cnt > 0 ? s / cnt : tot / R);
 }
 
 // The cell probabilities and their running sums, in cell order (FP64):
@@ -590,7 +591,8 @@ extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t
     } else {
         st = query_scratch(tree, o, d, n, nullptr, nullptr, rgb, nullptr, model, s);
         if (st == LQ_OK) {
-            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s, rgb, d,
+            const int64_t n_w = (int64_t)n_cells * dir_res * dir_res;
+            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_w + 255) / 256)), dim3(256), 0, s, rgb, d,
                                n_probes, n_cells, grid, dir_res, weights);
             if ((e = hipGetLastError()) != hipSuccess)
                 st = shade_fail(LQ_ERR_HIP, std::string("launching the guide reduction: ") + hipGetErrorString(e));
