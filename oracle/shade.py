@@ -105,9 +105,10 @@ def proxy_irradiance(tree, points, normals, u, background=(0.0, 0.0, 0.0), model
 # the luminaire also passes where it emits nothing).  A shading point x only
 # receives light through the faces it sees from the front (sgn x_axis > 1);
 # the others contribute exactly zero, so a sample of x picks among the cells
-# of those faces only, with probability p_k / P_vis(x) (P_vis the sum of
-# p over them), and a uniform point in the cell.  The estimate is unbiased
-# whenever every cell of a visible face has p_k > 0 (beta > 0 ensures it).
+# of those faces only: a face by its guide mass mixed with the irradiance
+# integrand at its centre (guided_cell), a cell of it in proportion to p_k,
+# and a uniform point in the cell.  The estimate is unbiased whenever every
+# cell of a visible face has p_k > 0 (beta > 0 ensures it).
 # With D > 1 direction bins the guide is directional: each probe also falls
 # in one of D x D bins of its outward direction (the light it measures
 # leaves the cell along -d) on the face's two tangent axes, a cell has one

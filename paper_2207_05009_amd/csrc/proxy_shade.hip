@@ -47,13 +47,10 @@ __global__ void k_proxy_zero(unsigned long long *p) { p[0] = 0ull; }
 constexpr int kCellsPerSide = 4;
 constexpr int kAimCells = 6 * kCellsPerSide * kCellsPerSide;
 // Guided sampling (cdf != null): the sample picks a cell of the faces its
-// point sees from the front (the others contribute nothing): with P_f the
-// probability of face f's cells (cdf[(f + 1) G^2] - cdf[f G^2]) and P_vis
-// their sum over the visible faces, t = u0 P_vis walks the visible faces in
-// order, and in the face where t < P_f (the last visible one takes any
-// remainder) the cell is the largest k of the face with cdf[k] <=
-// cdf[f G^2] + t (FP64, in the order the table was summed); u1, u2 give
-// the point in the cell, and the area density is p_k / (P_vis A_cell).
+// point sees from the front (the others contribute nothing), the face by
+// guide mass mixed with the face-centre geometry and the cell by the face's
+// table (guide_cell below); u1, u2 give the point in the cell, and the
+// weight divides by the cell's area density.
 struct Guide {
     const double *cdf;    // [D^2][n_cells + 1], or null: uniform sampling
     const double *prob;   // [D^2][n_cells]
