@@ -1,6 +1,5 @@
 """GPU surrogate (forward, backward, Adam, training, trust map, fallback)
 against the FP64 oracle, and the multi-luminaire query."""
-import os
 import sys
 
 import numpy as np
