@@ -495,12 +495,13 @@ def floor_variant(inputs, oct32, steps, samples=None):
 
 QUALITY_POINTS, QUALITY_SAMPLES = 4096, 4096
 GUIDE_DIRS = 2   # direction bins per tangent axis of the benchmarked guide (2 x 2 per cell)
+GUIDE_PROBES = 256   # probe rays per cell of the benchmarked guide
 
 
 def guided_variant(inputs, oct32, steps, samples=None):
     """Radiance-field-guided proxy sampling on the floor grid: the
     direction-binned guide (16 x 16 cells per face, 2 x 2 direction bins,
-    64 probe rays per cell, one lq_proxy_guide call) and the guided
+    256 probe rays per cell, one lq_proxy_guide call) and the guided
     irradiance call (1,048,576 points x 16 samples, the floor workload of
     the uniform variant), timed; then the estimator's quality on 4,096
     random points of the floor at 4,096 samples each: the variance of one
@@ -514,7 +515,7 @@ def guided_variant(inputs, oct32, steps, samples=None):
     means (near 0 when both estimate the same integral)."""
     import numpy as np
     import torch
-    G, R, Q, D = 16, 64, QUALITY_SAMPLES, GUIDE_DIRS
+    G, R, Q, D = 16, GUIDE_PROBES, QUALITY_SAMPLES, GUIDE_DIRS
     up = torch.from_numpy(inputs.rays.probe_numbers(6 * G * G, R, 90)).cuda()
     w = torch.empty((6 * G * G * D * D,), device="cuda")
     ms_guide, _ = time_launches(lambda: oct32.proxy_guide(G, up, weights=w, dir_res=D), steps, 1)

@@ -350,12 +350,12 @@ def test_guided_sampling_reduces_variance(lq, c0_tree):
 
 def test_guided_full_size_configuration(lq, c1_tree):
     """The benchmark's guided configuration on the depth-9 luminaire: the
-    guide (16 x 16 cells per face, 64 probes per cell) against the oracle's,
+    guide (16 x 16 cells per face, 256 probes per cell) against the oracle's,
     and the guided sampler on floor points (a seeded sample of the
     1024 x 1024 grid, 16 samples each) sample by sample against the oracle,
     with a synthetic guide of the same size."""
     import torch
-    G, R = 16, 64
+    G, R = 16, 256
     oct_ = lq.Octree(c1_tree, "f32")
     u = inputs.rays.probe_numbers(shade.guide_cells(G), R, 90)
     w = oct_.proxy_guide(G, _dev(u))
