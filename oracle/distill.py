@@ -168,10 +168,19 @@ def morton_encode(x, y, z):
 
 
 # ---------------------------------------------------------------- steps
-def _centre_chunk(args):
-    f, depth, thr, a, b = args
+def centre_decisions(f: Field, depth: int, codes, prune_sigma: float = 0.01):
+    """Step (1) for the given voxels (Morton codes): whether each is kept
+    (centre density >= prune_sigma, or inside a shell), and whether the
+    decision is ambiguous (either decision valid), as centre_occupancy
+    decides them."""
+    codes = np.asarray(codes, dtype=np.uint64)
+    thr = math.log(prune_sigma) - f.log_base
+    kept, near = _centre_decide(f, depth, thr, codes)
+    return kept, near
+
+
+def _centre_decide(f, depth, thr, codes):
     h = 2.0 / (1 << depth)
-    codes = np.arange(a, b, dtype=np.uint64)
     q = morton_decode(codes)
     x = -1.0 + (q + 0.5) * h
     S = log_density_sum(f, x)
@@ -179,6 +188,13 @@ def _centre_chunk(args):
     keep = inside | (S >= thr)
     near = (np.abs(S - thr) <= AMBIGUOUS_REL * max(1.0, abs(thr))) & ~inside
     near |= margin <= AMBIGUOUS_REL * (1.0 + f.shell_half_width)
+    return keep, near
+
+
+def _centre_chunk(args):
+    f, depth, thr, a, b = args
+    codes = np.arange(a, b, dtype=np.uint64)
+    keep, near = _centre_decide(f, depth, thr, codes)
     return codes[keep], codes[near]
 
 

@@ -150,3 +150,38 @@ def test_full_size_distillation(lq):
     gen = inputs.cached_tree(inputs.C1_TREE)
     gcodes = np.sort(inputs.morton3(gen.leaf_cells[:, 0], gen.leaf_cells[:, 1], gen.leaf_cells[:, 2]))
     _say(f"occupancy against the centre-sampled generator tree: {np.setxor1d(gcodes, g_codes).size} voxels differ")
+
+
+def test_depth_10_distillation_sampled(lq):
+    """The paper's finest octree depth, 10 (1024^3 voxels), on the depth-9
+    benchmark field: the centre decisions of 300,000 seeded voxels (200,000
+    uniform over the grid, 100,000 among the GPU's kept voxels) against the
+    oracle, the means of 1,000 kept voxels, and an octree built from the
+    leaves holding every one of them."""
+    import torch
+    p = field_params(inputs.C1_TREE)
+    f = od.field_from_params(p)
+    t0 = time.perf_counter()
+    codes, sig, sh = lq.distill_leaves(p, 10, 0.01, 256, 2023)
+    torch.cuda.synchronize()
+    g_codes = codes.cpu().numpy().view(np.uint32).astype(np.uint64)
+    _say(f"depth-10 distillation: {len(g_codes)} of 2^30 voxels kept in {time.perf_counter() - t0:.2f} s")
+    assert np.all(np.diff(g_codes.astype(np.int64)) > 0)
+    rng = np.random.default_rng(6)
+    sample = np.concatenate([rng.integers(0, 1 << 30, 200_000).astype(np.uint64),
+                             g_codes[rng.choice(len(g_codes), 100_000, replace=False)]])
+    kept, amb = od.centre_decisions(f, 10, sample)
+    pos = np.searchsorted(g_codes, sample)
+    on_gpu = (pos < len(g_codes)) & (g_codes[np.minimum(pos, len(g_codes) - 1)] == sample)
+    wrong = (on_gpu != kept) & ~amb
+    _say(f"centre decisions: {int(kept.sum())} of {len(sample)} sampled voxels kept, "
+         f"{int(amb.sum())} ambiguous, {int(wrong.sum())} differ")
+    assert not wrong.any(), sample[wrong][:10]
+    idx = np.sort(rng.choice(len(g_codes), 1000, replace=False))
+    o_sig, o_sh = od.average_samples(f, 10, g_codes[idx], 256, 2023)
+    _check_means(sig.cpu().numpy()[idx], sh.cpu().numpy()[idx], o_sig, o_sh, "depth 10, 1000 voxels")
+    tree = lq.octree_from_leaves(10, 2, codes, sig, sh, l_max=p["l_max"])
+    info = tree.info()
+    _say(f"depth-10 octree: {info}")
+    assert info["n_leaves"] == len(g_codes) and info["max_depth"] == 10
+    tree.free()
