@@ -227,7 +227,9 @@ class Octree:
                     dir_res: int = 1):
         """Guide weights [6 grid^2 dir_res^2] (cell-major) of the proxy's
         cells from probe rays (u_probe: float32 [6 grid^2, R, 5] CUDA tensor),
-        one per direction bin."""
+        one per direction bin.  dir_res = 1 averages over directions; 2 x 2
+        bins with a few hundred probes per cell gave the lowest estimator
+        variance on the benchmark's floor (finer bins need more probes)."""
         import torch
         n_cells = 6 * grid * grid
         if u_probe.shape[0] != n_cells or u_probe.shape[2] != 5:
