@@ -12,8 +12,8 @@
 //     t_a(P) - t_b(Q) = (P - o_a)/d_a - (Q - o_b)/d_b,
 // decided first from float32 approximations with a rigorous error bound and,
 // inside the bound, exactly: the numerator (P - o_a) d_b - (Q - o_b) d_a is
-// expanded into eight FP64 terms by error-free transformations (FP64 products
-// of float32 operands are exact) and summed as a Shewchuk expansion.  The
+// the sum of four products of float32 values, each an integer below 2^48
+// times a power of two, whose sign 64-bit integer arithmetic decides.  The
 // length of each leaf segment is computed from the same numerator with
 // float32 error-free transformations, so it keeps full relative precision
 // even for a leaf the ray only grazes.
@@ -156,41 +156,91 @@ LQ_HD inline void sh_basis(float x, float y, float z, float *Y) {
 }
 
 // ------------------------------------------------- exact arithmetic
-LQ_HD inline void two_sum(double a, double b, double &s, double &e) {
-    s = a + b;
-    double bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-LQ_HD inline void two_prod(double a, double b, double &p, double &e) {
-    p = a * b;
-    e = fma(a, b, -p);
-}
 LQ_HD inline void two_sum_f(float a, float b, float &s, float &e) {
     s = a + b;
     float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 
-// exact sign of t[0] + ... + t[7] (grow-expansion, Shewchuk 1997)
-LQ_HD inline int exact_sign8(const double (&t)[8]) {
-    double e[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        double q = t[j];
-#pragma unroll
-        for (int i = 0; i < j; ++i) {
-            double s, lo;
-            two_sum(q, e[i], s, lo);
-            e[i] = lo;
-            q = s;
-        }
-        e[j] = q;
+// One product x*y of two finite float32 values as an exact signed term
+// m 2^E: x = (-1)^sx mx 2^ex with an integer mx < 2^24 (normal: hidden bit
+// and ex = biased exponent - 150; subnormal: ex = -149), so m = mx my < 2^48
+// and E = ex + ey.  neg flips the sign.
+struct ExactTerm {
+    int64_t m;   // signed, |m| < 2^48 (0 for a zero product)
+    int E;
+};
+LQ_HD inline ExactTerm exact_product(float x, float y, bool neg) {
+    const uint32_t bx = __builtin_bit_cast(uint32_t, x), by = __builtin_bit_cast(uint32_t, y);
+    const uint32_t exb = (bx >> 23) & 0xffu, eyb = (by >> 23) & 0xffu;
+    const uint64_t mx = (bx & 0x7fffffu) | (exb ? 0x800000u : 0u);
+    const uint64_t my = (by & 0x7fffffu) | (eyb ? 0x800000u : 0u);
+    const int ex = exb ? (int)exb - 150 : -149, ey = eyb ? (int)eyb - 150 : -149;
+    const int64_t m = (int64_t)(mx * my);
+    const bool negative = (((bx ^ by) >> 31) != 0) != neg;
+    return ExactTerm{negative ? -m : m, ex + ey};
+}
+LQ_HD inline void order_terms(ExactTerm &a, ExactTerm &b) {   // larger exponent first
+    if (b.E > a.E) {
+        const ExactTerm t = a;
+        a = b;
+        b = t;
     }
-    int sgn = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        if (e[i] != 0.0) sgn = e[i] > 0.0 ? 1 : -1;   // the last nonzero one dominates
-    return sgn;
+}
+
+// P 2^E += t.m 2^t.E (t.E <= E); done once P's sign is the result's or
+// the terms left are zero
+LQ_HD inline void absorb_term(int64_t &P, int &E, bool &done, const ExactTerm &t) {
+    if (done || t.m == 0) {
+        done = true;
+        return;
+    }
+    if (P == 0) {
+        P = t.m;
+        E = t.E;
+        return;
+    }
+    const int g = E - t.E;                    // >= 0: the terms come in order
+    const int64_t aP = P < 0 ? -P : P;
+    if (g >= 50 || aP >= ((int64_t)1 << (50 - g))) {
+        done = true;
+        return;
+    }
+    P = P * ((int64_t)1 << g) + t.m;
+    E = t.E;
+}
+
+// sign((Pa - oa) db - (Pb - ob) da) for finite float32 operands, exact, in
+// 64-bit integer arithmetic: the expression is the sum of four products
+// Pa db - oa db - Pb da + ob da, each an integer below 2^48 times a power of
+// two.  The terms are added from the largest exponent down into an integer
+// P at the scale of the last term added.  Before a term of exponent E joins,
+// the terms still to come (at most three, each below 2^48 at scale 2^E) sum
+// to less than 2^50 at that scale; when P, shifted to it, reaches 2^50 its
+// sign is the result.  Otherwise the shifted P stays below 2^50 and the sum
+// below 2^51, so nothing overflows.
+LQ_HD inline int exact_cross_sign(float Pa, float oa, float da, float Pb, float ob, float db) {
+    ExactTerm t0 = exact_product(Pa, db, false);
+    ExactTerm t1 = exact_product(oa, db, true);
+    ExactTerm t2 = exact_product(Pb, da, true);
+    ExactTerm t3 = exact_product(ob, da, false);
+    // zero terms carry no exponent: put them last
+    if (t0.m == 0) t0.E = -1000;
+    if (t1.m == 0) t1.E = -1000;
+    if (t2.m == 0) t2.E = -1000;
+    if (t3.m == 0) t3.E = -1000;
+    order_terms(t0, t1);
+    order_terms(t2, t3);
+    order_terms(t0, t2);
+    order_terms(t1, t3);
+    order_terms(t1, t2);
+    int64_t P = t0.m;
+    int E = t0.E;
+    bool done = false;
+    absorb_term(P, E, done, t1);
+    absorb_term(P, E, done, t2);
+    absorb_term(P, E, done, t3);
+    return P > 0 ? 1 : (P < 0 ? -1 : 0);
 }
 
 struct Ray {
@@ -219,19 +269,11 @@ LQ_HD inline float sel3v(const float (&v)[3], int a) {
 
 LQ_HD inline float tapprox(const Ray &r, int a, float P) { return (P - sel3(r.o, a)) * sel3(r.inv, a); }
 
-// sign((Pa - oa)/da - (Pb - ob)/db), exact, for da, db != 0
-static LQ_HD __noinline__ int cross_cmp_exact(float Pa, float oa, float daf, float Pb, float ob, float dbf) {
-    double A1, A0, B1, B0;
-    two_sum((double)Pa, -(double)oa, A1, A0);
-    two_sum((double)Pb, -(double)ob, B1, B0);
-    double da = daf, db = dbf;
-    double t[8];
-    two_prod(A1, db, t[0], t[1]);
-    two_prod(A0, db, t[2], t[3]);
-    two_prod(-B1, da, t[4], t[5]);
-    two_prod(-B0, da, t[6], t[7]);
-    int s = exact_sign8(t);
-    return ((da > 0.0) == (db > 0.0)) ? s : -s;
+// sign((Pa - oa)/da - (Pb - ob)/db), exact, for da, db != 0: the sign of
+// (Pa - oa) db - (Pb - ob) da times that of da db
+static LQ_HD __noinline__ int cross_cmp_exact(float Pa, float oa, float da, float Pb, float ob, float db) {
+    const int s = exact_cross_sign(Pa, oa, da, Pb, ob, db);
+    return ((da > 0.0f) == (db > 0.0f)) ? s : -s;
 }
 
 // sign(t_a(Pa) - t_b(Pb)); ta/tb are tapprox() of the same planes
