@@ -117,7 +117,7 @@ int main(int argc, char **argv) {
     }
     const int storage = atoi(argv[2]);
     const long long n = atoll(argv[4]);
-    if (storage < 0 || storage > 2 || n <= 0) {
+    if (storage < 0 || storage > 2 || n <= 0 || n > (1ll << 30)) {   /* host buffers: 56 B per ray */
         fprintf(stderr, "bad storage or count\n");
         return 1;
     }
