@@ -287,33 +287,50 @@ __global__ void k_guide_rays(int G, int R, int64_t n, const float *u, float step
     d[3 * j + 2] = t2 - y2;
 }
 
-// Guide weights, D^2 per cell (cell-major), one thread per (cell, bin):
-// the mean luminance (channel mean) of the cell's probes whose outward
-// direction -d falls in the bin, summed in FP64 in probe order; a bin none
-// of them fell in takes the mean over all R probes (D = 1: that mean
-// alone).
-__global__ void k_guide_reduce(const float *rgb, const float *d, int R, int n_cells, int G, int D, float *weights) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Guide weights, D^2 per cell (cell-major), one wave per cell: per bin, the
+// mean luminance (channel mean) of the cell's probes whose outward direction
+// -d falls in the bin, summed in FP64 (each lane over its probes in order,
+// then the lanes by a fixed butterfly: deterministic); a bin none of them
+// fell in takes the mean over all R probes (D = 1: that mean alone).
+constexpr int kGuideReduceBlock = 256;
+
+__device__ inline double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ inline double probe_luminance(const float *rgb, int64_t j) {
+    const float *q = rgb + 3 * j;
+    return ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
+}
+
+__global__ __launch_bounds__(kGuideReduceBlock) void k_guide_reduce(const float *rgb, const float *d, int R,
+                                                                    int n_cells, int G, int D, float *weights) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t c = (int64_t)blockIdx.x * (kGuideReduceBlock / 64) + (threadIdx.x >> 6);
+    if (c >= n_cells) return;   // wave-uniform: the shuffles below see whole waves
     const int nb = D * D;
-    if (id >= (int64_t)n_cells * nb) return;
-    const int c = (int)(id / nb), b = (int)(id % nb);
-    const int a = (c / (G * G)) >> 1;
-    double tot = 0.0, s = 0.0;
-    int cnt = 0;
-    for (int r = 0; r < R; ++r) {
-        const int64_t j = (int64_t)c * R + r;
-        const float *q = rgb + 3 * j;
-        const double l = ((double)q[0] + (double)q[1] + (double)q[2]) / 3.0;
-        tot += l;
+    const int a = (int)(c / ((int64_t)G * G)) >> 1;
+    const int64_t j0 = c * R;
+    double tot = 0.0;
+    for (int r = lane; r < R; r += 64) tot += probe_luminance(rgb, j0 + r);
+    tot = wave_sum_f64(tot);
+    for (int b = 0; b < nb; ++b) {
+        double s = 0.0, cnt = 0.0;
         if (D > 1) {
-            const float *dj = d + 3 * j;
-            if (face_direction_bin(a, -(double)dj[0], -(double)dj[1], -(double)dj[2], D) == b) {
-                s += l;
-                ++cnt;
+            for (int r = lane; r < R; r += 64) {
+                const float *dj = d + 3 * (j0 + r);
+                if (face_direction_bin(a, -(double)dj[0], -(double)dj[1], -(double)dj[2], D) == b) {
+                    s += probe_luminance(rgb, j0 + r);
+                    cnt += 1.0;
+                }
             }
         }
+        s = wave_sum_f64(s);
+        cnt = wave_sum_f64(cnt);
+        if (lane == 0) weights[c * nb + b] = (float)(cnt > 0.0 ? s / cnt : tot / R);
     }
-    weights[id] = (float)(cnt > 0 ? s / cnt : tot / R);
 }
 
 // The cell probabilities and their running sums, in cell order (FP64):
@@ -588,9 +605,9 @@ extern "C" lq_status lq_proxy_guide(const lq_octree *tree, int32_t grid, int32_t
     } else {
         st = query_scratch(tree, o, d, n, nullptr, nullptr, rgb, nullptr, model, s);
         if (st == LQ_OK) {
-            const int64_t n_w = (int64_t)n_cells * dir_res * dir_res;
-            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_w + 255) / 256)), dim3(256), 0, s, rgb, d,
-                               n_probes, n_cells, grid, dir_res, weights);
+            constexpr int cells_per_block = kGuideReduceBlock / 64;
+            hipLaunchKernelGGL(k_guide_reduce, dim3((unsigned)((n_cells + cells_per_block - 1) / cells_per_block)),
+                               dim3(kGuideReduceBlock), 0, s, rgb, d, n_probes, n_cells, grid, dir_res, weights);
             if ((e = hipGetLastError()) != hipSuccess)
                 st = shade_fail(LQ_ERR_HIP, std::string("launching the guide reduction: ") + hipGetErrorString(e));
         }
